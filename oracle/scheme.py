@@ -1,0 +1,167 @@
+"""Oracle: DOLINC differentials, far-cell inversion and k-th order reconstruction.
+
+Test infrastructure only (FP64, plain NumPy); the product path never imports it.
+
+Steps, in the paper's order:
+1. Gauss-linear ("central differencing") gradient, Sec. 2.3:
+   grad(phi)_P = V_P^-1 sum_f S_f^(P) (omega_f phi_P + (1 - omega_f) phi_N).
+   Applying it again to each gradient component gives the second-order tensor.
+2. DOLINC differentials of the two face-adjacent cells (Sec. 2.3, definition
+   of the DOLINC differential): phi_n^(m) = 2^m (grad^m phi)_n : d^(x m),
+   with d the centre-to-centre vector of the face being reconstructed.
+3. Far-cell inversion with the two recursions of Sec. 2.3 (eq:diffDLC and the
+   two one-sided forms before it), applied step by step:
+     right:  phi_{n+2}^(m) = g (phi_n^(m) + g^n phi_{n+1}^(m+1)) + (1-g) phi_{n+1}^(m)
+     left:   phi_{n-1}^(m) = g^-1 (phi_{n+1}^(m) - g^n phi_n^(m+1)) + (1-g^-1) phi_n^(m)
+4. Reconstruction on the retrieved template with the coefficients of
+   eq:coeff (Sec. 2.4), evaluated numerically on cell widths g^j.
+The right state comes from the same steps in the mirrored (N -> P) frame:
+cells swap, d -> -d and g -> 1/g.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+SCHEMES = {"FOU": (1, 0), "CD2": (2, 0), "USR3": (3, 1), "CSR4": (4, 1), "USR5": (5, 2), "CSR6": (6, 2)}
+
+
+# ------------------------------------------------------------------ step 1
+def gauss_linear(mesh, geo, phi):
+    """phi [nc, ...] -> gradient [nc, ..., dim] (natural face-order sums)."""
+    P, N = mesh.owner, mesh.neighbour
+    w = geo.omega.reshape((-1,) + (1,) * (phi.ndim - 1))
+    phif = w * phi[P] + (1.0 - w) * phi[N]
+    flat = phif.reshape(mesh.n_faces, -1)
+    out = np.zeros((mesh.n_cells, flat.shape[1], mesh.dim))
+    for a in range(mesh.dim):
+        contrib = flat * geo.S[:, a:a + 1]
+        for k in range(flat.shape[1]):
+            out[:, k, a] = (np.bincount(P, weights=contrib[:, k], minlength=mesh.n_cells) -
+                            np.bincount(N, weights=contrib[:, k], minlength=mesh.n_cells))
+    out /= geo.V[:, None, None]
+    return out.reshape(phi.shape + (mesh.dim,))
+
+
+# ------------------------------------------------------------------ step 4 coefficients
+def shu_coefficients(widths, r):
+    """eq:coeff: reconstruction weights c_rj at the right edge of cell i.
+
+    widths [..., k]: widths of cells i-r .. i-r+k-1.  Returns [..., k].
+    """
+    widths = np.asarray(widths, dtype=np.float64)
+    k = widths.shape[-1]
+    xb = np.concatenate([np.zeros(widths.shape[:-1] + (1,)), np.cumsum(widths, -1)], -1)
+    xface = xb[..., r + 1]
+    c = np.zeros(widths.shape)
+    for j in range(k):
+        tot = np.zeros(widths.shape[:-1])
+        for m in range(j + 1, k + 1):
+            num = np.zeros(widths.shape[:-1])
+            for l in range(k + 1):
+                if l == m:
+                    continue
+                prod = np.ones(widths.shape[:-1])
+                for q in range(k + 1):
+                    if q != m and q != l:
+                        prod = prod * (xface - xb[..., q])
+                num = num + prod
+            den = np.ones(widths.shape[:-1])
+            for l in range(k + 1):
+                if l != m:
+                    den = den * (xb[..., m] - xb[..., l])
+            tot = tot + num / den
+        c[..., j] = tot * widths[..., j]
+    return c
+
+
+def growth_widths(g, k, r):
+    """Widths g^j of template cells j = -r .. k-r-1 under a constant growth rate."""
+    g = np.asarray(g, dtype=np.float64)
+    return np.stack([g ** j for j in range(-r, k - r)], -1)
+
+
+# ------------------------------------------------------------------ step 2
+def differentials(G, d, order):
+    """phi^(m) for m = 0..order of one cell: G = [phi, G1, G2] (cell values)."""
+    out = [G[0]]
+    if order >= 1:
+        out.append(2.0 * np.einsum("f...a,fa->f...", G[1], d))
+    if order >= 2:
+        out.append(4.0 * np.einsum("f...ab,fa,fb->f...", G[2], d, d))
+    return out
+
+
+# ------------------------------------------------------------------ step 3
+def invert(table, g, lo, hi):
+    """Extend {phi_0^(m), phi_1^(m)} to cells lo..hi with the recursions.
+
+    table: dict (n, m) -> values for n in {0, 1}.  Returns the dict extended
+    with every (n, m) the recursions can reach for lo <= n <= hi.
+    """
+    t = dict(table)
+    gb = g.reshape((-1,) + (1,) * (next(iter(t.values())).ndim - 1))
+    mmax = max(m for (_n, m) in t)
+    n = 1
+    while n + 1 <= hi:                    # phi_{n+1} from cells n-1, n
+        for m in range(0, mmax + 1):
+            if (n - 1, m) in t and (n, m + 1) in t and (n, m) in t:
+                t[(n + 1, m)] = gb * (t[(n - 1, m)] + gb ** (n - 1) * t[(n, m + 1)]) + \
+                    (1.0 - gb) * t[(n, m)]
+        n += 1
+    n = 0
+    while n - 1 >= lo:                    # phi_{n-1} from cells n, n+1
+        for m in range(0, mmax + 1):
+            if (n + 1, m) in t and (n, m + 1) in t and (n, m) in t:
+                t[(n - 1, m)] = (t[(n + 1, m)] - gb ** n * t[(n, m + 1)]) / gb + \
+                    (1.0 - 1.0 / gb) * t[(n, m)]
+        n -= 1
+    return t
+
+
+def one_side(G0, G1c, d, g, scheme):
+    """Face value at the right edge of cell 0 from cells 0 (upwind) and 1.
+
+    G0, G1c: lists [phi, grad, grad2] of cells 0 and 1 gathered per face.
+    """
+    k, r = SCHEMES[scheme]
+    order = 0 if k <= 2 else (1 if k <= 4 else 2)
+    D0 = differentials(G0, d, order)
+    D1 = differentials(G1c, d, order)
+    table = {}
+    for m in range(order + 1):
+        table[(0, m)] = D0[m]
+        table[(1, m)] = D1[m]
+    t = invert(table, g, -r, k - r - 1)
+    c = shu_coefficients(growth_widths(g, k, r), r)
+    out = np.zeros_like(G0[0])
+    cb = c.reshape(c.shape[:1] + (1,) * (G0[0].ndim - 1) + c.shape[1:])
+    for j in range(k):
+        out = out + cb[..., j] * t[(j - r, 0)]
+    return out
+
+
+def cell_derivs(mesh, geo, U, order):
+    G = [U]
+    if order >= 1:
+        G.append(gauss_linear(mesh, geo, U))
+    if order >= 2:
+        G.append(gauss_linear(mesh, geo, G[1]))
+    return G
+
+
+def scheme_order(scheme):
+    k, _r = SCHEMES[scheme]
+    return 0 if k <= 2 else (1 if k <= 4 else 2)
+
+
+def face_states(mesh, geo, U, scheme, G=None):
+    """High-order (U_L, U_R) on every face: L from the owner side, R mirrored."""
+    order = scheme_order(scheme)
+    if G is None:
+        G = cell_derivs(mesh, geo, U, order)
+    P, N = mesh.owner, mesh.neighbour
+    GP = [x[P] for x in G]
+    GN = [x[N] for x in G]
+    UL = one_side(GP, GN, geo.d, geo.g, scheme)
+    UR = one_side(GN, GP, -geo.d, 1.0 / geo.g, scheme)
+    return UL, UR, G
