@@ -1,0 +1,176 @@
+/*
+ * dolinc.h -- C ABI of the MI355X (gfx950) DOLINC explicit-residual library.
+ *
+ * The library evaluates the semi-discrete finite-volume residual of a
+ * hyperbolic conservation law on a face-addressed unstructured mesh with the
+ * DOLINC high-order reconstruction of arXiv 2404.08952, and advances cell
+ * averages with the third-order TVD (SSP) Runge-Kutta method (Sec. 3).
+ *
+ * Every compute step runs in HIP kernels on the device.  Plain pointers and
+ * sizes only; no C++ types cross this boundary and no function throws.
+ *
+ * Conventions
+ *   - "host" pointers are read during the call only; "device" pointers must
+ *     stay valid until the work enqueued on the given stream has finished.
+ *   - Cell arrays on the device use the library's INTERNAL cell order (the
+ *     mesh is renumbered for locality at creation); dolinc_permutation()
+ *     returns the map.  Face arrays exported by the library use the caller's
+ *     face order.
+ *   - Layout of a state U is [n_cells][n_v] (row-major), n_v = 1 for
+ *     advection / Burgers and dim + 2 for Euler (rho, rho*u.., rho*E).
+ *   - The element type of U, R and the exported gradients is double for
+ *     DOLINC_FP64 and float for DOLINC_FP32_MIXED.
+ *   - Return values: DOLINC_OK or an error code; dolinc_last_error() gives a
+ *     thread-local message.  Arguments are validated before anything is
+ *     enqueued; on error nothing is enqueued.
+ *   - One context may be used by one host thread / one stream at a time.
+ *     Calls on one context that overlap on different streams race.
+ */
+#ifndef DOLINC_H
+#define DOLINC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dolinc_ctx_s* dolinc_ctx;
+typedef void* dolinc_stream; /* a hipStream_t; NULL = the null stream */
+
+typedef enum {
+  DOLINC_OK = 0,
+  DOLINC_EINVAL = 1,       /* bad argument                                   */
+  DOLINC_EMESH = 2,        /* malformed mesh (unpaired face, V <= 0, ...)    */
+  DOLINC_ENOMEM = 3,       /* device or host allocation failed               */
+  DOLINC_EHIP = 4,         /* a HIP runtime call failed (no device, ...)     */
+  DOLINC_ESTATE = 5,       /* call out of order (e.g. residual before precompute) */
+  DOLINC_EUNSUPPORTED = 6  /* valid but not built combination                */
+} dolinc_status;
+
+typedef enum { DOLINC_ADVECTION = 0, DOLINC_BURGERS = 1, DOLINC_EULER = 2 } dolinc_pde;
+
+/* k-th order reconstructions of Sec. 2.4 (k cells, r of them upwind of the
+ * face): FOU k=1, CD2 k=2, USR3 k=3 r=1, CSR4 k=4 r=1 (first-order DOLINC
+ * schemes, inversion eq:lCoeffDLC1 / eq:rCoeffDLC1), USR5 k=5 r=2 (second
+ * order DOLINC scheme, inversion eq:lCoeffDLC2). */
+typedef enum {
+  DOLINC_FOU = 1, DOLINC_CD2 = 2, DOLINC_USR3 = 3, DOLINC_CSR4 = 4, DOLINC_USR5 = 5
+} dolinc_scheme;
+
+/* UPWIND: advection upwind flux (Sec. 3.2) and the Godunov flux of Burgers
+ * (Sec. 3.3); RUSANOV: local Lax-Friedrichs (Sec. 3.4); HLLC (Toro). */
+typedef enum { DOLINC_FLUX_UPWIND = 0, DOLINC_FLUX_RUSANOV = 1, DOLINC_FLUX_HLLC = 2 } dolinc_flux;
+
+/* FP64: all arithmetic in double.  FP32_MIXED: geometry and inversion /
+ * reconstruction coefficients computed in double, stored rounded to float;
+ * gradient, reconstruction, flux and update in float with compensated
+ * (Neumaier) face-to-cell sums. */
+typedef enum { DOLINC_FP64 = 0, DOLINC_FP32_MIXED = 1 } dolinc_precision;
+
+/* Blend of the high-order face state with a Van Leer limited second-order
+ * state: U = theta_f U_high + (1 - theta_f) U_limited, theta_f = min of the
+ * two cells' theta.  THETA takes theta per cell from dolinc_set_theta();
+ * CLASSICAL computes it from the DOLINC divided-difference sensor. */
+typedef enum { DOLINC_BLEND_NONE = 0, DOLINC_BLEND_THETA = 1, DOLINC_BLEND_CLASSICAL = 2 } dolinc_blend;
+
+typedef struct {
+  int32_t dim;                   /* 2 or 3                                          */
+  int64_t n_nodes, n_cells, n_faces;
+  const double* node_xyz;        /* host [n_nodes][dim]                              */
+  const int64_t* face_node_ptr;  /* host [n_faces + 1], CSR into face_nodes          */
+  const int32_t* face_nodes;     /* host; owner frame; right-hand normal owner->neigh */
+  const int32_t* owner;          /* host [n_faces]                                   */
+  const int32_t* neighbour;      /* host [n_faces]; every face has two cells         */
+  const double* neigh_shift;     /* host [n_faces][dim]: moves the neighbour's       */
+                                 /* geometry into the owner's frame (periodic)       */
+  int32_t renumber;              /* 0 keep, 1 reverse Cuthill-McKee, 2 Hilbert curve */
+  int32_t part_cells;            /* cells per partition (0 = default 256; <= 1024)   */
+} dolinc_mesh_desc;
+
+typedef struct {
+  int32_t pde;                   /* dolinc_pde        */
+  int32_t scheme;                /* dolinc_scheme     */
+  int32_t flux;                  /* dolinc_flux       */
+  int32_t precision;             /* dolinc_precision  */
+  int32_t blend;                 /* dolinc_blend      */
+  int32_t use_u_ref;             /* FP32: subtract the flux of u_ref on every face    */
+  double gamma;                  /* Euler ratio of specific heats                     */
+  double adv_vel[3];             /* advection velocity                                */
+  double burgers_dir[3];         /* Burgers flux u^2/2 * burgers_dir                   */
+  double u_ref[5];               /* reference state for the FP32 perturbation flux     */
+} dolinc_params;
+
+typedef struct {                 /* host-side partition statistics                    */
+  int64_t n_parts, n_entries, max_entries, max_cell_faces, n_slots;
+} dolinc_mesh_stats;
+
+/* Validate the mesh, renumber cells, build partitions and face entries and
+ * upload them (hipMalloc + synchronous copies on the null stream).  Defines
+ * the problem of Sec. 2.1-2.2: cell averages on a face-addressed mesh, every
+ * face shared by two cells, periodic faces carrying a translation (Sec. 2.6).
+ * EMESH for unpaired / self faces, out-of-range indices or non-closed cells. */
+dolinc_status dolinc_create(const dolinc_mesh_desc* mesh, dolinc_ctx* out);
+
+/* The host part of dolinc_create only (validation, renumbering, partitions);
+ * touches no device.  new_of_old (host [n_cells]) and stats may be NULL. */
+dolinc_status dolinc_mesh_prepare(const dolinc_mesh_desc* mesh, int32_t* new_of_old,
+                                  dolinc_mesh_stats* stats);
+
+/* new_of_old: host [n_cells]; internal index of each caller cell. */
+dolinc_status dolinc_permutation(dolinc_ctx ctx, int32_t* new_of_old);
+dolinc_status dolinc_stats(dolinc_ctx ctx, dolinc_mesh_stats* stats);
+
+/* FP64 precompute on the device (Sec. 2.2 growth rate g and weight omega,
+ * centre distance d; Sec. 2.3-2.4 inversion and reconstruction coefficients
+ * folded into the DOLINC representation eq:USR3 / eq:CSR4), then allocates
+ * the gradient and Runge-Kutta workspaces.  Synchronises before returning.
+ * May be called again to change params (re-allocates as needed). */
+dolinc_status dolinc_precompute(dolinc_ctx ctx, const dolinc_params* params, dolinc_stream s);
+
+/* R = dU/dt = -V^-1 sum_f sigma F_f (device [n_cells][n_v] each, U != R). */
+dolinc_status dolinc_residual(dolinc_ctx ctx, const void* U, void* R, dolinc_stream s);
+
+/* One SSP-RK3 step in place on U (device [n_cells][n_v]) with time step dt. */
+dolinc_status dolinc_rk_step(dolinc_ctx ctx, void* U, double dt, dolinc_stream s);
+
+/* n_steps SSP-RK3 steps (same as calling dolinc_rk_step n_steps times). */
+dolinc_status dolinc_advance(dolinc_ctx ctx, void* U, double dt, int64_t n_steps, dolinc_stream s);
+
+/* Per-cell blend weights for DOLINC_BLEND_THETA: device float [n_cells]
+ * (internal order), copied into the context on stream s. */
+dolinc_status dolinc_set_theta(dolinc_ctx ctx, const float* theta, dolinc_stream s);
+
+/* Classical sensor weight theta per cell (device float [n_cells]) for state U. */
+dolinc_status dolinc_classical_theta(dolinc_ctx ctx, const void* U, float* theta, dolinc_stream s);
+
+/* Gauss-linear gradient (Sec. 2.3) of U: G1 device [n_cells][n_v][dim];
+ * G2 (may be NULL) the symmetrised gradient of G1, [n_cells][n_v][dim*(dim+1)/2]
+ * ordered xx,yy,(zz),xy,(xz,yz).  Element type as U. */
+dolinc_status dolinc_gradients(dolinc_ctx ctx, const void* U, void* G1, void* G2, dolinc_stream s);
+
+/* Reconstructed face states (after blend and positivity fallback) per face
+ * in the caller's face order: UL, UR device [n_faces][n_v]; F (may be NULL)
+ * the face-integrated numerical flux [n_faces][n_v]. */
+dolinc_status dolinc_face_states(dolinc_ctx ctx, const void* U, void* UL, void* UR, void* F,
+                                 dolinc_stream s);
+
+/* FP64 geometry after precompute: V, xc device double [n_cells], [n_cells][dim]
+ * (internal order); S, xf [n_faces][dim], omega, g [n_faces] (caller order).
+ * Any pointer may be NULL. */
+dolinc_status dolinc_geometry(dolinc_ctx ctx, double* V, double* xc, double* S, double* xf,
+                              double* omega, double* g, dolinc_stream s);
+
+/* Diagnostics of U into host double out[n_v + 3]: conserved totals
+ * sum_c V_c U_c (FP64 sums) for every variable, then min rho (or min u),
+ * min p (Euler; else max u) and the count of non-finite entries.  Blocks on s. */
+dolinc_status dolinc_diagnostics(dolinc_ctx ctx, const void* U, double* out, dolinc_stream s);
+
+void dolinc_destroy(dolinc_ctx ctx);
+const char* dolinc_last_error(void);
+int32_t dolinc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DOLINC_H */

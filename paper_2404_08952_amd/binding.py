@@ -1,0 +1,282 @@
+"""ctypes binding of ``libdolinc.so`` (argument marshalling only).
+
+Every compute step runs in the library's HIP kernels; PyTorch supplies device
+memory and the stream.  There is no CPU fallback: if the library is missing
+or no GPU is present, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdolinc.so")
+
+OK, EINVAL, EMESH, ENOMEM, EHIP, ESTATE, EUNSUPPORTED = range(7)
+PDE = {"advection": 0, "burgers": 1, "euler": 2}
+SCHEME = {"FOU": 1, "CD2": 2, "USR3": 3, "CSR4": 4, "USR5": 5}
+FLUX = {"upwind": 0, "rusanov": 1, "hllc": 2}
+PRECISION = {"fp64": 0, "fp32": 1}
+BLEND = {"none": 0, "theta": 1, "classical": 2}
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n_nodes", C.c_int64), ("n_cells", C.c_int64), ("n_faces", C.c_int64),
+                ("node_xyz", C.c_void_p), ("face_node_ptr", C.c_void_p), ("face_nodes", C.c_void_p),
+                ("owner", C.c_void_p), ("neighbour", C.c_void_p), ("neigh_shift", C.c_void_p),
+                ("renumber", C.c_int32), ("part_cells", C.c_int32)]
+
+
+class Params(C.Structure):
+    _fields_ = [("pde", C.c_int32), ("scheme", C.c_int32), ("flux", C.c_int32), ("precision", C.c_int32),
+                ("blend", C.c_int32), ("use_u_ref", C.c_int32), ("gamma", C.c_double),
+                ("adv_vel", C.c_double * 3), ("burgers_dir", C.c_double * 3), ("u_ref", C.c_double * 5)]
+
+
+class MeshStats(C.Structure):
+    _fields_ = [("n_parts", C.c_int64), ("n_entries", C.c_int64), ("max_entries", C.c_int64),
+                ("max_cell_faces", C.c_int64), ("n_slots", C.c_int64)]
+
+
+class DolincError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"dolinc status {status}: {msg}")
+        self.status = status
+
+
+_LIB = None
+
+SIGNATURES = {
+    "dolinc_create": [C.POINTER(MeshDesc), C.POINTER(C.c_void_p)],
+    "dolinc_mesh_prepare": [C.POINTER(MeshDesc), C.c_void_p, C.POINTER(MeshStats)],
+    "dolinc_permutation": [C.c_void_p, C.c_void_p],
+    "dolinc_stats": [C.c_void_p, C.POINTER(MeshStats)],
+    "dolinc_precompute": [C.c_void_p, C.POINTER(Params), C.c_void_p],
+    "dolinc_residual": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+    "dolinc_rk_step": [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p],
+    "dolinc_advance": [C.c_void_p, C.c_void_p, C.c_double, C.c_int64, C.c_void_p],
+    "dolinc_set_theta": [C.c_void_p, C.c_void_p, C.c_void_p],
+    "dolinc_classical_theta": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+    "dolinc_gradients": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+    "dolinc_face_states": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+    "dolinc_geometry": [C.c_void_p] + [C.c_void_p] * 6 + [C.c_void_p],
+    "dolinc_diagnostics": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+    "dolinc_destroy": [C.c_void_p],
+    "dolinc_last_error": [],
+    "dolinc_version": [],
+}
+
+
+def load(path=LIB_PATH):
+    """Load the HIP library (raises if it has not been built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"{path} not found: build it with paper_2404_08952_amd/build.py")
+    lib = C.CDLL(path)
+    for name, args in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = C.c_int32
+    lib.dolinc_destroy.restype = None
+    lib.dolinc_last_error.restype = C.c_char_p
+    _LIB = lib
+    return lib
+
+
+def _check(lib, st):
+    if st != OK:
+        raise DolincError(st, lib.dolinc_last_error().decode())
+
+
+def mesh_desc(mesh, renumber=2, part_cells=0):
+    """Fill a MeshDesc from a synth.mesh.Mesh; returns (desc, keepalive)."""
+    keep = dict(nodes=np.ascontiguousarray(mesh.nodes, dtype=np.float64),
+                fptr=np.ascontiguousarray(mesh.face_ptr, dtype=np.int64),
+                fn=np.ascontiguousarray(mesh.face_nodes, dtype=np.int32),
+                own=np.ascontiguousarray(mesh.owner, dtype=np.int32),
+                nei=np.ascontiguousarray(mesh.neighbour, dtype=np.int32),
+                sh=np.ascontiguousarray(mesh.shift, dtype=np.float64))
+    d = MeshDesc(mesh.dim, mesh.n_nodes, mesh.n_cells, mesh.n_faces,
+                 keep["nodes"].ctypes.data, keep["fptr"].ctypes.data, keep["fn"].ctypes.data,
+                 keep["own"].ctypes.data, keep["nei"].ctypes.data, keep["sh"].ctypes.data,
+                 renumber, part_cells)
+    return d, keep
+
+
+def mesh_prepare(mesh, renumber=2, part_cells=0):
+    """Host-only preparation (no device): (new_of_old, stats dict)."""
+    lib = load()
+    d, _keep = mesh_desc(mesh, renumber, part_cells)
+    perm = np.empty(mesh.n_cells, dtype=np.int32)
+    st = MeshStats()
+    _check(lib, lib.dolinc_mesh_prepare(C.byref(d), perm.ctypes.data, C.byref(st)))
+    return perm, {k: getattr(st, k) for k, _ in MeshStats._fields_}
+
+
+def make_params(pde, scheme, flux="upwind", precision="fp64", blend="none", gamma=1.4,
+                adv_vel=(1.0, 0.5, 0.0), burgers_dir=(1.0, 1.0, 0.0), u_ref=None):
+    p = Params()
+    p.pde = PDE[pde]
+    p.scheme = SCHEME[scheme]
+    p.flux = FLUX[flux]
+    p.precision = PRECISION[precision]
+    p.blend = BLEND[blend]
+    p.gamma = gamma
+    for k in range(3):
+        p.adv_vel[k] = adv_vel[k] if k < len(adv_vel) else 0.0
+        p.burgers_dir[k] = burgers_dir[k] if k < len(burgers_dir) else 0.0
+    p.use_u_ref = 0 if u_ref is None else 1
+    if u_ref is not None:
+        for k in range(5):
+            p.u_ref[k] = u_ref[k]
+    return p
+
+
+class Solver:
+    """A mesh uploaded to the GPU plus one set of scheme parameters.
+
+    Device tensors passed in and out are in the library's internal cell order
+    (``perm[old] = new``); use ``to_internal`` / ``to_external``.
+    """
+
+    def __init__(self, mesh, pde, scheme, flux="upwind", precision="fp64", blend="none", gamma=1.4,
+                 adv_vel=(1.0, 0.5, 0.0), burgers_dir=(1.0, 1.0, 0.0), u_ref=None, renumber=2,
+                 part_cells=0, device="cuda:0"):
+        import torch
+        self.torch = torch
+        self.lib = load()
+        self.device = torch.device(device)
+        torch.cuda.set_device(self.device)
+        d, keep = mesh_desc(mesh, renumber, part_cells)
+        h = C.c_void_p()
+        _check(self.lib, self.lib.dolinc_create(C.byref(d), C.byref(h)))
+        self.h = h
+        del keep
+        self.dim = mesh.dim
+        self.n_cells = mesh.n_cells
+        self.n_faces = mesh.n_faces
+        self.perm = np.empty(mesh.n_cells, dtype=np.int32)
+        _check(self.lib, self.lib.dolinc_permutation(self.h, self.perm.ctypes.data))
+        self.inv = np.empty_like(self.perm)
+        self.inv[self.perm] = np.arange(mesh.n_cells, dtype=np.int32)
+        self.configure(pde, scheme, flux, precision, blend, gamma, adv_vel, burgers_dir, u_ref)
+
+    def configure(self, pde, scheme, flux="upwind", precision="fp64", blend="none", gamma=1.4,
+                  adv_vel=(1.0, 0.5, 0.0), burgers_dir=(1.0, 1.0, 0.0), u_ref=None):
+        p = make_params(pde, scheme, flux, precision, blend, gamma, adv_vel, burgers_dir, u_ref)
+        self.pde, self.scheme, self.precision = pde, scheme, precision
+        self.nv = self.dim + 2 if pde == "euler" else 1
+        self.dtype = self.torch.float64 if precision == "fp64" else self.torch.float32
+        _check(self.lib, self.lib.dolinc_precompute(self.h, C.byref(p), self._stream()))
+
+    # -- helpers
+    def _stream(self):
+        return C.c_void_p(self.torch.cuda.current_stream(self.device).cuda_stream)
+
+    def _ptr(self, t, shape=None, dtype=None):
+        if t is None:
+            return None
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError("expected a contiguous device tensor")
+        if dtype is not None and t.dtype != dtype:
+            raise TypeError(f"expected {dtype}, got {t.dtype}")
+        if shape is not None and tuple(t.shape) != tuple(shape):
+            raise ValueError(f"expected shape {shape}, got {tuple(t.shape)}")
+        return C.c_void_p(t.data_ptr())
+
+    def empty_state(self):
+        return self.torch.empty((self.n_cells, self.nv), dtype=self.dtype, device=self.device)
+
+    def to_internal(self, U):
+        """Host array in caller order -> device tensor in internal order."""
+        U = np.asarray(U).reshape(self.n_cells, -1)
+        out = np.empty_like(U)
+        out[self.perm] = U
+        return self.torch.from_numpy(np.ascontiguousarray(out)).to(self.device, self.dtype)
+
+    def to_external(self, U):
+        """Device tensor in internal order -> host float64 array in caller order."""
+        a = U.detach().to("cpu", self.torch.float64).numpy()
+        return a[self.perm]
+
+    # -- calls
+    def residual(self, U, R=None):
+        R = self.empty_state() if R is None else R
+        _check(self.lib, self.lib.dolinc_residual(self.h, self._ptr(U, (self.n_cells, self.nv), self.dtype),
+                                                  self._ptr(R, (self.n_cells, self.nv), self.dtype),
+                                                  self._stream()))
+        return R
+
+    def rk_step(self, U, dt):
+        _check(self.lib, self.lib.dolinc_rk_step(self.h, self._ptr(U, (self.n_cells, self.nv), self.dtype),
+                                                 float(dt), self._stream()))
+        return U
+
+    def advance(self, U, dt, n):
+        _check(self.lib, self.lib.dolinc_advance(self.h, self._ptr(U, (self.n_cells, self.nv), self.dtype),
+                                                 float(dt), int(n), self._stream()))
+        return U
+
+    def gradients(self, U, second=False):
+        t = self.torch
+        G1 = t.empty((self.n_cells, self.nv, self.dim), dtype=self.dtype, device=self.device)
+        G2 = t.empty((self.n_cells, self.nv, self.dim * (self.dim + 1) // 2), dtype=self.dtype,
+                     device=self.device) if second else None
+        _check(self.lib, self.lib.dolinc_gradients(self.h, self._ptr(U), self._ptr(G1), self._ptr(G2),
+                                                   self._stream()))
+        return (G1, G2) if second else G1
+
+    def face_states(self, U):
+        t = self.torch
+        mk = lambda: t.empty((self.n_faces, self.nv), dtype=self.dtype, device=self.device)  # noqa: E731
+        UL, UR, F = mk(), mk(), mk()
+        _check(self.lib, self.lib.dolinc_face_states(self.h, self._ptr(U), self._ptr(UL), self._ptr(UR),
+                                                     self._ptr(F), self._stream()))
+        return UL, UR, F
+
+    def set_theta(self, theta):
+        _check(self.lib, self.lib.dolinc_set_theta(self.h, self._ptr(theta, (self.n_cells,),
+                                                                     self.torch.float32), self._stream()))
+
+    def classical_theta(self, U):
+        th = self.torch.empty(self.n_cells, dtype=self.torch.float32, device=self.device)
+        _check(self.lib, self.lib.dolinc_classical_theta(self.h, self._ptr(U), self._ptr(th), self._stream()))
+        return th
+
+    def geometry(self):
+        t = self.torch
+        f64 = dict(dtype=t.float64, device=self.device)
+        V = t.empty(self.n_cells, **f64)
+        xc = t.empty((self.n_cells, self.dim), **f64)
+        S = t.empty((self.n_faces, self.dim), **f64)
+        xf = t.empty((self.n_faces, self.dim), **f64)
+        om = t.empty(self.n_faces, **f64)
+        g = t.empty(self.n_faces, **f64)
+        _check(self.lib, self.lib.dolinc_geometry(self.h, *[self._ptr(x) for x in (V, xc, S, xf, om, g)],
+                                                  self._stream()))
+        return dict(V=V, xc=xc, S=S, xf=xf, omega=om, g=g)
+
+    def diagnostics(self, U):
+        out = np.empty(self.nv + 3, dtype=np.float64)
+        _check(self.lib, self.lib.dolinc_diagnostics(self.h, self._ptr(U), out.ctypes.data, self._stream()))
+        return out
+
+    def stats(self):
+        st = MeshStats()
+        _check(self.lib, self.lib.dolinc_stats(self.h, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in MeshStats._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.dolinc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

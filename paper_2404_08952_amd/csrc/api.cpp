@@ -1,0 +1,480 @@
+// C ABI of the DOLINC residual library (declarations and contracts in
+// include/dolinc.h).  Host orchestration only: every compute step is a HIP
+// kernel enqueued on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace dolinc {
+hipError_t flux_f64(dolinc_ctx_s*, const void*, const void*, void*, int, double, double, double, hipStream_t);
+hipError_t flux_f32(dolinc_ctx_s*, const void*, const void*, void*, int, double, double, double, hipStream_t);
+hipError_t export_f64(dolinc_ctx_s*, const void*, void*, void*, void*, hipStream_t);
+hipError_t export_f32(dolinc_ctx_s*, const void*, void*, void*, void*, hipStream_t);
+hipError_t grad_f64(dolinc_ctx_s*, const void*, void*, void*, hipStream_t);
+hipError_t grad_f32(dolinc_ctx_s*, const void*, void*, void*, hipStream_t);
+hipError_t theta_f64(dolinc_ctx_s*, const void*, const void*, float*, hipStream_t);
+hipError_t theta_f32(dolinc_ctx_s*, const void*, const void*, float*, hipStream_t);
+hipError_t diag_f64(dolinc_ctx_s*, const void*, double*, int, hipStream_t);
+hipError_t diag_f32(dolinc_ctx_s*, const void*, double*, int, hipStream_t);
+}  // namespace dolinc
+
+using namespace dolinc;
+
+namespace {
+
+thread_local std::string g_err;
+constexpr int KTPB_HOST = 256;
+
+// Live contexts, so that a destroyed or foreign handle is reported instead
+// of dereferenced.
+std::mutex g_live_mu;
+std::set<const void*> g_live;
+
+dolinc_status fail(dolinc_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIPCHK(expr)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) return fail(DOLINC_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+bool valid_ctx(dolinc_ctx c) {
+  if (!c) return false;
+  std::lock_guard<std::mutex> lk(g_live_mu);
+  return g_live.count((const void*)c) != 0;
+}
+
+template <class X>
+hipError_t upload(X** dst, const X* src, size_t n) {
+  hipError_t e = hipMalloc((void**)dst, n * sizeof(X) + (n == 0 ? sizeof(X) : 0));
+  if (e != hipSuccess) return e;
+  if (n) e = hipMemcpy(*dst, src, n * sizeof(X), hipMemcpyHostToDevice);
+  return e;
+}
+
+void dfree(void*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+template <class X>
+void dfree_t(X*& p) {
+  void* q = (void*)p;
+  dfree(q);
+  p = nullptr;
+}
+
+void free_work(dolinc_ctx c) {
+  Work& w = c->w;
+  dfree(w.sw); dfree(w.dc); dfree(w.rV); dfree(w.G1); dfree(w.G2); dfree(w.W1); dfree(w.W2);
+  dfree_t(w.theta);
+  w.scheme = w.precision = -1;
+  w.nv = 0;
+}
+
+void free_all(dolinc_ctx c) {
+  free_work(c);
+  DevMesh& m = c->m;
+  dfree_t(m.part_ptr); dfree_t(m.ent_face); dfree_t(m.ent_pn); dfree_t(m.slot_ptr); dfree_t(m.slots);
+  dfree_t(m.face_ent); dfree_t(m.face_own); dfree_t(m.face_nei);
+  dfree_t(m.nodes); dfree_t(m.fptr); dfree_t(m.fnodes); dfree_t(m.shift);
+  dfree_t(m.V); dfree_t(m.xc); dfree_t(m.S); dfree_t(m.xf); dfree_t(m.fanc); dfree_t(m.omega); dfree_t(m.g);
+  dfree_t(m.dvec);
+  dfree_t(c->w.diag);
+  dfree_t(c->w.flag);
+}
+
+dolinc_status check_params(const dolinc_params* p, int dim) {
+  if (!p) return fail(DOLINC_EINVAL, "params is NULL");
+  if (p->pde < 0 || p->pde > 2) return fail(DOLINC_EINVAL, "unknown pde");
+  if (p->scheme < 1 || p->scheme > 5) return fail(DOLINC_EINVAL, "unknown scheme");
+  if (p->precision < 0 || p->precision > 1) return fail(DOLINC_EINVAL, "unknown precision");
+  if (p->blend < 0 || p->blend > 2) return fail(DOLINC_EINVAL, "unknown blend");
+  if (p->flux < 0 || p->flux > 2) return fail(DOLINC_EINVAL, "unknown flux");
+  if (p->pde != DOLINC_EULER && p->flux != DOLINC_FLUX_UPWIND)
+    return fail(DOLINC_EINVAL, "scalar equations use the upwind (Godunov) flux");
+  if (p->pde == DOLINC_EULER && p->flux == DOLINC_FLUX_UPWIND)
+    return fail(DOLINC_EINVAL, "Euler needs the Rusanov or HLLC flux");
+  if (p->pde == DOLINC_EULER && dim != 3) return fail(DOLINC_EUNSUPPORTED, "Euler is built for dim = 3");
+  if (p->blend != DOLINC_BLEND_NONE && p->pde != DOLINC_EULER)
+    return fail(DOLINC_EUNSUPPORTED, "blending is built for the Euler equations");
+  if (p->pde == DOLINC_EULER && !(p->gamma > 1.0 && std::isfinite(p->gamma)))
+    return fail(DOLINC_EINVAL, "gamma must be > 1");
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(p->adv_vel[k]) || !std::isfinite(p->burgers_dir[k]))
+      return fail(DOLINC_EINVAL, "non-finite velocity");
+  if (p->use_u_ref) {
+    if (p->pde != DOLINC_EULER) return fail(DOLINC_EUNSUPPORTED, "u_ref is built for the Euler equations");
+    for (int k = 0; k < 5; ++k)
+      if (!std::isfinite(p->u_ref[k])) return fail(DOLINC_EINVAL, "non-finite u_ref");
+  }
+  return DOLINC_OK;
+}
+
+hipError_t grad_dispatch(dolinc_ctx c, const void* U, void* G1, void* G2, hipStream_t s) {
+  return c->w.precision == DOLINC_FP64 ? grad_f64(c, U, G1, G2, s) : grad_f32(c, U, G1, G2, s);
+}
+
+// gradients (and classical theta) that one residual evaluation of U needs
+hipError_t prepare_stage(dolinc_ctx c, const void* U, hipStream_t s) {
+  const int ord = scheme_order(c->params.scheme);
+  const bool bl = c->params.blend != DOLINC_BLEND_NONE;
+  if (ord >= 1 || bl) {
+    hipError_t e = grad_dispatch(c, U, c->w.G1, ord >= 2 ? c->w.G2 : nullptr, s);
+    if (e != hipSuccess) return e;
+  }
+  if (c->params.blend == DOLINC_BLEND_CLASSICAL)
+    return c->w.precision == DOLINC_FP64 ? theta_f64(c, U, c->w.G1, c->w.theta, s)
+                                         : theta_f32(c, U, c->w.G1, c->w.theta, s);
+  return hipSuccess;
+}
+
+hipError_t stage(dolinc_ctx c, const void* Us, const void* Un, void* out, int mode, double al, double be, double dt,
+                 hipStream_t s) {
+  hipError_t e = prepare_stage(c, Us, s);
+  if (e != hipSuccess) return e;
+  return c->w.precision == DOLINC_FP64 ? flux_f64(c, Us, Un, out, mode, al, be, dt, s)
+                                       : flux_f32(c, Us, Un, out, mode, al, be, dt, s);
+}
+
+dolinc_status need_ready(dolinc_ctx c) {
+  if (!valid_ctx(c)) return fail(DOLINC_ESTATE, "invalid or destroyed context");
+  if (!c->precomputed) return fail(DOLINC_ESTATE, "dolinc_precompute has not been called");
+  return DOLINC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dolinc_last_error(void) { return g_err.c_str(); }
+int32_t dolinc_version(void) { return 100; }
+
+dolinc_status dolinc_mesh_prepare(const dolinc_mesh_desc* mesh, int32_t* new_of_old, dolinc_mesh_stats* stats) {
+  if (!mesh) return fail(DOLINC_EINVAL, "mesh is NULL");
+  try {
+    Prepared P;
+    std::string msg;
+    dolinc_status st = prepare_mesh(*mesh, P, msg);
+    if (st != DOLINC_OK) return fail(st, msg);
+    if (new_of_old) std::memcpy(new_of_old, P.new_of_old.data(), P.new_of_old.size() * sizeof(int32_t));
+    if (stats) {
+      stats->n_parts = P.n_parts;
+      stats->n_entries = (int64_t)P.ent_face.size();
+      stats->max_entries = P.max_entries;
+      stats->max_cell_faces = P.max_cell_faces;
+      stats->n_slots = (int64_t)P.slots.size();
+    }
+  } catch (const std::bad_alloc&) {
+    return fail(DOLINC_ENOMEM, "host allocation failed");
+  }
+  return DOLINC_OK;
+}
+
+dolinc_status dolinc_create(const dolinc_mesh_desc* mesh, dolinc_ctx* out) {
+  if (!mesh || !out) return fail(DOLINC_EINVAL, "NULL argument");
+  *out = nullptr;
+  dolinc_ctx c = nullptr;
+  try {
+    Prepared P;
+    std::string msg;
+    dolinc_status st = prepare_mesh(*mesh, P, msg);
+    if (st != DOLINC_OK) return fail(st, msg);
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return fail(DOLINC_EHIP, "no HIP device");
+    c = new dolinc_ctx_s();
+    c->dim = P.dim;
+    c->n_cells = P.n_cells;
+    c->n_faces = P.n_faces;
+    c->n_nodes = P.n_nodes;
+    c->n_entries = (int64_t)P.ent_face.size();
+    c->n_parts = P.n_parts;
+    c->part_cells = P.part_cells;
+    c->max_entries = P.max_entries;
+    c->max_cell_faces = P.max_cell_faces;
+    c->new_of_old = P.new_of_old;
+    const int dim = P.dim;
+    const int64_t nf = P.n_faces;
+    std::vector<int2> pn(c->n_entries);
+    for (int64_t e = 0; e < c->n_entries; ++e) pn[e] = make_int2(P.ent_p[e], P.ent_n[e]);
+    std::vector<int32_t> fo(nf), fn(nf);
+    for (int64_t f = 0; f < nf; ++f) {
+      fo[f] = P.new_of_old[mesh->owner[f]];
+      fn[f] = P.new_of_old[mesh->neighbour[f]];
+    }
+    DevMesh& m = c->m;
+    hipError_t e = hipSuccess;
+#define UP(dst, src, n)                                       \
+  if (e == hipSuccess) e = upload(&(dst), (src), (size_t)(n));
+    UP(m.part_ptr, P.part_ent_ptr.data(), P.part_ent_ptr.size());
+    UP(m.ent_face, P.ent_face.data(), P.ent_face.size());
+    UP(m.ent_pn, pn.data(), pn.size());
+    UP(m.slot_ptr, P.slot_ptr.data(), P.slot_ptr.size());
+    UP(m.slots, P.slots.data(), P.slots.size());
+    UP(m.face_ent, P.face_first_ent.data(), P.face_first_ent.size());
+    UP(m.face_own, fo.data(), fo.size());
+    UP(m.face_nei, fn.data(), fn.size());
+    UP(m.nodes, mesh->node_xyz, mesh->n_nodes * dim);
+    UP(m.fptr, mesh->face_node_ptr, nf + 1);
+    UP(m.fnodes, mesh->face_nodes, mesh->face_node_ptr[nf]);
+    UP(m.shift, mesh->neigh_shift, nf * dim);
+#undef UP
+    const size_t nc = (size_t)P.n_cells;
+    auto dm = [&](double** p, size_t n) {
+      if (e == hipSuccess) e = hipMalloc((void**)p, n * sizeof(double));
+    };
+    dm(&m.V, nc);
+    dm(&m.xc, 3 * nc);
+    dm(&m.S, 3 * (size_t)nf);
+    dm(&m.xf, 3 * (size_t)nf);
+    dm(&m.fanc, 3 * (size_t)nf);
+    dm(&m.omega, nf);
+    dm(&m.g, nf);
+    dm(&m.dvec, 3 * (size_t)nf);
+    if (e == hipSuccess) e = hipMalloc((void**)&c->w.flag, sizeof(int));
+    if (e == hipSuccess) e = hipMalloc((void**)&c->w.diag, 1024 * 8 * sizeof(double));
+    if (e != hipSuccess) {
+      free_all(c);
+      delete c;
+      return fail(e == hipErrorOutOfMemory ? DOLINC_ENOMEM : DOLINC_EHIP,
+                  std::string("device upload failed: ") + hipGetErrorString(e));
+    }
+  } catch (const std::bad_alloc&) {
+    if (c) {
+      free_all(c);
+      delete c;
+    }
+    return fail(DOLINC_ENOMEM, "host allocation failed");
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_live_mu);
+    g_live.insert((const void*)c);
+  }
+  *out = c;
+  return DOLINC_OK;
+}
+
+dolinc_status dolinc_permutation(dolinc_ctx c, int32_t* new_of_old) {
+  if (!valid_ctx(c)) return fail(DOLINC_ESTATE, "invalid or destroyed context");
+  if (!new_of_old) return fail(DOLINC_EINVAL, "NULL output");
+  std::memcpy(new_of_old, c->new_of_old.data(), c->new_of_old.size() * sizeof(int32_t));
+  return DOLINC_OK;
+}
+
+dolinc_status dolinc_stats(dolinc_ctx c, dolinc_mesh_stats* st) {
+  if (!valid_ctx(c)) return fail(DOLINC_ESTATE, "invalid or destroyed context");
+  if (!st) return fail(DOLINC_EINVAL, "NULL output");
+  st->n_parts = c->n_parts;
+  st->n_entries = c->n_entries;
+  st->max_entries = c->max_entries;
+  st->max_cell_faces = c->max_cell_faces;
+  st->n_slots = 2 * c->n_faces;
+  return DOLINC_OK;
+}
+
+dolinc_status dolinc_precompute(dolinc_ctx c, const dolinc_params* p, dolinc_stream stream) {
+  if (!valid_ctx(c)) return fail(DOLINC_ESTATE, "invalid or destroyed context");
+  dolinc_status st = check_params(p, c->dim);
+  if (st != DOLINC_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  c->precomputed = false;
+  if (!c->geometry_done) {
+    HIPCHK(hipMemsetAsync(c->w.flag, 0, sizeof(int), s));
+    HIPCHK(launch_geometry(c, s));
+    int flag = 0;
+    HIPCHK(hipMemcpyAsync(&flag, c->w.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (flag & 1) return fail(DOLINC_EMESH, "a cell has non-positive volume");
+    if (flag & 2) return fail(DOLINC_EMESH, "a cell is not closed (sum of face area vectors != 0)");
+    if (flag & 4) return fail(DOLINC_EMESH, "a face has a degenerate distance weight");
+    c->geometry_done = true;
+    dfree_t(c->m.nodes);
+    dfree_t(c->m.fnodes);
+    dfree_t(c->m.fptr);
+    dfree_t(c->m.fanc);
+  }
+  const int nv = p->pde == DOLINC_EULER ? c->dim + 2 : 1;
+  const size_t el = p->precision == DOLINC_FP64 ? sizeof(double) : sizeof(float);
+  const int ord = scheme_order(p->scheme);
+  const bool bl = p->blend != DOLINC_BLEND_NONE;
+  if ((size_t)c->max_entries * nv * el > 65536)
+    return fail(DOLINC_EUNSUPPORTED, "partition face fluxes exceed 64 KiB of LDS; use a smaller part_cells");
+  if (c->w.precision != p->precision || c->w.scheme != p->scheme || c->w.nv != nv || c->w.blend != p->blend) {
+    free_work(c);
+    const size_t nc = (size_t)c->n_cells, ne = (size_t)c->n_entries;
+    hipError_t e = hipSuccess;
+    auto al = [&](void** q, size_t bytes) {
+      if (e == hipSuccess) e = hipMalloc(q, bytes ? bytes : 16);
+    };
+    al(&c->w.sw, ne * 4 * el);
+    al(&c->w.dc, ne * (size_t)dc_stride(p->scheme) * el);
+    al(&c->w.rV, nc * el);
+    if (ord >= 1 || bl) al(&c->w.G1, nc * nv * c->dim * el);
+    if (ord >= 2) al(&c->w.G2, nc * nv * (c->dim * (c->dim + 1) / 2) * el);
+    al(&c->w.W1, nc * nv * el);
+    al(&c->w.W2, nc * nv * el);
+    if (bl) al((void**)&c->w.theta, nc * sizeof(float));
+    if (e != hipSuccess) {
+      free_work(c);
+      return fail(DOLINC_ENOMEM, std::string("workspace allocation failed: ") + hipGetErrorString(e));
+    }
+    c->w.precision = p->precision;
+    c->w.scheme = p->scheme;
+    c->w.nv = nv;
+    c->w.blend = p->blend;
+    c->w.elem = el;
+  }
+  c->params = *p;
+  HIPCHK(launch_entry_fill(c, s));
+  if (bl) HIPCHK(hipMemsetAsync(c->w.theta, 0, (size_t)c->n_cells * sizeof(float), s));
+  HIPCHK(hipStreamSynchronize(s));
+  c->precomputed = true;
+  return DOLINC_OK;
+}
+
+dolinc_status dolinc_residual(dolinc_ctx c, const void* U, void* R, dolinc_stream stream) {
+  dolinc_status st = need_ready(c);
+  if (st != DOLINC_OK) return st;
+  if (!U || !R) return fail(DOLINC_EINVAL, "NULL state");
+  if (U == R) return fail(DOLINC_EINVAL, "U and R must differ");
+  HIPCHK(stage(c, U, nullptr, R, 0, 0.0, 0.0, 0.0, (hipStream_t)stream));
+  return DOLINC_OK;
+}
+
+static dolinc_status rk_step_impl(dolinc_ctx c, void* U, double dt, hipStream_t s) {
+  // SSP-RK3 (third-order TVD Runge-Kutta, Sec. 3); stage outputs in W1, W2,
+  // the last stage overwrites U cell by cell after reading it
+  HIPCHK(stage(c, U, nullptr, c->w.W1, 1, 0.0, 1.0, dt, s));
+  HIPCHK(stage(c, c->w.W1, U, c->w.W2, 1, 0.75, 0.25, dt, s));
+  HIPCHK(stage(c, c->w.W2, U, U, 1, 1.0 / 3.0, 2.0 / 3.0, dt, s));
+  return DOLINC_OK;
+}
+
+dolinc_status dolinc_rk_step(dolinc_ctx c, void* U, double dt, dolinc_stream stream) {
+  dolinc_status st = need_ready(c);
+  if (st != DOLINC_OK) return st;
+  if (!U) return fail(DOLINC_EINVAL, "NULL state");
+  if (!(std::isfinite(dt) && dt > 0.0)) return fail(DOLINC_EINVAL, "dt must be finite and > 0");
+  return rk_step_impl(c, U, dt, (hipStream_t)stream);
+}
+
+dolinc_status dolinc_advance(dolinc_ctx c, void* U, double dt, int64_t n, dolinc_stream stream) {
+  dolinc_status st = need_ready(c);
+  if (st != DOLINC_OK) return st;
+  if (!U) return fail(DOLINC_EINVAL, "NULL state");
+  if (!(std::isfinite(dt) && dt > 0.0)) return fail(DOLINC_EINVAL, "dt must be finite and > 0");
+  if (n < 0) return fail(DOLINC_EINVAL, "n_steps must be >= 0");
+  for (int64_t k = 0; k < n; ++k) {
+    st = rk_step_impl(c, U, dt, (hipStream_t)stream);
+    if (st != DOLINC_OK) return st;
+  }
+  return DOLINC_OK;
+}
+
+dolinc_status dolinc_set_theta(dolinc_ctx c, const float* theta, dolinc_stream stream) {
+  dolinc_status st = need_ready(c);
+  if (st != DOLINC_OK) return st;
+  if (c->params.blend != DOLINC_BLEND_THETA) return fail(DOLINC_ESTATE, "blend mode is not THETA");
+  if (!theta) return fail(DOLINC_EINVAL, "NULL theta");
+  HIPCHK(hipMemcpyAsync(c->w.theta, theta, (size_t)c->n_cells * sizeof(float), hipMemcpyDeviceToDevice,
+                        (hipStream_t)stream));
+  return DOLINC_OK;
+}
+
+dolinc_status dolinc_classical_theta(dolinc_ctx c, const void* U, float* theta, dolinc_stream stream) {
+  dolinc_status st = need_ready(c);
+  if (st != DOLINC_OK) return st;
+  if (!U || !theta) return fail(DOLINC_EINVAL, "NULL argument");
+  if (!c->w.G1) return fail(DOLINC_ESTATE, "no gradient workspace (scheme of order 0 without blend)");
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(grad_dispatch(c, U, c->w.G1, nullptr, s));
+  HIPCHK(c->w.precision == DOLINC_FP64 ? theta_f64(c, U, c->w.G1, theta, s) : theta_f32(c, U, c->w.G1, theta, s));
+  return DOLINC_OK;
+}
+
+dolinc_status dolinc_gradients(dolinc_ctx c, const void* U, void* G1, void* G2, dolinc_stream stream) {
+  dolinc_status st = need_ready(c);
+  if (st != DOLINC_OK) return st;
+  if (!U || !G1) return fail(DOLINC_EINVAL, "NULL argument");
+  HIPCHK(grad_dispatch(c, U, G1, G2, (hipStream_t)stream));
+  return DOLINC_OK;
+}
+
+dolinc_status dolinc_face_states(dolinc_ctx c, const void* U, void* UL, void* UR, void* F, dolinc_stream stream) {
+  dolinc_status st = need_ready(c);
+  if (st != DOLINC_OK) return st;
+  if (!U || !UL || !UR) return fail(DOLINC_EINVAL, "NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(prepare_stage(c, U, s));
+  HIPCHK(c->w.precision == DOLINC_FP64 ? export_f64(c, U, UL, UR, F, s) : export_f32(c, U, UL, UR, F, s));
+  return DOLINC_OK;
+}
+
+dolinc_status dolinc_geometry(dolinc_ctx c, double* V, double* xc, double* S, double* xf, double* omega, double* g,
+                              dolinc_stream stream) {
+  if (!valid_ctx(c)) return fail(DOLINC_ESTATE, "invalid or destroyed context");
+  if (!c->geometry_done) return fail(DOLINC_ESTATE, "dolinc_precompute has not been called");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t nc = (size_t)c->n_cells, nf = (size_t)c->n_faces;
+  const int d = c->dim;
+  if (V) HIPCHK(hipMemcpyAsync(V, c->m.V, nc * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (xc) HIPCHK(hipMemcpy2DAsync(xc, d * sizeof(double), c->m.xc, 3 * sizeof(double), d * sizeof(double), nc,
+                                  hipMemcpyDeviceToDevice, s));
+  if (S) HIPCHK(hipMemcpy2DAsync(S, d * sizeof(double), c->m.S, 3 * sizeof(double), d * sizeof(double), nf,
+                                 hipMemcpyDeviceToDevice, s));
+  if (xf) HIPCHK(hipMemcpy2DAsync(xf, d * sizeof(double), c->m.xf, 3 * sizeof(double), d * sizeof(double), nf,
+                                  hipMemcpyDeviceToDevice, s));
+  if (omega) HIPCHK(hipMemcpyAsync(omega, c->m.omega, nf * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (g) HIPCHK(hipMemcpyAsync(g, c->m.g, nf * sizeof(double), hipMemcpyDeviceToDevice, s));
+  return DOLINC_OK;
+}
+
+dolinc_status dolinc_diagnostics(dolinc_ctx c, const void* U, double* out, dolinc_stream stream) {
+  dolinc_status st = need_ready(c);
+  if (st != DOLINC_OK) return st;
+  if (!U || !out) return fail(DOLINC_EINVAL, "NULL argument");
+  hipStream_t s = (hipStream_t)stream;
+  const int nv = c->w.nv, nout = nv + 3;
+  int nb = (int)((c->n_cells + KTPB_HOST - 1) / KTPB_HOST);
+  if (nb > 1024) nb = 1024;
+  HIPCHK(c->w.precision == DOLINC_FP64 ? diag_f64(c, U, c->w.diag, nb, s) : diag_f32(c, U, c->w.diag, nb, s));
+  std::vector<double> part((size_t)nb * nout);
+  HIPCHK(hipMemcpyAsync(part.data(), c->w.diag, part.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const bool euler = c->params.pde == DOLINC_EULER;
+  for (int k = 0; k < nout; ++k) {
+    double acc = k < nv || k == nv + 2 ? 0.0 : (k == nv || euler ? 1e300 : -1e300);
+    for (int b = 0; b < nb; ++b) {
+      double x = part[(size_t)b * nout + k];
+      if (k < nv || k == nv + 2)
+        acc += x;
+      else if (k == nv || euler)
+        acc = std::fmin(acc, x);
+      else
+        acc = std::fmax(acc, x);
+    }
+    out[k] = acc;
+  }
+  return DOLINC_OK;
+}
+
+void dolinc_destroy(dolinc_ctx c) {
+  {
+    std::lock_guard<std::mutex> lk(g_live_mu);
+    if (!c || !g_live.erase((const void*)c)) return;
+  }
+  free_all(c);
+  delete c;
+}
+
+}  // extern "C"

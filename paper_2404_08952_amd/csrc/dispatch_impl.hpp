@@ -1,0 +1,184 @@
+// Launch-side dispatch from runtime parameters to kernel instantiations.
+// Included once per working type (kernels_f64.hip, kernels_f32.hip).
+#pragma once
+#include "residual_impl.hpp"
+
+namespace dolinc {
+
+template <class T>
+KArgs<T> base_args(dolinc_ctx_s* c) {
+  KArgs<T> a{};
+  a.nc = c->n_cells;
+  a.np = (int)c->n_parts;
+  a.B = c->part_cells;
+  a.per_xcd = (int)((c->n_parts + 7) / 8);
+  a.n_cell_blocks = (int)((c->n_cells + KTPB - 1) / KTPB);
+  a.cell_per_xcd = (a.n_cell_blocks + 7) / 8;
+  a.part_ptr = c->m.part_ptr;
+  a.ent_pn = c->m.ent_pn;
+  a.slot_ptr = c->m.slot_ptr;
+  a.slots = c->m.slots;
+  a.sw = (const T*)c->w.sw;
+  a.dc = (const T*)c->w.dc;
+  a.rV = (const T*)c->w.rV;
+  a.G1 = (const T*)c->w.G1;
+  a.G2 = (const T*)c->w.G2;
+  a.theta = c->w.theta;
+  a.gamma = (T)c->params.gamma;
+  for (int k = 0; k < 3; ++k) {
+    a.adv[k] = (T)c->params.adv_vel[k];
+    a.bdir[k] = (T)c->params.burgers_dir[k];
+  }
+  a.use_ref = c->params.use_u_ref;
+  for (int k = 0; k < 5; ++k) a.uref[k] = (T)c->params.u_ref[k];
+  a.face_ent = c->m.face_ent;
+  a.nf = c->n_faces;
+  return a;
+}
+
+// pk: 0 advection, 1 Burgers, 2 Euler-Rusanov, 3 Euler-HLLC
+inline int pde_kind(const dolinc_params& p) {
+  if (p.pde == DOLINC_ADVECTION) return 0;
+  if (p.pde == DOLINC_BURGERS) return 1;
+  return p.flux == DOLINC_FLUX_HLLC ? 3 : 2;
+}
+
+template <class T, int D, int PK, int SCH, bool BL>
+hipError_t go_flux(const KArgs<T>& a, size_t lds, hipStream_t s, bool exporting) {
+  if (exporting) {
+    const unsigned nb = (unsigned)((a.nf + KTPB - 1) / KTPB);
+    hipLaunchKernelGGL((k_face_export<T, D, PK, SCH, BL>), dim3(nb), dim3(KTPB), 0, s, a);
+  } else {
+    hipLaunchKernelGGL((k_flux<T, D, PK, SCH, BL>), dim3(8 * a.per_xcd), dim3(KTPB), lds, s, a);
+  }
+  return hipGetLastError();
+}
+
+template <class T, int D, int PK, bool BL>
+hipError_t flux_by_scheme(int sch, const KArgs<T>& a, size_t lds, hipStream_t s, bool ex) {
+  switch (sch) {
+    case 1: return go_flux<T, D, PK, 1, BL>(a, lds, s, ex);
+    case 2: return go_flux<T, D, PK, 2, BL>(a, lds, s, ex);
+    case 3: return go_flux<T, D, PK, 3, BL>(a, lds, s, ex);
+    case 4: return go_flux<T, D, PK, 4, BL>(a, lds, s, ex);
+    case 5: return go_flux<T, D, PK, 5, BL>(a, lds, s, ex);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <class T>
+hipError_t run_flux(dolinc_ctx_s* c, const KArgs<T>& a, hipStream_t s, bool ex) {
+  const int pk = pde_kind(c->params);
+  const int nv = c->w.nv;
+  const size_t lds = (size_t)c->max_entries * nv * sizeof(T);
+  const bool bl = c->params.blend != DOLINC_BLEND_NONE;
+  const int sch = c->params.scheme;
+  if (c->dim == 2) {
+    if (pk == 0) return flux_by_scheme<T, 2, 0, false>(sch, a, lds, s, ex);
+    if (pk == 1) return flux_by_scheme<T, 2, 1, false>(sch, a, lds, s, ex);
+    return hipErrorInvalidValue;
+  }
+  if (pk == 0) return flux_by_scheme<T, 3, 0, false>(sch, a, lds, s, ex);
+  if (pk == 1) return flux_by_scheme<T, 3, 1, false>(sch, a, lds, s, ex);
+  if (pk == 2) return bl ? flux_by_scheme<T, 3, 2, true>(sch, a, lds, s, ex)
+                         : flux_by_scheme<T, 3, 2, false>(sch, a, lds, s, ex);
+  return bl ? flux_by_scheme<T, 3, 3, true>(sch, a, lds, s, ex) : flux_by_scheme<T, 3, 3, false>(sch, a, lds, s, ex);
+}
+
+template <class T>
+hipError_t run_gradients(dolinc_ctx_s* c, const void* U, void* G1, void* G2, hipStream_t s) {
+  KArgs<T> a = base_args<T>(c);
+  const dim3 grid(8 * a.cell_per_xcd), blk(KTPB);
+  const int nv = c->w.nv;
+  const T* u = (const T*)U;
+  T* g1 = (T*)G1;
+  T* g2 = (T*)G2;
+  if (c->dim == 2) {
+    if (nv != 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_grad<T, 2, 1, false>), grid, blk, 0, s, a, u, g1);
+    if (g2) hipLaunchKernelGGL((k_grad<T, 2, 2, true>), grid, blk, 0, s, a, (const T*)g1, g2);
+  } else if (nv == 1) {
+    hipLaunchKernelGGL((k_grad<T, 3, 1, false>), grid, blk, 0, s, a, u, g1);
+    if (g2) hipLaunchKernelGGL((k_grad<T, 3, 3, true>), grid, blk, 0, s, a, (const T*)g1, g2);
+  } else {
+    hipLaunchKernelGGL((k_grad<T, 3, 5, false>), grid, blk, 0, s, a, u, g1);
+    if (g2) hipLaunchKernelGGL((k_grad<T, 3, 15, true>), grid, blk, 0, s, a, (const T*)g1, g2);
+  }
+  return hipGetLastError();
+}
+
+template <class T>
+hipError_t run_theta(dolinc_ctx_s* c, const void* U, const void* G1, float* theta, hipStream_t s) {
+  KArgs<T> a = base_args<T>(c);
+  a.U = (const T*)U;
+  a.G1 = (const T*)G1;
+  const dim3 grid(8 * a.cell_per_xcd), blk(KTPB);
+  const int dcs = dc_stride(c->params.scheme);
+  if (c->dim == 2) {
+    hipLaunchKernelGGL((k_theta<T, 2, 1>), grid, blk, 0, s, a, dcs, theta);
+  } else if (c->w.nv == 1) {
+    hipLaunchKernelGGL((k_theta<T, 3, 1>), grid, blk, 0, s, a, dcs, theta);
+  } else {
+    hipLaunchKernelGGL((k_theta<T, 3, 5>), grid, blk, 0, s, a, dcs, theta);
+  }
+  return hipGetLastError();
+}
+
+// Per-block partial diagnostics: [sum V*U_v (v < nv), min q0, min p | max q0, nonfinite]
+template <class T>
+__global__ __launch_bounds__(KTPB) void k_diag(int64_t nc, int nv, int euler, T gamma, const T* __restrict__ U,
+                                               const double* __restrict__ V, double* __restrict__ part) {
+  __shared__ double red[KTPB];
+  double acc[8];
+  for (int k = 0; k < 8; ++k) acc[k] = 0.0;
+  double mn0 = 1e300, m2 = euler ? 1e300 : -1e300, bad = 0.0;
+  for (int64_t c = (int64_t)blockIdx.x * KTPB + threadIdx.x; c < nc; c += (int64_t)gridDim.x * KTPB) {
+    const double vol = V[c];
+    double ke = 0.0;
+    for (int v = 0; v < nv; ++v) {
+      const double x = (double)U[c * nv + v];
+      if (!isfinite(x)) bad += 1.0;
+      acc[v] += vol * x;
+    }
+    const double q0 = (double)U[c * nv];
+    mn0 = fmin(mn0, q0);
+    if (euler) {
+      for (int v = 1; v < nv - 1; ++v) ke += (double)U[c * nv + v] * (double)U[c * nv + v];
+      const double p = ((double)gamma - 1.0) * ((double)U[c * nv + nv - 1] - 0.5 * ke / q0);
+      m2 = fmin(m2, p);
+    } else {
+      m2 = fmax(m2, q0);
+    }
+  }
+  const int nout = nv + 3;
+  for (int k = 0; k < nout; ++k) {
+    double x = k < nv ? acc[k] : (k == nv ? mn0 : (k == nv + 1 ? m2 : bad));
+    red[threadIdx.x] = x;
+    __syncthreads();
+    for (int w = KTPB / 2; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) {
+        double y = red[threadIdx.x + w];
+        double z = red[threadIdx.x];
+        if (k < nv || k == nv + 2)
+          red[threadIdx.x] = z + y;
+        else if (k == nv || euler)
+          red[threadIdx.x] = fmin(z, y);
+        else
+          red[threadIdx.x] = fmax(z, y);
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * nout + k] = red[0];
+    __syncthreads();
+  }
+}
+
+template <class T>
+hipError_t run_diag(dolinc_ctx_s* c, const void* U, double* part, int nblocks, hipStream_t s) {
+  const int euler = c->params.pde == DOLINC_EULER;
+  hipLaunchKernelGGL(k_diag<T>, dim3(nblocks), dim3(KTPB), 0, s, c->n_cells, c->w.nv, euler, (T)c->params.gamma,
+                     (const T*)U, c->m.V, part);
+  return hipGetLastError();
+}
+
+}  // namespace dolinc

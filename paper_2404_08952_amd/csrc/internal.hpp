@@ -1,0 +1,97 @@
+// Library-internal declarations shared by the C ABI layer and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/dolinc.h"
+#include "mesh_prep.hpp"
+
+namespace dolinc {
+
+// Per-face record layout (one record per partition entry).
+//   sw[e][4]  : S_x, S_y, S_z (0 in 2-D), omega (owner weight)
+//   dc[e][DC] : d_x, d_y, d_z, then the coefficients of the DOLINC
+//               representation of each side (see kernels for the meaning).
+inline int coef_left(int scheme) { return scheme <= 2 ? 1 : scheme == 3 ? 2 : scheme == 4 ? 3 : 4; }
+inline int coef_right(int scheme) { return scheme <= 2 ? 1 : scheme == 3 ? 2 : scheme == 4 ? 0 : 4; }
+inline int dc_stride(int scheme) {
+  int n = 3 + coef_left(scheme) + coef_right(scheme);
+  return (n + 3) & ~3;
+}
+inline int scheme_order(int scheme) { return scheme <= 2 ? 0 : scheme <= 4 ? 1 : 2; }
+
+struct DevMesh {
+  // partitions / entries / slots
+  int32_t* part_ptr = nullptr;
+  int32_t* ent_face = nullptr;
+  int2* ent_pn = nullptr;
+  int32_t* slot_ptr = nullptr;
+  uint16_t* slots = nullptr;
+  int32_t* face_ent = nullptr;   // one entry per caller face
+  int32_t* face_own = nullptr;   // internal owner per caller face
+  int32_t* face_nei = nullptr;
+  // raw mesh (precompute only)
+  double* nodes = nullptr;
+  int64_t* fptr = nullptr;
+  int32_t* fnodes = nullptr;
+  double* shift = nullptr;
+  // FP64 geometry
+  double* V = nullptr;
+  double* xc = nullptr;
+  double* S = nullptr;
+  double* xf = nullptr;
+  double* fanc = nullptr;
+  double* omega = nullptr;
+  double* g = nullptr;
+  double* dvec = nullptr;
+};
+
+struct Work {
+  void* sw = nullptr;
+  void* dc = nullptr;
+  void* rV = nullptr;
+  void* G1 = nullptr;
+  void* G2 = nullptr;
+  void* W1 = nullptr;
+  void* W2 = nullptr;
+  float* theta = nullptr;
+  double* diag = nullptr;  // partial sums for diagnostics
+  int* flag = nullptr;     // device error flag
+  size_t elem = 0;         // sizeof working type
+  int scheme = -1, precision = -1, nv = 0, blend = 0;
+};
+
+}  // namespace dolinc
+
+struct dolinc_ctx_s {
+  int dim = 0;
+  int64_t n_cells = 0, n_faces = 0, n_nodes = 0, n_entries = 0, n_parts = 0;
+  int part_cells = 256;
+  int64_t max_entries = 0, max_cell_faces = 0;
+  std::vector<int32_t> new_of_old;
+  dolinc::DevMesh m;
+  dolinc::Work w;
+  dolinc_params params{};
+  bool geometry_done = false;
+  bool precomputed = false;
+};
+
+namespace dolinc {
+
+// Launchers (kernels.hip / precompute.hip).  Return hipSuccess or an error.
+hipError_t launch_geometry(dolinc_ctx_s* c, hipStream_t s);
+hipError_t launch_entry_fill(dolinc_ctx_s* c, hipStream_t s);
+// stage kernels
+hipError_t launch_gradients(dolinc_ctx_s* c, const void* U, void* G1, void* G2, hipStream_t s);
+hipError_t launch_theta(dolinc_ctx_s* c, const void* U, const void* G1, float* theta, hipStream_t s);
+// mode 0: out = R(Us); mode 1: out = alpha*Un + beta*(Us + dt*R(Us))
+hipError_t launch_flux(dolinc_ctx_s* c, const void* Us, const void* Un, void* out, int mode, double alpha,
+                       double beta, double dt, hipStream_t s);
+hipError_t launch_face_export(dolinc_ctx_s* c, const void* U, void* UL, void* UR, void* F, hipStream_t s);
+hipError_t launch_diagnostics(dolinc_ctx_s* c, const void* U, double* out_host, hipStream_t s);
+bool flux_supported(const dolinc_params& p, int dim);
+
+}  // namespace dolinc

@@ -1,0 +1,43 @@
+// Host-side mesh preparation: validation, locality renumbering, partitions.
+//
+// The finite-volume mesh is face addressed (Sec. 2.1): a cell knows its
+// neighbours only through shared faces.  For the device kernels the cells are
+// renumbered (reverse Cuthill-McKee or a Hilbert space-filling curve) and cut
+// into contiguous partitions of at most B cells.  Each partition owns the list
+// of faces ("entries") touching any of its cells; faces on a partition seam
+// appear in both partitions.  A cell addresses its faces through "slots":
+// (local entry index, side) pairs, side 0 = owner (sigma = +1), 1 = neighbour.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/dolinc.h"
+
+namespace dolinc {
+
+struct Prepared {
+  int dim = 0;
+  int64_t n_cells = 0, n_faces = 0, n_nodes = 0;
+  int part_cells = 256;
+  std::vector<int32_t> new_of_old, old_of_new;
+  // partitions
+  int64_t n_parts = 0;
+  std::vector<int32_t> part_ent_ptr;   // [n_parts + 1]
+  std::vector<int32_t> ent_face;       // [n_entries] caller face id
+  std::vector<int32_t> ent_p, ent_n;   // [n_entries] internal cell ids (owner, neighbour)
+  std::vector<int32_t> face_first_ent; // [n_faces] one entry of every face
+  std::vector<int32_t> slot_ptr;       // [n_cells + 1] (internal order)
+  std::vector<uint16_t> slots;         // local entry | side << 15
+  int64_t max_entries = 0, max_cell_faces = 0;
+};
+
+// Returns DOLINC_OK or an error; msg receives a description.
+dolinc_status prepare_mesh(const dolinc_mesh_desc& d, Prepared& out, std::string& msg);
+
+// Renumbering helpers (exposed for tests through dolinc_mesh_prepare).
+void rcm_order(int64_t n, const std::vector<int64_t>& adj_ptr, const std::vector<int32_t>& adj,
+               std::vector<int32_t>& new_of_old);
+void hilbert_order(int dim, int64_t n, const std::vector<double>& pts, std::vector<int32_t>& new_of_old);
+
+}  // namespace dolinc

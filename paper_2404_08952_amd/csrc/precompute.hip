@@ -1,0 +1,312 @@
+// FP64 precompute on the device: geometry, face scalars and the per-face
+// coefficients of the DOLINC representation.
+//
+// Geometry (textbook finite volumes; the paper leaves it to the host code):
+//   face  : 2-D edge a->b: S = (t_y, -t_x); 3-D: triangle fan about the vertex
+//           average c, S = sum of fan triangle area vectors, centre weighted
+//           by triangle area.
+//   cell  : simplices (x_e, c, p_k, p_k+1), x_e = mean of the face centres;
+//           gives exact volume and centroid of the fan-bounded polyhedron.
+// Face scalars (Sec. 2.2): d = x_N - x_P, omega = |x_N - x_f| /
+// (|x_P - x_f| + |x_N - x_f|), growth rate g = omega / (1 - omega).
+// Coefficients (Sec. 2.3-2.4): reconstruction weights c_rj of eq:coeff in
+// closed form in g (USR3, CSR4 as printed; USR5 from the same formula),
+// G_n always summed as 1 + g + ... + g^(n-1); far cells folded in with the
+// inversion coefficients eq:lCoeffDLC1, eq:rCoeffDLC1, eq:lCoeffDLC2 into
+//   U_side = phi_other + w (phi_self - phi_other)
+//            + k0 phi_self^(1) + k1 phi_other^(1) + k2 phi_self^(2).
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+
+namespace dolinc {
+namespace {
+
+constexpr int TPB = 256;
+
+__device__ inline void cross3(const double* a, const double* b, double* o) {
+  o[0] = a[1] * b[2] - a[2] * b[1];
+  o[1] = a[2] * b[0] - a[0] * b[2];
+  o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+__global__ void k_face_geom(int64_t nf, int dim, const int64_t* __restrict__ fptr,
+                            const int32_t* __restrict__ fnodes, const double* __restrict__ nodes,
+                            double* __restrict__ S, double* __restrict__ xf, double* __restrict__ fanc) {
+  int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  const int64_t a = fptr[f], b = fptr[f + 1];
+  if (dim == 2) {
+    const double* p0 = nodes + 2 * (int64_t)fnodes[a];
+    const double* p1 = nodes + 2 * (int64_t)fnodes[a + 1];
+    double tx = p1[0] - p0[0], ty = p1[1] - p0[1];
+    S[3 * f + 0] = ty;
+    S[3 * f + 1] = -tx;
+    S[3 * f + 2] = 0.0;
+    xf[3 * f + 0] = fanc[3 * f + 0] = 0.5 * (p0[0] + p1[0]);
+    xf[3 * f + 1] = fanc[3 * f + 1] = 0.5 * (p0[1] + p1[1]);
+    xf[3 * f + 2] = fanc[3 * f + 2] = 0.0;
+    return;
+  }
+  const int m = (int)(b - a);
+  double c[3] = {0, 0, 0};
+  for (int k = 0; k < m; ++k) {
+    const double* p = nodes + 3 * (int64_t)fnodes[a + k];
+    c[0] += p[0]; c[1] += p[1]; c[2] += p[2];
+  }
+  c[0] /= m; c[1] /= m; c[2] /= m;
+  double s[3] = {0, 0, 0}, cen[3] = {0, 0, 0}, area = 0.0;
+  for (int k = 0; k < m; ++k) {
+    const double* q1 = nodes + 3 * (int64_t)fnodes[a + k];
+    const double* q2 = nodes + 3 * (int64_t)fnodes[a + (k + 1) % m];
+    double u[3] = {q1[0] - c[0], q1[1] - c[1], q1[2] - c[2]};
+    double v[3] = {q2[0] - c[0], q2[1] - c[1], q2[2] - c[2]};
+    double t[3];
+    cross3(u, v, t);
+    t[0] *= 0.5; t[1] *= 0.5; t[2] *= 0.5;
+    s[0] += t[0]; s[1] += t[1]; s[2] += t[2];
+    double at = sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+    area += at;
+    for (int x = 0; x < 3; ++x) cen[x] += at * (c[x] + q1[x] + q2[x]) / 3.0;
+  }
+  for (int x = 0; x < 3; ++x) {
+    S[3 * f + x] = s[x];
+    xf[3 * f + x] = cen[x] / area;
+    fanc[3 * f + x] = c[x];
+  }
+}
+
+// One thread per (internal) cell; faces reached through the partition slots.
+__global__ void k_cell_geom(int64_t nc, int dim, int B, const int32_t* __restrict__ part_ptr,
+                            const int32_t* __restrict__ ent_face, const int32_t* __restrict__ slot_ptr,
+                            const uint16_t* __restrict__ slots, const int64_t* __restrict__ fptr,
+                            const int32_t* __restrict__ fnodes, const double* __restrict__ nodes,
+                            const double* __restrict__ shift, const double* __restrict__ S,
+                            const double* __restrict__ xf, const double* __restrict__ fanc,
+                            double* __restrict__ V, double* __restrict__ xc, int* __restrict__ flag) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= nc) return;
+  const int e0 = part_ptr[c / B];
+  const int s0 = slot_ptr[c], s1 = slot_ptr[c + 1];
+  double xe[3] = {0, 0, 0}, clo[3] = {0, 0, 0}, sabs = 0.0;
+  for (int s = s0; s < s1; ++s) {
+    const uint16_t sl = slots[s];
+    const int f = ent_face[e0 + (sl & 0x7fff)];
+    const double sg = (sl >> 15) ? -1.0 : 1.0;
+    for (int x = 0; x < dim; ++x) {
+      xe[x] += xf[3 * f + x] - ((sl >> 15) ? shift[(int64_t)dim * f + x] : 0.0);
+      clo[x] += sg * S[3 * f + x];
+    }
+    sabs += sqrt(S[3 * f] * S[3 * f] + S[3 * f + 1] * S[3 * f + 1] + S[3 * f + 2] * S[3 * f + 2]);
+  }
+  const double inv = 1.0 / (double)(s1 - s0);
+  for (int x = 0; x < 3; ++x) xe[x] *= inv;
+  double vol = 0.0, mom[3] = {0, 0, 0};
+  for (int s = s0; s < s1; ++s) {
+    const uint16_t sl = slots[s];
+    const int f = ent_face[e0 + (sl & 0x7fff)];
+    const bool nb = (sl >> 15) != 0;
+    double t[3] = {0, 0, 0};
+    if (nb)
+      for (int x = 0; x < dim; ++x) t[x] = -shift[(int64_t)dim * f + x];
+    const int64_t a = fptr[f];
+    const int m = (int)(fptr[f + 1] - a);
+    if (dim == 2) {
+      const double* pa = nodes + 2 * (int64_t)fnodes[a + (nb ? 1 : 0)];
+      const double* pb = nodes + 2 * (int64_t)fnodes[a + (nb ? 0 : 1)];
+      double ax = pa[0] + t[0] - xe[0], ay = pa[1] + t[1] - xe[1];
+      double bx = pb[0] + t[0] - xe[0], by = pb[1] + t[1] - xe[1];
+      double v = 0.5 * (ax * by - ay * bx);
+      vol += v;
+      mom[0] += v * (xe[0] + (pa[0] + t[0]) + (pb[0] + t[0])) / 3.0;
+      mom[1] += v * (xe[1] + (pa[1] + t[1]) + (pb[1] + t[1])) / 3.0;
+      continue;
+    }
+    double fc[3] = {fanc[3 * f] + t[0], fanc[3 * f + 1] + t[1], fanc[3 * f + 2] + t[2]};
+    double w[3] = {fc[0] - xe[0], fc[1] - xe[1], fc[2] - xe[2]};
+    for (int k = 0; k < m; ++k) {
+      int k1 = nb ? (k + 1) % m : k;
+      int k2 = nb ? k : (k + 1) % m;
+      const double* q1 = nodes + 3 * (int64_t)fnodes[a + k1];
+      const double* q2 = nodes + 3 * (int64_t)fnodes[a + k2];
+      double u[3] = {q1[0] + t[0] - xe[0], q1[1] + t[1] - xe[1], q1[2] + t[2] - xe[2]};
+      double v[3] = {q2[0] + t[0] - xe[0], q2[1] + t[1] - xe[1], q2[2] + t[2] - xe[2]};
+      double cr[3];
+      cross3(u, v, cr);
+      double tv = (w[0] * cr[0] + w[1] * cr[1] + w[2] * cr[2]) / 6.0;
+      vol += tv;
+      for (int x = 0; x < 3; ++x)
+        mom[x] += tv * (xe[x] + fc[x] + (q1[x] + t[x]) + (q2[x] + t[x])) / 4.0;
+    }
+  }
+  V[c] = vol;
+  for (int x = 0; x < 3; ++x) xc[3 * c + x] = (x < dim) ? mom[x] / vol : 0.0;
+  const double cl = sqrt(clo[0] * clo[0] + clo[1] * clo[1] + clo[2] * clo[2]);
+  if (!(vol > 0.0)) atomicOr(flag, 1);
+  if (!(cl <= 1e-9 * sabs)) atomicOr(flag, 2);
+}
+
+__global__ void k_face_scalars(int64_t nf, int dim, const int32_t* __restrict__ own,
+                               const int32_t* __restrict__ nei, const double* __restrict__ xc,
+                               const double* __restrict__ shift, const double* __restrict__ xf,
+                               double* __restrict__ dvec, double* __restrict__ omega, double* __restrict__ g,
+                               int* __restrict__ flag) {
+  int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  const int P = own[f], N = nei[f];
+  double dP2 = 0.0, dN2 = 0.0;
+  for (int x = 0; x < 3; ++x) {
+    double sh = x < dim ? shift[(int64_t)dim * f + x] : 0.0;
+    double xP = xc[3 * P + x], xN = xc[3 * N + x] + sh;
+    dvec[3 * f + x] = xN - xP;
+    double a = xP - xf[3 * f + x], b = xN - xf[3 * f + x];
+    dP2 += a * a;
+    dN2 += b * b;
+  }
+  const double dP = sqrt(dP2), dN = sqrt(dN2);
+  const double om = dN / (dP + dN);
+  omega[f] = om;
+  g[f] = om / (1.0 - om);
+  if (!(om > 0.0 && om < 1.0)) atomicOr(flag, 4);
+}
+
+// DOLINC representation of one side (self = upwind cell of this frame,
+// growth rate g from self to other).  w, k0, k1, k2 as in the file comment.
+__device__ void side_coefficients(int scheme, double g, double* w, double* k0, double* k1, double* k2) {
+  *k0 = 0.0; *k1 = 0.0; *k2 = 0.0;
+  const double ig = 1.0 / g;
+  const double g2 = g * g, g3 = g2 * g, g4 = g3 * g, g5 = g4 * g;
+  const double G2 = 1.0 + g, G3 = 1.0 + g + g2, G4 = G3 + g3, G5 = G4 + g4;
+  switch (scheme) {
+    case DOLINC_FOU:
+      *w = 1.0;
+      return;
+    case DOLINC_CD2:
+      *w = g / G2;  // linear interpolation with the distance weight
+      return;
+    case DOLINC_USR3: {
+      const double den = G2 * G3;
+      const double c10 = -g3 / den, c11 = g * (1.0 + 2.0 * g + 2.0 * g2) / den;
+      // eq:lCoeffDLC1: a0 = 1 - 1/g, A = -phi_self^(1) / g
+      *w = c10 * (1.0 - ig) + c11;
+      *k0 = -c10 * ig;
+      return;
+    }
+    case DOLINC_CSR4: {
+      const double den = G3 * G4;
+      const double c10 = -g5 / den;
+      const double c11 = g2 * (1.0 + 2.0 * g + 2.0 * g2 + 2.0 * g3) / den;
+      const double c13 = -1.0 / den;
+      // eq:lCoeffDLC1 for the left far cell, eq:rCoeffDLC1 (a0 = g,
+      // A = g phi_other^(1)) for the right one
+      *w = c10 * (1.0 - ig) + c11 + c13 * g;
+      *k0 = -c10 * ig;
+      *k1 = c13 * g;
+      return;
+    }
+    case DOLINC_USR5: {
+      const double q = 1.0 + g2;
+      const double den = G2 * q * G3 * G5;
+      const double c0 = g4 * g5 / (q * G3 * G5);
+      const double c1 = -g5 * (g5 + 3.0 * g4 + 3.0 * g3 + 3.0 * g2 + 2.0 * g + 1.0) / den;
+      const double c2 = g2 * (3.0 * g5 * g2 + 6.0 * g3 * g3 + 9.0 * g5 + 10.0 * g4 + 9.0 * g3 + 6.0 * g2 +
+                              3.0 * g + 1.0) / den;
+      const double c4 = -1.0 / (G2 * q * G5);
+      const double ig2 = ig * ig, ig3 = ig2 * ig;
+      // eq:lCoeffDLC2 (phi_-2), eq:lCoeffDLC1 (phi_-1), eq:rCoeffDLC1 (phi_2)
+      *w = c0 * (1.0 - ig + ig2) + c1 * (1.0 - ig) + c2 + c4 * g;
+      *k0 = -c0 * ig * (1.0 - ig2) - c1 * ig;
+      *k1 = -c0 * ig3 + c4 * g;
+      *k2 = c0 * ig3;
+      return;
+    }
+    default:
+      *w = 1.0;
+  }
+}
+
+template <class T>
+__global__ void k_entry_fill(int64_t ne, int dim, int scheme, int dcs, const int32_t* __restrict__ ent_face,
+                             const double* __restrict__ S, const double* __restrict__ omega,
+                             const double* __restrict__ g, const double* __restrict__ dvec, T* __restrict__ sw,
+                             T* __restrict__ dc) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  const int f = ent_face[e];
+  sw[4 * e + 0] = (T)S[3 * f + 0];
+  sw[4 * e + 1] = (T)S[3 * f + 1];
+  sw[4 * e + 2] = (T)S[3 * f + 2];
+  sw[4 * e + 3] = (T)omega[f];
+  T* o = dc + (int64_t)dcs * e;
+  for (int x = 0; x < dcs; ++x) o[x] = (T)0;
+  o[0] = (T)dvec[3 * f + 0];
+  o[1] = (T)dvec[3 * f + 1];
+  o[2] = (T)dvec[3 * f + 2];
+  double w, k0, k1, k2;
+  const double gf = g[f];
+  // left state: frame P -> N, growth g; factors 2 and 4 of the DOLINC
+  // differentials folded in (they multiply d.G1 and d.G2.d)
+  side_coefficients(scheme, gf, &w, &k0, &k1, &k2);
+  int k = 3;
+  if (scheme <= DOLINC_CD2) {
+    o[k++] = (T)w;
+  } else if (scheme == DOLINC_USR3) {
+    o[k++] = (T)w; o[k++] = (T)(2.0 * k0);
+  } else if (scheme == DOLINC_CSR4) {
+    o[k++] = (T)w; o[k++] = (T)(2.0 * k0); o[k++] = (T)(2.0 * k1);
+  } else {
+    o[k++] = (T)w; o[k++] = (T)(2.0 * k0); o[k++] = (T)(2.0 * k1); o[k++] = (T)(4.0 * k2);
+  }
+  if (scheme == DOLINC_CSR4) return;  // symmetric template: one state per face
+  // right state: mirrored frame N -> P, growth 1/g, d -> -d
+  side_coefficients(scheme, 1.0 / gf, &w, &k0, &k1, &k2);
+  if (scheme <= DOLINC_CD2) {
+    o[k++] = (T)w;
+  } else if (scheme == DOLINC_USR3) {
+    o[k++] = (T)w; o[k++] = (T)(-2.0 * k0);
+  } else {
+    o[k++] = (T)w; o[k++] = (T)(-2.0 * k0); o[k++] = (T)(-2.0 * k1); o[k++] = (T)(4.0 * k2);
+  }
+}
+
+template <class T>
+__global__ void k_recip(int64_t n, const double* __restrict__ V, T* __restrict__ rV) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n) rV[c] = (T)(1.0 / V[c]);
+}
+
+inline unsigned nblk(int64_t n) { return (unsigned)((n + TPB - 1) / TPB); }
+
+}  // namespace
+
+hipError_t launch_geometry(dolinc_ctx_s* c, hipStream_t s) {
+  DevMesh& m = c->m;
+  hipLaunchKernelGGL(k_face_geom, dim3(nblk(c->n_faces)), dim3(TPB), 0, s, c->n_faces, c->dim, m.fptr, m.fnodes,
+                     m.nodes, m.S, m.xf, m.fanc);
+  hipLaunchKernelGGL(k_cell_geom, dim3(nblk(c->n_cells)), dim3(TPB), 0, s, c->n_cells, c->dim, c->part_cells,
+                     m.part_ptr, m.ent_face, m.slot_ptr, m.slots, m.fptr, m.fnodes, m.nodes, m.shift, m.S, m.xf,
+                     m.fanc, m.V, m.xc, c->w.flag);
+  hipLaunchKernelGGL(k_face_scalars, dim3(nblk(c->n_faces)), dim3(TPB), 0, s, c->n_faces, c->dim, m.face_own,
+                     m.face_nei, m.xc, m.shift, m.xf, m.dvec, m.omega, m.g, c->w.flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_entry_fill(dolinc_ctx_s* c, hipStream_t s) {
+  DevMesh& m = c->m;
+  const int sch = c->params.scheme;
+  const int dcs = dc_stride(sch);
+  if (c->w.precision == DOLINC_FP64) {
+    hipLaunchKernelGGL(k_entry_fill<double>, dim3(nblk(c->n_entries)), dim3(TPB), 0, s, c->n_entries, c->dim, sch,
+                       dcs, m.ent_face, m.S, m.omega, m.g, m.dvec, (double*)c->w.sw, (double*)c->w.dc);
+    hipLaunchKernelGGL(k_recip<double>, dim3(nblk(c->n_cells)), dim3(TPB), 0, s, c->n_cells, m.V,
+                       (double*)c->w.rV);
+  } else {
+    hipLaunchKernelGGL(k_entry_fill<float>, dim3(nblk(c->n_entries)), dim3(TPB), 0, s, c->n_entries, c->dim, sch,
+                       dcs, m.ent_face, m.S, m.omega, m.g, m.dvec, (float*)c->w.sw, (float*)c->w.dc);
+    hipLaunchKernelGGL(k_recip<float>, dim3(nblk(c->n_cells)), dim3(TPB), 0, s, c->n_cells, m.V,
+                       (float*)c->w.rV);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace dolinc

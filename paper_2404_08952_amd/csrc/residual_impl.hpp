@@ -1,0 +1,478 @@
+// Residual kernels, templated on the working type T (double or float).
+//
+// One residual evaluation (one Runge-Kutta stage) runs:
+//   k_grad1  Gauss-linear gradient of U (Sec. 2.3), difference form
+//            G1_P = V_P^-1 sum_f sigma S_f (phi_f - phi_P),
+//            phi_f - phi_P = (1 - omega)(phi_N - phi_P) on the owner side and
+//            omega (phi_P - phi_N) on the neighbour side.
+//   k_grad2  the same operator on G1, symmetrised (USR5 only: its
+//            differential phi^(2) = 4 d.G2.d sees only the symmetric part).
+//   k_flux   per partition: every face entry evaluates the DOLINC
+//            differentials (phi^(1) = 2 d.G1, phi^(2) = 4 d.G2.d), the
+//            reconstructed left/right states in the DOLINC representation
+//            (eq:USR3 / eq:CSR4 form: weight + explicit correction), the
+//            optional blend with a Van Leer limited state, and the Riemann
+//            flux; fluxes land in LDS.  After a barrier every cell of the
+//            partition sums its faces' fluxes in a fixed order (no atomics)
+//            and applies the update epilogue.
+// Faces on a partition seam are evaluated by both partitions with identical
+// operands and code, so both sides see bitwise identical fluxes and the
+// scheme stays conservative to round-off.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "internal.hpp"
+
+namespace dolinc {
+
+constexpr int KTPB = 256;
+
+template <class T>
+struct KArgs {
+  int64_t nc;
+  int np, B, per_xcd, n_cell_blocks, cell_per_xcd;
+  const int32_t* part_ptr;
+  const int2* ent_pn;
+  const int32_t* slot_ptr;
+  const uint16_t* slots;
+  const T* sw;
+  const T* dc;
+  const T* rV;
+  const T* U;
+  const T* G1;
+  const T* G2;
+  const float* theta;
+  const T* Un;
+  T* out;
+  T alpha, beta, dt;
+  int mode;
+  T gamma;
+  T adv[3];
+  T bdir[3];
+  int use_ref;
+  T uref[5];
+  const int32_t* face_ent;
+  int64_t nf;
+  T* eUL;
+  T* eUR;
+  T* eF;
+};
+
+// Partitions are handed out so that each XCD (workgroups go round-robin
+// over the 8 XCDs) walks a contiguous range of partitions: neighbouring
+// partitions share seam faces and gathered cells through that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int b, int per_xcd, int n) {
+  const int p = (b & 7) * per_xcd + (b >> 3);
+  return p < n ? p : -1;
+}
+
+template <int PK, int D>
+struct NVars {
+  static constexpr int value = PK >= 2 ? D + 2 : 1;
+};
+
+template <int SCH>
+struct SchemeInfo {
+  static constexpr int ORD = SCH <= 2 ? 0 : (SCH <= 4 ? 1 : 2);
+  static constexpr int NL = SCH <= 2 ? 1 : (SCH == 3 ? 2 : (SCH == 4 ? 3 : 4));
+  static constexpr int NR = SCH <= 2 ? 1 : (SCH == 3 ? 2 : (SCH == 4 ? 0 : 4));
+  static constexpr int DCS = (3 + NL + NR + 3) & ~3;
+};
+
+template <class T>
+__device__ __forceinline__ T vanleer_inc(T s, T delta) {
+  const T prod = s * delta;
+  return prod > T(0) ? T(2) * prod / (s + delta) : T(0);
+}
+
+// ---------------------------------------------------------------- Euler fluxes
+template <class T, int D>
+__device__ __forceinline__ void euler_prim(const T* U, T gamma, T& r, T* v, T& E, T& p) {
+  r = U[0];
+  T ke = T(0);
+  for (int a = 0; a < D; ++a) {
+    v[a] = U[1 + a] / r;
+    ke += v[a] * U[1 + a];
+  }
+  E = U[D + 1];
+  p = (gamma - T(1)) * (E - T(0.5) * ke);
+}
+
+template <class T, int D>
+__device__ __forceinline__ void euler_phys(const T* U, T r, const T* v, T E, T p, const T* n, T* F) {
+  T un = T(0);
+  for (int a = 0; a < D; ++a) un += v[a] * n[a];
+  F[0] = r * un;
+  for (int a = 0; a < D; ++a) F[1 + a] = U[1 + a] * un + p * n[a];
+  F[D + 1] = (E + p) * un;
+}
+
+template <class T, int D>
+__device__ __forceinline__ void flux_rusanov(const T* UL, const T* UR, const T* S, T gamma, T* F) {
+  T area2 = T(0);
+  for (int a = 0; a < D; ++a) area2 += S[a] * S[a];
+  const T area = sqrt(area2);
+  T rL, vL[D], EL, pL, rR, vR[D], ER, pR;
+  euler_prim<T, D>(UL, gamma, rL, vL, EL, pL);
+  euler_prim<T, D>(UR, gamma, rR, vR, ER, pR);
+  T qL = T(0), qR = T(0);
+  for (int a = 0; a < D; ++a) {
+    qL += vL[a] * S[a];
+    qR += vR[a] * S[a];
+  }
+  qL /= area;
+  qR /= area;
+  const T cL = sqrt(gamma * pL / rL), cR = sqrt(gamma * pR / rR);
+  const T lam = fmax(fabs(qL) + cL, fabs(qR) + cR);
+  T FL[D + 2], FR[D + 2];
+  euler_phys<T, D>(UL, rL, vL, EL, pL, S, FL);
+  euler_phys<T, D>(UR, rR, vR, ER, pR, S, FR);
+  const T diss = T(0.5) * lam * area;
+  for (int k = 0; k < D + 2; ++k) F[k] = T(0.5) * (FL[k] + FR[k]) - diss * (UR[k] - UL[k]);
+}
+
+template <class T, int D>
+__device__ __forceinline__ void flux_hllc(const T* UL, const T* UR, const T* S, T gamma, T* F) {
+  T area2 = T(0);
+  for (int a = 0; a < D; ++a) area2 += S[a] * S[a];
+  const T area = sqrt(area2);
+  T n[D];
+  for (int a = 0; a < D; ++a) n[a] = S[a] / area;
+  T rL, vL[D], EL, pL, rR, vR[D], ER, pR;
+  euler_prim<T, D>(UL, gamma, rL, vL, EL, pL);
+  euler_prim<T, D>(UR, gamma, rR, vR, ER, pR);
+  T qL = T(0), qR = T(0);
+  for (int a = 0; a < D; ++a) {
+    qL += vL[a] * n[a];
+    qR += vR[a] * n[a];
+  }
+  const T cL = sqrt(gamma * pL / rL), cR = sqrt(gamma * pR / rR);
+  const T SL = fmin(qL - cL, qR - cR);
+  const T SR = fmax(qL + cL, qR + cR);
+  const T Ss = (pR - pL + rL * qL * (SL - qL) - rR * qR * (SR - qR)) / (rL * (SL - qL) - rR * (SR - qR));
+  // choose the side: the flux is F_K (+ S_K (U*_K - U_K) inside the fan)
+  const bool left = SL >= T(0) || Ss >= T(0);
+  const T* UK = left ? UL : UR;
+  const T rK = left ? rL : rR, EK = left ? EL : ER, pK = left ? pL : pR, qK = left ? qL : qR;
+  const T SK = left ? SL : SR;
+  T vK[D];
+  for (int a = 0; a < D; ++a) vK[a] = left ? vL[a] : vR[a];
+  T FK[D + 2];
+  euler_phys<T, D>(UK, rK, vK, EK, pK, n, FK);
+  const bool star = left ? (SL < T(0)) : (SR > T(0));
+  if (star) {
+    const T fac = rK * (SK - qK) / (SK - Ss);
+    T Us[D + 2];
+    Us[0] = fac;
+    for (int a = 0; a < D; ++a) Us[1 + a] = fac * (vK[a] + (Ss - qK) * n[a]);
+    Us[D + 1] = fac * (EK / rK + (Ss - qK) * (Ss + pK / (rK * (SK - qK))));
+    for (int k = 0; k < D + 2; ++k) FK[k] += SK * (Us[k] - UK[k]);
+  }
+  for (int k = 0; k < D + 2; ++k) F[k] = FK[k] * area;
+}
+
+// ---------------------------------------------------------------- face evaluation
+// Loads one face entry, reconstructs (U_L, U_R) and returns the
+// face-integrated flux F.S (owner -> neighbour).
+template <class T, int D, int PK, int SCH, bool BLEND>
+__device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T* UR, T* F) {
+  constexpr int NV = NVars<PK, D>::value;
+  constexpr int ORD = SchemeInfo<SCH>::ORD;
+  constexpr int DCS = SchemeInfo<SCH>::DCS;
+  constexpr int NS2 = D * (D + 1) / 2;
+  const int2 pn = a.ent_pn[e];
+  const int64_t P = pn.x, N = pn.y;
+  const T* swp = a.sw + 4 * e;
+  T S[3] = {swp[0], swp[1], swp[2]};
+  const T om = swp[3];
+  const T* dcp = a.dc + (int64_t)DCS * e;
+  T dc[DCS];
+#pragma unroll
+  for (int k = 0; k < DCS; ++k) dc[k] = dcp[k];
+  T uP[NV], uN[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    uP[v] = a.U[P * NV + v];
+    uN[v] = a.U[N * NV + v];
+  }
+  T gP[NV], gN[NV], hP[NV], hN[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) gP[v] = gN[v] = hP[v] = hN[v] = T(0);
+  if constexpr (ORD >= 1 || BLEND) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const T* gp = a.G1 + (P * NV + v) * D;
+      const T* gn = a.G1 + (N * NV + v) * D;
+#pragma unroll
+      for (int x = 0; x < D; ++x) {
+        gP[v] += dc[x] * gp[x];
+        gN[v] += dc[x] * gn[x];
+      }
+    }
+  }
+  if constexpr (ORD >= 2) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const T* hp = a.G2 + (P * NV + v) * NS2;
+      const T* hn = a.G2 + (N * NV + v) * NS2;
+      T sp = T(0), sn = T(0);
+#pragma unroll
+      for (int x = 0; x < D; ++x) {
+        sp += hp[x] * dc[x] * dc[x];
+        sn += hn[x] * dc[x] * dc[x];
+      }
+      if constexpr (D == 3) {
+        const T dxy = T(2) * dc[0] * dc[1], dxz = T(2) * dc[0] * dc[2], dyz = T(2) * dc[1] * dc[2];
+        sp += hp[3] * dxy + hp[4] * dxz + hp[5] * dyz;
+        sn += hn[3] * dxy + hn[4] * dxz + hn[5] * dyz;
+      } else {
+        const T dxy = T(2) * dc[0] * dc[1];
+        sp += hp[2] * dxy;
+        sn += hn[2] * dxy;
+      }
+      hP[v] = sp;
+      hN[v] = sn;
+    }
+  }
+  // reconstruction in the DOLINC representation (coefficients from precompute)
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    if constexpr (SCH <= 2) {
+      UL[v] = uN[v] + dc[3] * (uP[v] - uN[v]);
+      UR[v] = uP[v] + dc[4] * (uN[v] - uP[v]);
+    } else if constexpr (SCH == 3) {
+      UL[v] = uN[v] + dc[3] * (uP[v] - uN[v]) + dc[4] * gP[v];
+      UR[v] = uP[v] + dc[5] * (uN[v] - uP[v]) + dc[6] * gN[v];
+    } else if constexpr (SCH == 4) {
+      UL[v] = uN[v] + dc[3] * (uP[v] - uN[v]) + dc[4] * gP[v] + dc[5] * gN[v];
+      UR[v] = UL[v];
+    } else {
+      UL[v] = uN[v] + dc[3] * (uP[v] - uN[v]) + dc[4] * gP[v] + dc[5] * gN[v] + dc[6] * hP[v];
+      UR[v] = uP[v] + dc[7] * (uN[v] - uP[v]) + dc[8] * gN[v] + dc[9] * gP[v] + dc[10] * hN[v];
+    }
+  }
+  if constexpr (BLEND) {
+    const T tf = (T)fminf(a.theta[P], a.theta[N]);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const T dL = uN[v] - uP[v];
+      const T VL = uP[v] + (T(1) - om) * vanleer_inc(T(2) * gP[v] - dL, dL);
+      const T dR = uP[v] - uN[v];
+      const T VR = uN[v] + om * vanleer_inc(T(-2) * gN[v] - dR, dR);
+      UL[v] = tf * UL[v] + (T(1) - tf) * VL;
+      UR[v] = tf * UR[v] + (T(1) - tf) * VR;
+    }
+  }
+  if constexpr (PK == 0) {
+    T an = T(0);
+#pragma unroll
+    for (int x = 0; x < D; ++x) an += a.adv[x] * S[x];
+    F[0] = an >= T(0) ? an * UL[0] : an * UR[0];
+  } else if constexpr (PK == 1) {
+    T s = T(0);
+#pragma unroll
+    for (int x = 0; x < D; ++x) s += a.bdir[x] * S[x];
+    const T uL = UL[0], uR = UR[0];
+    const T fL = T(0.5) * uL * uL * s, fR = T(0.5) * uR * uR * s;
+    const T lo = fmin(uL, uR), hi = fmax(uL, uR);
+    const bool has0 = lo <= T(0) && hi >= T(0);
+    T fmn = fmin(fL, fR), fmx = fmax(fL, fR);
+    if (has0) {
+      fmn = fmin(fmn, T(0));
+      fmx = fmax(fmx, T(0));
+    }
+    F[0] = uL <= uR ? fmn : fmx;
+  } else {
+    // positivity: a side with rho <= 0 or p <= 0 falls back to its cell value
+    {
+      T r, vv[D], E, p;
+      euler_prim<T, D>(UL, a.gamma, r, vv, E, p);
+      if (!(r > T(0) && p > T(0)))
+        for (int v = 0; v < NV; ++v) UL[v] = uP[v];
+      euler_prim<T, D>(UR, a.gamma, r, vv, E, p);
+      if (!(r > T(0) && p > T(0)))
+        for (int v = 0; v < NV; ++v) UR[v] = uN[v];
+    }
+    if constexpr (PK == 2)
+      flux_rusanov<T, D>(UL, UR, S, a.gamma, F);
+    else
+      flux_hllc<T, D>(UL, UR, S, a.gamma, F);
+    if (a.use_ref) {
+      T r, vv[D], E, p, Fr[D + 2];
+      euler_prim<T, D>(a.uref, a.gamma, r, vv, E, p);
+      euler_phys<T, D>(a.uref, r, vv, E, p, S, Fr);
+#pragma unroll
+      for (int k = 0; k < NV; ++k) F[k] -= Fr[k];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- kernels
+template <class T, int D, int PK, int SCH, bool BLEND>
+__global__ __launch_bounds__(KTPB) void k_flux(KArgs<T> a) {
+  constexpr int NV = NVars<PK, D>::value;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* Fs = reinterpret_cast<T*>(smem_raw);
+  const int p = xcd_remap(blockIdx.x, a.per_xcd, a.np);
+  if (p < 0) return;
+  const int e0 = a.part_ptr[p], e1 = a.part_ptr[p + 1];
+  for (int e = e0 + (int)threadIdx.x; e < e1; e += KTPB) {
+    T UL[NV], UR[NV], F[NV];
+    eval_face<T, D, PK, SCH, BLEND>(a, e, UL, UR, F);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Fs[(e - e0) * NV + v] = F[v];
+  }
+  __syncthreads();
+  const int64_t c0 = (int64_t)p * a.B;
+  const int64_t c1 = c0 + a.B < a.nc ? c0 + a.B : a.nc;
+  for (int64_t c = c0 + threadIdx.x; c < c1; c += KTPB) {
+    const int s0 = a.slot_ptr[c], s1 = a.slot_ptr[c + 1];
+    T sum[NV], comp[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sum[v] = comp[v] = T(0);
+    for (int s = s0; s < s1; ++s) {
+      const uint16_t sl = a.slots[s];
+      const T* Fp = Fs + (sl & 0x7fff) * NV;
+      const bool nb = (sl >> 15) != 0;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const T x = nb ? -Fp[v] : Fp[v];
+        if constexpr (sizeof(T) == 4) {  // Neumaier compensated sum
+          const T t = sum[v] + x;
+          comp[v] += fabs(sum[v]) >= fabs(x) ? (sum[v] - t) + x : (x - t) + sum[v];
+          sum[v] = t;
+        } else {
+          sum[v] += x;
+        }
+      }
+    }
+    const T rv = a.rV[c];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const T R = -(sum[v] + comp[v]) * rv;
+      const int64_t i = c * NV + v;
+      if (a.mode == 0)
+        a.out[i] = R;
+      else
+        a.out[i] = a.alpha * a.Un[i] + a.beta * (a.U[i] + a.dt * R);
+    }
+  }
+}
+
+template <class T, int D, int PK, int SCH, bool BLEND>
+__global__ __launch_bounds__(KTPB) void k_face_export(KArgs<T> a) {
+  constexpr int NV = NVars<PK, D>::value;
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= a.nf) return;
+  T UL[NV], UR[NV], F[NV];
+  eval_face<T, D, PK, SCH, BLEND>(a, a.face_ent[f], UL, UR, F);
+  for (int v = 0; v < NV; ++v) {
+    a.eUL[f * NV + v] = UL[v];
+    a.eUR[f * NV + v] = UR[v];
+    if (a.eF) a.eF[f * NV + v] = F[v];
+  }
+}
+
+// Cell-centric Gauss-linear gradient of phi [nc][NQ] -> out [nc][NQ][D].
+// SYM: NQ = NV*D input components (a gradient) and the output is the
+// symmetrised second derivative [nc][NV][D(D+1)/2].
+template <class T, int D, int NQ, bool SYM>
+__global__ __launch_bounds__(KTPB) void k_grad(KArgs<T> a, const T* __restrict__ phi, T* __restrict__ out) {
+  const int b = xcd_remap(blockIdx.x, a.cell_per_xcd, a.n_cell_blocks);
+  if (b < 0) return;
+  const int64_t c = (int64_t)b * KTPB + threadIdx.x;
+  if (c >= a.nc) return;
+  const int e0 = a.part_ptr[c / a.B];
+  const int s0 = a.slot_ptr[c], s1 = a.slot_ptr[c + 1];
+  T q[NQ];
+#pragma unroll
+  for (int k = 0; k < NQ; ++k) q[k] = phi[c * NQ + k];
+  T acc[NQ][D];
+#pragma unroll
+  for (int k = 0; k < NQ; ++k)
+#pragma unroll
+    for (int x = 0; x < D; ++x) acc[k][x] = T(0);
+  for (int s = s0; s < s1; ++s) {
+    const uint16_t sl = a.slots[s];
+    const int64_t e = e0 + (sl & 0x7fff);
+    const bool nb = (sl >> 15) != 0;
+    const int2 pn = a.ent_pn[e];
+    const int64_t o = nb ? pn.x : pn.y;
+    const T* swp = a.sw + 4 * e;
+    const T om = swp[3];
+    const T wgt = nb ? -om : T(1) - om;
+    T Sw[D];
+#pragma unroll
+    for (int x = 0; x < D; ++x) Sw[x] = wgt * swp[x];
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+      const T dq = phi[o * NQ + k] - q[k];
+#pragma unroll
+      for (int x = 0; x < D; ++x) acc[k][x] += dq * Sw[x];
+    }
+  }
+  const T rv = a.rV[c];
+  if constexpr (!SYM) {
+#pragma unroll
+    for (int k = 0; k < NQ; ++k)
+#pragma unroll
+      for (int x = 0; x < D; ++x) out[(c * NQ + k) * D + x] = acc[k][x] * rv;
+  } else {
+    constexpr int NV = NQ / D;
+    constexpr int NS2 = D * (D + 1) / 2;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      T* o2 = out + (c * NV + v) * NS2;
+      // acc[v*D + i][j] = d/dx_j of G1_i
+#pragma unroll
+      for (int i = 0; i < D; ++i) o2[i] = acc[v * D + i][i] * rv;
+      if constexpr (D == 3) {
+        o2[3] = T(0.5) * (acc[v * D + 0][1] + acc[v * D + 1][0]) * rv;
+        o2[4] = T(0.5) * (acc[v * D + 0][2] + acc[v * D + 2][0]) * rv;
+        o2[5] = T(0.5) * (acc[v * D + 1][2] + acc[v * D + 2][1]) * rv;
+      } else {
+        o2[2] = T(0.5) * (acc[v * D + 0][1] + acc[v * D + 1][0]) * rv;
+      }
+    }
+  }
+}
+
+// Classical sensor: beta = |s - Delta| / (|s| + |Delta| + eps) on every face
+// in the frame where the cell is upwind; s = phi_0^(1) - Delta.
+template <class T, int D, int NV>
+__global__ __launch_bounds__(KTPB) void k_theta(KArgs<T> a, int dcs, float* __restrict__ theta) {
+  const int b = xcd_remap(blockIdx.x, a.cell_per_xcd, a.n_cell_blocks);
+  if (b < 0) return;
+  const int64_t c = (int64_t)b * KTPB + threadIdx.x;
+  if (c >= a.nc) return;
+  const int e0 = a.part_ptr[c / a.B];
+  const int s0 = a.slot_ptr[c], s1 = a.slot_ptr[c + 1];
+  T beta = T(0);
+  for (int s = s0; s < s1; ++s) {
+    const uint16_t sl = a.slots[s];
+    const int64_t e = e0 + (sl & 0x7fff);
+    const bool nb = (sl >> 15) != 0;
+    const int2 pn = a.ent_pn[e];
+    const int64_t o = nb ? pn.x : pn.y;
+    const T* dcp = a.dc + (int64_t)dcs * e;
+    const T sg = nb ? T(-1) : T(1);
+#pragma unroll
+    for (int q = 0; q < (NV == 1 ? 1 : 2); ++q) {
+      const int v = q == 0 ? 0 : NV - 1;
+      T dot = T(0);
+#pragma unroll
+      for (int x = 0; x < D; ++x) dot += dcp[x] * a.G1[(c * NV + v) * D + x];
+      const T phi0 = a.U[c * NV + v], phi1 = a.U[o * NV + v];
+      const T delta = phi1 - phi0;
+      const T sdiff = T(2) * sg * dot - delta;
+      const T eps = T(1e-8) * (fabs(phi0) + fabs(phi1)) + T(1e-30);
+      const T bf = fabs(sdiff - delta) / (fabs(sdiff) + fabs(delta) + eps);
+      beta = fmax(beta, bf);
+    }
+  }
+  T th = (T(0.9) - beta) / T(0.3);
+  th = th < T(0) ? T(0) : (th > T(1) ? T(1) : th);
+  theta[c] = (float)th;
+}
+
+}  // namespace dolinc

@@ -1,0 +1,302 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+FP64 path: element-wise agreement to rounding (rtol 1e-10 with an absolute
+floor of 1e-12 times the field scale); the two sides evaluate the same
+mathematics in different algebraic forms and summation orders.
+FP32-mixed path: relative L2 error per stage and per variable <= 1e-5
+against the FP64 oracle evaluated on the same (FP32-rounded) input.
+"""
+import numpy as np
+import pytest
+
+from oracle import geometry as OG
+from oracle import limiter as OL
+from oracle import scheme as OS
+from oracle import solver as SV
+from synth import configs, fields
+from synth import mesh as M
+
+from .helpers import oracle_params, rel_l2, small_meshes, submesh
+
+pytestmark = pytest.mark.gpu
+
+MESHES = small_meshes()
+
+
+def _solver(mesh, **kw):
+    from paper_2404_08952_amd import Solver
+    return Solver(mesh, **kw)
+
+
+def _close(gpu, ref, rtol=1e-10, afloor=1e-12):
+    ref = np.asarray(ref)
+    scale = max(np.abs(ref).max(), 1e-300)
+    np.testing.assert_allclose(np.asarray(gpu), ref, rtol=rtol, atol=afloor * scale)
+
+
+def _euler_state(n, rng, amp=0.2):
+    rho = 1.0 + amp * (rng.random(n) - 0.5)
+    vel = 0.3 * rng.normal(size=(n, 3))
+    p = 1.0 + amp * (rng.random(n) - 0.5)
+    return fields.prim_to_cons(rho, vel, p)
+
+
+@pytest.fixture(scope="module")
+def geos():
+    return {k: OG.geometry(m) for k, m in MESHES.items()}
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+def test_geometry_parity(name, geos):
+    mesh, geo = MESHES[name], geos[name]
+    pde = "euler" if mesh.dim == 3 else "advection"
+    s = _solver(mesh, pde=pde, scheme="USR3", flux="rusanov" if pde == "euler" else "upwind")
+    g = {k: v.cpu().numpy() for k, v in s.geometry().items()}
+    _close(g["V"][s.perm], geo.V)
+    _close(g["xc"][s.perm], geo.xc)
+    _close(g["S"], geo.S)
+    _close(g["xf"], geo.xf)
+    _close(g["omega"], geo.omega)
+    _close(g["g"], geo.g)
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+def test_gradient_parity(name, geos):
+    mesh, geo = MESHES[name], geos[name]
+    rng = np.random.default_rng(1)
+    if mesh.dim == 3:
+        U = _euler_state(mesh.n_cells, rng)
+        s = _solver(mesh, pde="euler", scheme="USR5", flux="hllc")
+    else:
+        U = rng.normal(size=(mesh.n_cells, 1))
+        s = _solver(mesh, pde="advection", scheme="USR5")
+    G1, G2 = s.gradients(s.to_internal(U), second=True)
+    r1 = OS.gauss_linear(mesh, geo, U)
+    r2 = OS.gauss_linear(mesh, geo, r1)
+    r2s = 0.5 * (r2 + np.swapaxes(r2, -1, -2))
+    d = mesh.dim
+    iu = [(a, a) for a in range(d)] + ([(0, 1), (0, 2), (1, 2)] if d == 3 else [(0, 1)])
+    r2p = np.stack([r2s[..., a, b] for (a, b) in iu], -1)
+    _close(G1.cpu().numpy()[s.perm], r1)
+    _close(G2.cpu().numpy()[s.perm], r2p)
+
+
+@pytest.mark.parametrize("scheme", ["FOU", "CD2", "USR3", "CSR4", "USR5"])
+@pytest.mark.parametrize("name", ["tri2d", "mixed2d", "mixed3d"])
+def test_face_state_parity(name, scheme, geos):
+    mesh, geo = MESHES[name], geos[name]
+    rng = np.random.default_rng(2)
+    U = rng.normal(size=(mesh.n_cells, 1))
+    s = _solver(mesh, pde="advection", scheme=scheme)
+    UL, UR, F = s.face_states(s.to_internal(U))
+    rL, rR, _ = OS.face_states(mesh, geo, U, scheme)
+    _close(UL.cpu().numpy(), rL)
+    _close(UR.cpu().numpy(), rR)
+
+
+RES_CASES = [
+    ("tri2d", dict(pde="advection", scheme="USR3")),
+    ("tri2d", dict(pde="advection", scheme="CSR4")),
+    ("tri2d", dict(pde="advection", scheme="USR5")),
+    ("mixed2d", dict(pde="advection", scheme="FOU")),
+    ("mixed2d", dict(pde="burgers", scheme="USR3")),
+    ("mixed2d", dict(pde="burgers", scheme="CSR4")),
+    ("mixed2d", dict(pde="burgers", scheme="USR5")),
+    ("hex3d", dict(pde="advection", scheme="USR5")),
+    ("tet3d", dict(pde="euler", scheme="CSR4", flux="rusanov")),
+    ("tet3d", dict(pde="euler", scheme="USR3", flux="hllc")),
+    ("hex3d", dict(pde="euler", scheme="USR5", flux="hllc")),
+    ("hex3d", dict(pde="euler", scheme="CD2", flux="rusanov")),
+    ("mixed3d", dict(pde="euler", scheme="USR3", flux="rusanov")),
+    ("mixed3d", dict(pde="euler", scheme="USR5", flux="hllc")),
+]
+
+
+def _state_for(mesh, kw, rng):
+    if kw["pde"] == "euler":
+        return _euler_state(mesh.n_cells, rng)
+    if kw["pde"] == "burgers":
+        return 0.5 + 0.3 * rng.normal(size=(mesh.n_cells, 1))
+    return rng.normal(size=(mesh.n_cells, 1))
+
+
+@pytest.mark.parametrize("name,kw", RES_CASES, ids=[f"{n}-{k['pde']}-{k['scheme']}" for n, k in RES_CASES])
+def test_residual_parity(name, kw, geos):
+    mesh, geo = MESHES[name], geos[name]
+    rng = np.random.default_rng(3)
+    U = _state_for(mesh, kw, rng)
+    s = _solver(mesh, **kw)
+    R = s.to_external(s.residual(s.to_internal(U)))
+    ref = SV.residual(mesh, geo, U, oracle_params(kw))
+    for v in range(ref.shape[1]):
+        _close(R[:, v], ref[:, v])
+    # exported face fluxes against the oracle's face fluxes
+    _UL, _UR, F = s.face_states(s.to_internal(U))
+    _close(F.cpu().numpy(), SV.face_flux(mesh, geo, U, oracle_params(kw)))
+
+
+@pytest.mark.parametrize("name,kw", [RES_CASES[1], RES_CASES[5], RES_CASES[10], RES_CASES[8]],
+                         ids=["adv-CSR4", "burgers-CSR4", "euler-USR5-hllc", "euler-CSR4-rusanov"])
+def test_rk_step_parity(name, kw, geos):
+    mesh, geo = MESHES[name], geos[name]
+    rng = np.random.default_rng(4)
+    U = _state_for(mesh, kw, rng)
+    s = _solver(mesh, **kw)
+    Ud = s.to_internal(U)
+    dt = 1e-3
+    ref = U.copy()
+    for _ in range(3):
+        s.rk_step(Ud, dt)
+        ref = SV.rk_step(mesh, geo, ref, dt, oracle_params(kw))
+    _close(s.to_external(Ud), ref, rtol=1e-10, afloor=1e-12)
+
+
+@pytest.mark.parametrize("name,kw", [RES_CASES[0], RES_CASES[4], RES_CASES[5], RES_CASES[8], RES_CASES[10]],
+                         ids=["adv-USR3", "burgers-USR3", "burgers-CSR4", "euler-CSR4", "euler-USR5"])
+def test_fp32_stage_error(name, kw, geos):
+    """FP32 bulk with FP64-derived coefficients: per-variable relative L2 of
+    R32 against the FP64 oracle on the same FP32-rounded input <= 1e-5."""
+    mesh, geo = MESHES[name], geos[name]
+    rng = np.random.default_rng(5)
+    U = _state_for(mesh, kw, rng).astype(np.float32).astype(np.float64)
+    s = _solver(mesh, precision="fp32", **kw)
+    R32 = s.to_external(s.residual(s.to_internal(U)))
+    ref = SV.residual(mesh, geo, U, oracle_params(kw))
+    for v in range(ref.shape[1]):
+        assert rel_l2(R32[:, v], ref[:, v]) <= 1e-5, (v, rel_l2(R32[:, v], ref[:, v]))
+
+
+def test_conservation_determinism_and_partitions(geos):
+    mesh, geo = MESHES["mixed3d"], geos["mixed3d"]
+    rng = np.random.default_rng(6)
+    U = _euler_state(mesh.n_cells, rng)
+    kw = dict(pde="euler", scheme="USR5", flux="hllc")
+    s = _solver(mesh, **kw)
+    R1 = s.residual(s.to_internal(U)).cpu().numpy()
+    R2 = s.residual(s.to_internal(U)).cpu().numpy()
+    assert np.array_equal(R1, R2)
+    Ud = s.to_internal(U)
+    tot0 = s.diagnostics(Ud)[:5]
+    for _ in range(5):
+        s.rk_step(Ud, 1e-3)
+    tot1 = s.diagnostics(Ud)[:5]
+    scale = (geo.V[:, None] * np.abs(U)).sum(0)
+    assert np.all(np.abs(tot1 - tot0) <= 50 * np.finfo(float).eps * scale)
+    ref = s.to_external(s.residual(s.to_internal(U)))
+    for renumber in (0, 1, 2):
+        for pc in (32, 64, 1024):
+            t = _solver(mesh, renumber=renumber, part_cells=pc, **kw)
+            R = t.to_external(t.residual(t.to_internal(U)))
+            _close(R, ref, rtol=1e-12, afloor=1e-13)
+
+
+def test_classical_blend_parity(geos):
+    mesh, geo = MESHES["mixed3d"], geos["mixed3d"]
+    rng = np.random.default_rng(7)
+    U = _euler_state(mesh.n_cells, rng, amp=0.6)
+    kw = dict(pde="euler", scheme="USR3", flux="rusanov")
+    s = _solver(mesh, blend="classical", **kw)
+    th = s.classical_theta(s.to_internal(U)).cpu().numpy()[s.perm]
+    G1 = OS.gauss_linear(mesh, geo, U)
+    ref_th, _beta = OL.classical_theta(mesh, geo, U, G1)
+    np.testing.assert_allclose(th, ref_th, atol=1e-6)
+    R = s.to_external(s.residual(s.to_internal(U)))
+    ref = SV.residual(mesh, geo, U, oracle_params(kw), theta=ref_th.astype(np.float32).astype(np.float64))
+    _close(R, ref, rtol=1e-8, afloor=1e-10)
+    # explicit theta (the learned-indicator path) with theta from the host
+    t = _solver(mesh, blend="theta", **kw)
+    import torch
+    th_in = rng.random(mesh.n_cells).astype(np.float32)
+    tin = np.empty_like(th_in)
+    tin[t.perm] = th_in
+    t.set_theta(torch.from_numpy(tin).cuda())
+    R = t.to_external(t.residual(t.to_internal(U)))
+    ref = SV.residual(mesh, geo, U, oracle_params(kw), theta=th_in.astype(np.float64))
+    _close(R, ref)
+
+
+def test_tiny_meshes_and_errors():
+    from paper_2404_08952_amd import DolincError
+    for mesh in (M.periodic_3d(2, kinds=M.KUHN6), M.periodic_2d(2, 2, split=1.0), M.periodic_3d(2)):
+        geo = OG.geometry(mesh)
+        kw = dict(pde="euler", scheme="USR5", flux="hllc") if mesh.dim == 3 else dict(pde="advection",
+                                                                                      scheme="USR3")
+        U = _state_for(mesh, kw, np.random.default_rng(8))
+        s = _solver(mesh, **kw)
+        _close(s.to_external(s.residual(s.to_internal(U))), SV.residual(mesh, geo, U, oracle_params(kw)))
+    mesh = MESHES["tri2d"]
+    with pytest.raises(DolincError) as e:
+        _solver(mesh, pde="euler", scheme="USR3", flux="rusanov")
+    assert e.value.status == 6
+    s = _solver(mesh, pde="advection", scheme="USR3")
+    U = s.to_internal(np.zeros((mesh.n_cells, 1)))
+    with pytest.raises(DolincError):
+        s.rk_step(U, -1.0)
+    s.close()
+    import ctypes
+    st = s.lib.dolinc_residual(ctypes.c_void_p(12345), None, None, None)
+    assert st == 5
+
+
+def test_c1_end_to_end_against_oracle_and_exact():
+    """Config-1 workload: USR3 + upwind, SSP-RK3 to t = 0.1 on jittered
+    triangles; GPU and oracle final states agree; error vs the translated
+    wave is reported (about first order on jittered meshes)."""
+    case = configs.advection_2d()
+    mesh = case.mesh
+    geo = OG.geometry(mesh)
+    s = _solver(mesh, **case.params)
+    Ud = s.to_internal(case.U0)
+    s.advance(Ud, case.dt, case.steps)
+    ref = case.U0.copy()
+    for _ in range(case.steps):
+        ref = SV.rk_step(mesh, geo, ref, case.dt, case.params)
+    _close(s.to_external(Ud), ref, rtol=1e-10, afloor=1e-12)
+    exact = fields.cell_averages(mesh, case.exact(case.dt * case.steps), n_pts=5)
+    _L1, L2 = SV.error_norms(geo, s.to_external(Ud), exact)
+    assert L2[0] < 2e-2
+
+
+def test_design_order_on_uniform_line():
+    """USR3 / CSR4 advection of a sine on a uniform periodic line through the
+    GPU path with SSP-RK3 at a small CFL: observed orders 3 and 4."""
+    for scheme, order in (("USR3", 3.0), ("CSR4", 4.0)):
+        errs = []
+        for n in (32, 64):
+            mesh = configs.line_1d(n, dim=2)
+            U0 = fields.cell_averages(mesh, fields.sine1d(), n_pts=6)
+            s = _solver(mesh, pde="advection", scheme=scheme, adv_vel=(1.0, 0.0, 0.0))
+            steps = 16 * n
+            Ud = s.to_internal(U0)
+            s.advance(Ud, 0.25 / steps, steps)
+            ex = fields.cell_averages(mesh, fields.sine1d(t=0.25), n_pts=6)
+            errs.append(np.sqrt(np.mean((s.to_external(Ud) - ex) ** 2)))
+        assert abs(np.log2(errs[0] / errs[1]) - order) < 0.15, (scheme, errs)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_full_size_vortex_sampled(precision):
+    """The 3-D Euler vortex workload at full size (64^3 x 6 tetrahedra, CSR4,
+    Rusanov) in the benchmark's launch configuration: sampled cells against
+    the oracle on their neighbourhood, conservation over one step."""
+    case = configs.vortex_3d(point_ic=True)
+    mesh = case.mesh
+    s = _solver(mesh, **case.params, precision=precision)
+    U0 = case.U0.astype(np.float32).astype(np.float64) if precision == "fp32" else case.U0
+    Ud = s.to_internal(U0)
+    R = s.to_external(s.residual(Ud))
+    seeds = np.random.default_rng(9).choice(mesh.n_cells, 48, replace=False)
+    sub, cells, _f = submesh(mesh, seeds, 5)
+    sgeo = OG.geometry(sub)
+    loc = np.searchsorted(cells, seeds)
+    ref = SV.residual(sub, sgeo, U0[cells], case.params)[loc]
+    if precision == "fp64":
+        _close(R[seeds], ref, rtol=1e-10, afloor=1e-12)
+    else:
+        for v in range(5):
+            assert rel_l2(R[seeds, v], ref[:, v]) < 1e-5
+    tot0 = s.diagnostics(Ud)[:5]
+    s.rk_step(Ud, case.dt)
+    tot1 = s.diagnostics(Ud)[:5]
+    eps = np.finfo(np.float64 if precision == "fp64" else np.float32).eps
+    assert np.all(np.abs(tot1 - tot0) <= 1e3 * eps * np.abs(tot0))
