@@ -354,7 +354,7 @@ dolinc_status dolinc_residual(dolinc_ctx c, const void* U, void* R, dolinc_strea
 static dolinc_status rk_step_impl(dolinc_ctx c, void* U, double dt, hipStream_t s) {
   // SSP-RK3 (third-order TVD Runge-Kutta, Sec. 3); stage outputs in W1, W2,
   // the last stage overwrites U cell by cell after reading it
-  HIPCHK(stage(c, U, nullptr, c->w.W1, 1, 0.0, 1.0, dt, s));
+  HIPCHK(stage(c, U, U, c->w.W1, 1, 0.0, 1.0, dt, s));
   HIPCHK(stage(c, c->w.W1, U, c->w.W2, 1, 0.75, 0.25, dt, s));
   HIPCHK(stage(c, c->w.W2, U, U, 1, 1.0 / 3.0, 2.0 / 3.0, dt, s));
   return DOLINC_OK;

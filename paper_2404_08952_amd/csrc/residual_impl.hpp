@@ -351,10 +351,12 @@ __global__ __launch_bounds__(KTPB) void k_flux(KArgs<T> a) {
     for (int v = 0; v < NV; ++v) {
       const T R = -(sum[v] + comp[v]) * rv;
       const int64_t i = c * NV + v;
-      if (a.mode == 0)
+      if (a.mode == 0) {
         a.out[i] = R;
-      else
-        a.out[i] = a.alpha * a.Un[i] + a.beta * (a.U[i] + a.dt * R);
+      } else {
+        const T un = a.Un ? a.Un[i] : T(0);
+        a.out[i] = a.alpha * un + a.beta * (a.U[i] + a.dt * R);
+      }
     }
   }
 }

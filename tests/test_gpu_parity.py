@@ -287,9 +287,10 @@ def test_full_size_vortex_sampled(precision):
     R = s.to_external(s.residual(Ud))
     seeds = np.random.default_rng(9).choice(mesh.n_cells, 48, replace=False)
     sub, cells, _f = submesh(mesh, seeds, 5)
-    sgeo = OG.geometry(sub)
     loc = np.searchsorted(cells, seeds)
-    ref = SV.residual(sub, sgeo, U0[cells], case.params)[loc]
+    with np.errstate(all="ignore"):  # ghost cells on the rim have open face sets
+        sgeo = OG.geometry(sub)
+        ref = SV.residual(sub, sgeo, U0[cells], case.params)[loc]
     if precision == "fp64":
         _close(R[seeds], ref, rtol=1e-10, afloor=1e-12)
     else:
@@ -299,4 +300,6 @@ def test_full_size_vortex_sampled(precision):
     s.rk_step(Ud, case.dt)
     tot1 = s.diagnostics(Ud)[:5]
     eps = np.finfo(np.float64 if precision == "fp64" else np.float32).eps
-    assert np.all(np.abs(tot1 - tot0) <= 1e3 * eps * np.abs(tot0))
+    V = s.geometry()["V"].cpu().numpy()[s.perm]
+    scale = (V[:, None] * np.abs(U0)).sum(0)
+    assert np.all(np.abs(tot1 - tot0) <= 1e3 * eps * scale), (tot1 - tot0, scale)
