@@ -1,0 +1,253 @@
+#!/usr/bin/env python3
+"""Throughput of the DOLINC explicit residual on one MI355X.
+
+A step is one SSP-RK3 step (three residual stages: gradients, reconstruction,
+Riemann flux, face-to-cell accumulation and the stage update) over the whole
+mesh, with the state resident in HBM.  The headline value is cell-updates per
+second per Runge-Kutta stage of the FP32-mixed path; the FP64 path on the
+same mesh is reported beside it.  One JSON line goes to stdout.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "cell-updates/s per RK stage (FP32 vs FP64) + achieved HBM GB/s, 3D Euler"
+HBM_PEAK_GBPS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_case(workload):
+    from synth import configs
+    if workload == "vortex3d":
+        case = configs.vortex_3d(point_ic=True)
+        desc = ("3-D Euler isentropic vortex, [0,10]^3 periodic, 64^3 jittered hexes x 6 Kuhn tets "
+                f"({case.mesh.n_cells:,} cells, {case.mesh.n_faces:,} faces), CSR4 DOLINC, Rusanov, SSP-RK3")
+    elif workload == "tgv3d":
+        case = configs.taylor_green_3d()
+        desc = ("3-D Euler Taylor-Green vortex Mach 0.1, [0,2pi]^3 periodic, 288^3 jittered hexes "
+                f"({case.mesh.n_cells:,} cells, {case.mesh.n_faces:,} faces), USR5 DOLINC, HLLC, SSP-RK3")
+    else:
+        raise SystemExit(f"unknown workload {workload}")
+    return case, desc
+
+
+def flux_kernel_bytes(nc, nf, nv, dim, el, scheme, blend=False):
+    """Algorithmic bytes of one flux + update launch: every array it needs
+    read once, its output written once (Un counted in 2 of 3 stages)."""
+    ord_ = 0 if scheme in ("FOU", "CD2") else (1 if scheme in ("USR3", "CSR4") else 2)
+    nl = {"FOU": 1, "CD2": 1, "USR3": 2, "CSR4": 3, "USR5": 4}[scheme]
+    nr = {"FOU": 1, "CD2": 1, "USR3": 2, "CSR4": 0, "USR5": 4}[scheme]
+    dcs = (3 + nl + nr + 3) & ~3
+    ns2 = dim * (dim + 1) // 2
+    per_cell = nv * el + (nv * dim * el if ord_ >= 1 or blend else 0) + (nv * ns2 * el if ord_ >= 2 else 0) \
+        + el + 4 + nv * el + (2.0 / 3.0) * nv * el + (4 if blend else 0)
+    per_face = 8 + 4 * el + dcs * el + 4
+    return nc * per_cell + nf * per_face, per_cell, per_face
+
+
+def grad_kernel_bytes(nc, nf, nq, dim, el, out_per_cell):
+    return nc * (nq * el + out_per_cell * el + el + 4) + nf * (8 + 4 * el + 4)
+
+
+def time_path(case, precision, steps, warmup):
+    import torch
+
+    from paper_2404_08952_amd import Solver
+    t0 = time.time()
+    s = Solver(case.mesh, **case.params, precision=precision)
+    log(f"[bench] {precision}: create + precompute {time.time() - t0:.1f} s")
+    U = s.to_internal(case.U0)
+    torch.cuda.synchronize()
+    for _ in range(warmup):
+        s.rk_step(U, case.dt)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    s.timing(True)
+    e0.record(stream)
+    for _ in range(steps):
+        s.rk_step(U, case.dt)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_k, n_k = s.timing(False)
+    ms = e0.elapsed_time(e1)
+    diag = s.diagnostics(U)
+    out = dict(ms_total=ms, ms_per_step=ms / steps, kernel_ms=ms_k.tolist(), kernel_n=n_k.tolist(),
+               stats=s.stats(), finite=bool(diag[-1] == 0), min_rho=float(diag[s.nv]), min_p=float(diag[s.nv + 1]))
+    s.close()
+    del U
+    torch.cuda.empty_cache()
+    return out
+
+
+def copy_bandwidth():
+    import torch
+    n = 1 << 29  # 2 GiB of float32 per buffer
+    a = torch.empty(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(2):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    reps = 10
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbps = 2 * 4 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbps
+
+
+def cpu_baseline_leg(budget_s):
+    """The FP64 oracle, single-threaded, on a bounded sample of the workload."""
+    import numpy as np
+
+    from oracle import geometry as OG
+    from oracle import solver as SV
+    from synth import configs
+    case = configs.vortex_3d(n=24, point_ic=True)
+    geo = OG.geometry(case.mesh)
+    U = case.U0
+    SV.residual(case.mesh, geo, U, case.params)  # warm
+    n, t0 = 0, time.perf_counter()
+    while True:
+        SV.residual(case.mesh, geo, U, case.params)
+        n += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return dict(value=case.mesh.n_cells * n / dt, unit="cell-updates/s", cores=1, kind="oracle",
+                sample=(f"oracle.solver.residual (FP64 NumPy) on the same workload at a 24^3 x 6 lattice "
+                        f"({case.mesh.n_cells:,} tets), {n} stages in {dt:.1f} s, one thread"),
+                cpu=_cpu_model(), host_cpus=os.cpu_count(), stages=n, seconds=dt,
+                _np=np.__version__)
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def run_cpu_baseline(budget_s):
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1",
+               NUMEXPR_NUM_THREADS="1")
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-only", "--cpu-budget", str(budget_s)]
+    r = subprocess.run(cmd, env=env, capture_output=True, text=True, timeout=600)
+    if r.returncode != 0:
+        log(r.stderr[-2000:])
+        return None
+    res = json.loads(r.stdout.strip().splitlines()[-1])
+    res.pop("_np", None)
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="vortex3d", choices=["vortex3d", "tgv3d"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--cpu-baseline-only", action="store_true")
+    args = ap.parse_args()
+
+    if args.cpu_baseline_only:
+        print(json.dumps(cpu_baseline_leg(args.cpu_budget)))
+        return
+    if args.gpus != 1:
+        raise SystemExit("this benchmark runs on one GPU only (no multi-GPU path is built); use --gpus 1")
+
+    import torch
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    dev = torch.cuda.get_device_name(0)
+    t0 = time.time()
+    case, desc = make_case(args.workload)
+    log(f"[bench] {args.workload}: mesh + initial data {time.time() - t0:.1f} s")
+    nc, nf = case.mesh.n_cells, case.mesh.n_faces
+    nv, dim = 5, 3
+    scheme = case.params["scheme"]
+    res = {}
+    for prec in ("fp32", "fp64"):
+        res[prec] = time_path(case, prec, args.steps, args.warmup)
+        log(f"[bench] {prec}: {res[prec]['ms_per_step']:.3f} ms/step, kernels ms {res[prec]['kernel_ms']}")
+    gbps_copy = copy_bandwidth()
+    log(f"[bench] device-to-device copy: {gbps_copy:.0f} GB/s")
+
+    def summarize(prec):
+        r = res[prec]
+        el = 4 if prec == "fp32" else 8
+        stages = 3 * args.steps
+        cups = nc * stages / (r["ms_total"] * 1e-3)
+        fb, fpc, fpf = flux_kernel_bytes(nc, nf, nv, dim, el, scheme)
+        gb = grad_kernel_bytes(nc, nf, nv, dim, el, nv * dim)
+        ms_flux = r["kernel_ms"][3] / max(r["kernel_n"][3], 1)
+        ms_grad = r["kernel_ms"][0] / max(r["kernel_n"][0], 1)
+        return dict(value=cups, ms_per_step=r["ms_per_step"], ms_per_stage=r["ms_per_step"] / 3,
+                    flux_kernel=dict(avg_ms=ms_flux, alg_bytes=fb, gbps=fb / (ms_flux * 1e-3) / 1e9,
+                                     bytes_per_cell=fpc, bytes_per_face=fpf),
+                    grad_kernel=dict(avg_ms=ms_grad, alg_bytes=gb, gbps=gb / (ms_grad * 1e-3) / 1e9),
+                    finite=r["finite"], min_rho=r["min_rho"], min_p=r["min_p"], partitions=r["stats"])
+
+    s32, s64 = summarize("fp32"), summarize("fp64")
+    fk = s32["flux_kernel"]
+    out = {
+        "metric": METRIC,
+        "value": s32["value"],
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": s32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": desc, "cells": nc, "faces": nf, "stages_per_step": 3,
+                   "precision": "FP32 bulk, coefficients precomputed in FP64"},
+        "roofline": {"bound": "hbm", "achieved": fk["gbps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": fk["gbps"] / HBM_PEAK_GBPS, "traffic": None,
+                     "kernel": "k_flux (reconstruction + Riemann flux + segmented accumulation + RK update)",
+                     "alg_bytes_per_launch": fk["alg_bytes"], "avg_launch_ms": fk["avg_ms"]},
+        "fp64": {"value": s64["value"], "ms_per_step": s64["ms_per_step"], "dtype": "f64",
+                 "flux_kernel_gbps": s64["flux_kernel"]["gbps"],
+                 "flux_kernel_frac": s64["flux_kernel"]["gbps"] / HBM_PEAK_GBPS},
+        "fp32_detail": s32,
+        "fp64_detail": s64,
+        "fp32_over_fp64": s32["value"] / s64["value"],
+        "device": dev,
+        "copy_gbps": gbps_copy,
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle baseline ...")
+        out["cpu_baseline"] = run_cpu_baseline(args.cpu_budget)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -94,7 +94,10 @@ typedef struct {
   int32_t flux;                  /* dolinc_flux       */
   int32_t precision;             /* dolinc_precision  */
   int32_t blend;                 /* dolinc_blend      */
-  int32_t use_u_ref;             /* FP32: subtract the flux of u_ref on every face    */
+  int32_t use_u_ref;             /* Euler: reconstruct U - u_ref and evaluate the     */
+                                 /* flux difference F(U) - F(u_ref) in difference     */
+                                 /* form (the FP32 reference-state form; the dropped  */
+                                 /* F(u_ref).S terms cancel over closed cells)        */
   double gamma;                  /* Euler ratio of specific heats                     */
   double adv_vel[3];             /* advection velocity                                */
   double burgers_dir[3];         /* Burgers flux u^2/2 * burgers_dir                   */
@@ -165,6 +168,14 @@ dolinc_status dolinc_geometry(dolinc_ctx ctx, double* V, double* xc, double* S, 
  * sum_c V_c U_c (FP64 sums) for every variable, then min rho (or min u),
  * min p (Euler; else max u) and the count of non-finite entries.  Blocks on s. */
 dolinc_status dolinc_diagnostics(dolinc_ctx ctx, const void* U, double* out, dolinc_stream s);
+
+/* Kernel timing with HIP events recorded around every launch on the stream
+ * the kernel runs on.  enable = 1 clears the accumulators and starts
+ * recording, 0 stops.  ms (host double[4]) and count (host int64_t[4]), each
+ * may be NULL, receive the accumulated milliseconds and launch counts of the
+ * kernel kinds {first gradient, second gradient, sensor, flux + update};
+ * reading waits for the recorded events. */
+dolinc_status dolinc_timing(dolinc_ctx ctx, int32_t enable, double* ms, int64_t* count);
 
 void dolinc_destroy(dolinc_ctx ctx);
 const char* dolinc_last_error(void);

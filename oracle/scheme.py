@@ -22,7 +22,8 @@ from __future__ import annotations
 
 import numpy as np
 
-SCHEMES = {"FOU": (1, 0), "CD2": (2, 0), "USR3": (3, 1), "CSR4": (4, 1), "USR5": (5, 2), "CSR6": (6, 2)}
+SCHEMES = {"FOU": (1, 0), "CD2": (2, 0), "USR3": (3, 1), "CSR4": (4, 1), "USR4": (4, 2), "USR5": (5, 2),
+           "CSR6": (6, 2)}
 
 
 # ------------------------------------------------------------------ step 1
@@ -124,7 +125,7 @@ def one_side(G0, G1c, d, g, scheme):
     G0, G1c: lists [phi, grad, grad2] of cells 0 and 1 gathered per face.
     """
     k, r = SCHEMES[scheme]
-    order = 0 if k <= 2 else (1 if k <= 4 else 2)
+    order = scheme_order(scheme)
     D0 = differentials(G0, d, order)
     D1 = differentials(G1c, d, order)
     table = {}
@@ -150,8 +151,11 @@ def cell_derivs(mesh, geo, U, order):
 
 
 def scheme_order(scheme):
-    k, _r = SCHEMES[scheme]
-    return 0 if k <= 2 else (1 if k <= 4 else 2)
+    """DOLINC order: the highest differential the far cells need.  Cell -n
+    (n >= 1) needs phi^(n) of the upwind cell; cell 1 + n needs phi^(n) of
+    the downwind cell."""
+    k, r = SCHEMES[scheme]
+    return max(0, r, k - r - 2)
 
 
 def face_states(mesh, geo, U, scheme, G=None):

@@ -63,6 +63,7 @@ SIGNATURES = {
     "dolinc_face_states": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
     "dolinc_geometry": [C.c_void_p] + [C.c_void_p] * 6 + [C.c_void_p],
     "dolinc_diagnostics": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+    "dolinc_timing": [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p],
     "dolinc_destroy": [C.c_void_p],
     "dolinc_last_error": [],
     "dolinc_version": [],
@@ -264,6 +265,14 @@ class Solver:
         out = np.empty(self.nv + 3, dtype=np.float64)
         _check(self.lib, self.lib.dolinc_diagnostics(self.h, self._ptr(U), out.ctypes.data, self._stream()))
         return out
+
+    def timing(self, enable):
+        """Start (True) / stop (False) per-kernel HIP-event timing; returns the
+        accumulated (ms[4], count[4]) for {grad1, grad2, sensor, flux}."""
+        ms = np.zeros(4)
+        n = np.zeros(4, dtype=np.int64)
+        _check(self.lib, self.lib.dolinc_timing(self.h, int(bool(enable)), ms.ctypes.data, n.ctypes.data))
+        return ms, n
 
     def stats(self):
         st = MeshStats()

@@ -20,6 +20,8 @@ hipError_t export_f64(dolinc_ctx_s*, const void*, void*, void*, void*, hipStream
 hipError_t export_f32(dolinc_ctx_s*, const void*, void*, void*, void*, hipStream_t);
 hipError_t grad_f64(dolinc_ctx_s*, const void*, void*, void*, hipStream_t);
 hipError_t grad_f32(dolinc_ctx_s*, const void*, void*, void*, hipStream_t);
+hipError_t grad2_f64(dolinc_ctx_s*, const void*, void*, hipStream_t);
+hipError_t grad2_f32(dolinc_ctx_s*, const void*, void*, hipStream_t);
 hipError_t theta_f64(dolinc_ctx_s*, const void*, const void*, float*, hipStream_t);
 hipError_t theta_f32(dolinc_ctx_s*, const void*, const void*, float*, hipStream_t);
 hipError_t diag_f64(dolinc_ctx_s*, const void*, double*, int, hipStream_t);
@@ -121,8 +123,43 @@ dolinc_status check_params(const dolinc_params* p, int dim) {
   return DOLINC_OK;
 }
 
+// HIP events around a launch when timing is on (kind: 0 grad1, 1 grad2,
+// 2 sensor, 3 flux + update)
+struct TimedLaunch {
+  dolinc_ctx c;
+  hipStream_t s;
+  size_t slot = (size_t)-1;
+  TimedLaunch(dolinc_ctx c_, hipStream_t s_, int kind) : c(c_), s(s_) {
+    if (!c->timing) return;
+    if (c->ev_used + 2 > c->ev_pool.size()) {
+      hipEvent_t a, b;
+      if (hipEventCreate(&a) != hipSuccess) return;
+      if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return;
+      }
+      c->ev_pool.push_back(a);
+      c->ev_pool.push_back(b);
+    }
+    slot = c->ev_used;
+    c->ev_used += 2;
+    c->ev_kind.push_back(kind);
+    (void)hipEventRecord(c->ev_pool[slot], s);
+  }
+  ~TimedLaunch() {
+    if (slot != (size_t)-1) (void)hipEventRecord(c->ev_pool[slot + 1], s);
+  }
+};
+
 hipError_t grad_dispatch(dolinc_ctx c, const void* U, void* G1, void* G2, hipStream_t s) {
-  return c->w.precision == DOLINC_FP64 ? grad_f64(c, U, G1, G2, s) : grad_f32(c, U, G1, G2, s);
+  hipError_t e;
+  {
+    TimedLaunch t(c, s, 0);
+    e = c->w.precision == DOLINC_FP64 ? grad_f64(c, U, G1, nullptr, s) : grad_f32(c, U, G1, nullptr, s);
+  }
+  if (e != hipSuccess || !G2) return e;
+  TimedLaunch t(c, s, 1);
+  return c->w.precision == DOLINC_FP64 ? grad2_f64(c, G1, G2, s) : grad2_f32(c, G1, G2, s);
 }
 
 // gradients (and classical theta) that one residual evaluation of U needs
@@ -133,9 +170,11 @@ hipError_t prepare_stage(dolinc_ctx c, const void* U, hipStream_t s) {
     hipError_t e = grad_dispatch(c, U, c->w.G1, ord >= 2 ? c->w.G2 : nullptr, s);
     if (e != hipSuccess) return e;
   }
-  if (c->params.blend == DOLINC_BLEND_CLASSICAL)
+  if (c->params.blend == DOLINC_BLEND_CLASSICAL) {
+    TimedLaunch t(c, s, 2);
     return c->w.precision == DOLINC_FP64 ? theta_f64(c, U, c->w.G1, c->w.theta, s)
                                          : theta_f32(c, U, c->w.G1, c->w.theta, s);
+  }
   return hipSuccess;
 }
 
@@ -143,6 +182,7 @@ hipError_t stage(dolinc_ctx c, const void* Us, const void* Un, void* out, int mo
                  hipStream_t s) {
   hipError_t e = prepare_stage(c, Us, s);
   if (e != hipSuccess) return e;
+  TimedLaunch t(c, s, 3);
   return c->w.precision == DOLINC_FP64 ? flux_f64(c, Us, Un, out, mode, al, be, dt, s)
                                        : flux_f32(c, Us, Un, out, mode, al, be, dt, s);
 }
@@ -468,12 +508,38 @@ dolinc_status dolinc_diagnostics(dolinc_ctx c, const void* U, double* out, dolin
   return DOLINC_OK;
 }
 
+dolinc_status dolinc_timing(dolinc_ctx c, int32_t enable, double* ms, int64_t* count) {
+  if (!valid_ctx(c)) return fail(DOLINC_ESTATE, "invalid or destroyed context");
+  double acc[4] = {0, 0, 0, 0};
+  int64_t n[4] = {0, 0, 0, 0};
+  if (ms || count) {
+    for (size_t k = 0; k < c->ev_kind.size(); ++k) {
+      HIPCHK(hipEventSynchronize(c->ev_pool[2 * k + 1]));
+      float t = 0.f;
+      HIPCHK(hipEventElapsedTime(&t, c->ev_pool[2 * k], c->ev_pool[2 * k + 1]));
+      acc[c->ev_kind[k]] += t;
+      n[c->ev_kind[k]] += 1;
+    }
+    for (int k = 0; k < 4; ++k) {
+      if (ms) ms[k] = acc[k];
+      if (count) count[k] = n[k];
+    }
+  }
+  if (enable) {
+    c->ev_used = 0;
+    c->ev_kind.clear();
+  }
+  c->timing = enable != 0;
+  return DOLINC_OK;
+}
+
 void dolinc_destroy(dolinc_ctx c) {
   {
     std::lock_guard<std::mutex> lk(g_live_mu);
     if (!c || !g_live.erase((const void*)c)) return;
   }
   free_all(c);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   delete c;
 }
 

@@ -108,6 +108,20 @@ hipError_t run_gradients(dolinc_ctx_s* c, const void* U, void* G1, void* G2, hip
 }
 
 template <class T>
+hipError_t run_grad2(dolinc_ctx_s* c, const void* G1, void* G2, hipStream_t s) {
+  KArgs<T> a = base_args<T>(c);
+  const dim3 grid(8 * a.cell_per_xcd), blk(KTPB);
+  const int nv = c->w.nv;
+  if (c->dim == 2)
+    hipLaunchKernelGGL((k_grad<T, 2, 2, true>), grid, blk, 0, s, a, (const T*)G1, (T*)G2);
+  else if (nv == 1)
+    hipLaunchKernelGGL((k_grad<T, 3, 3, true>), grid, blk, 0, s, a, (const T*)G1, (T*)G2);
+  else
+    hipLaunchKernelGGL((k_grad<T, 3, 15, true>), grid, blk, 0, s, a, (const T*)G1, (T*)G2);
+  return hipGetLastError();
+}
+
+template <class T>
 hipError_t run_theta(dolinc_ctx_s* c, const void* U, const void* G1, float* theta, hipStream_t s) {
   KArgs<T> a = base_args<T>(c);
   a.U = (const T*)U;

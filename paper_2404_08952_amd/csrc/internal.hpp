@@ -77,6 +77,11 @@ struct dolinc_ctx_s {
   dolinc_params params{};
   bool geometry_done = false;
   bool precomputed = false;
+  // kernel timing (dolinc_timing)
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<int> ev_kind;   // kind per recorded (start, stop) pair
+  size_t ev_used = 0;
 };
 
 namespace dolinc {
@@ -86,6 +91,7 @@ hipError_t launch_geometry(dolinc_ctx_s* c, hipStream_t s);
 hipError_t launch_entry_fill(dolinc_ctx_s* c, hipStream_t s);
 // stage kernels
 hipError_t launch_gradients(dolinc_ctx_s* c, const void* U, void* G1, void* G2, hipStream_t s);
+hipError_t launch_grad2(dolinc_ctx_s* c, const void* G1, void* G2, hipStream_t s);
 hipError_t launch_theta(dolinc_ctx_s* c, const void* U, const void* G1, float* theta, hipStream_t s);
 // mode 0: out = R(Us); mode 1: out = alpha*Un + beta*(Us + dt*R(Us))
 hipError_t launch_flux(dolinc_ctx_s* c, const void* Us, const void* Un, void* out, int mode, double alpha,

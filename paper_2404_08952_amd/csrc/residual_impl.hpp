@@ -171,6 +171,145 @@ __device__ __forceinline__ void flux_hllc(const T* UL, const T* UR, const T* S, 
   for (int k = 0; k < D + 2; ++k) F[k] = FK[k] * area;
 }
 
+// ---------------------------------------------------------------- reference-state (perturbation) fluxes
+// With a constant reference state U_r, the states are carried as
+// perturbations dU = U - U_r and the flux difference F(U) - F(U_r) is
+// formed algebraically, so the O(1) part of the flux never appears in
+// rounded arithmetic:
+//   u - u_r = (dm - u_r drho) / rho,   dk = (dm.u + m_r.du) / 2,
+//   dp = (gamma - 1)(dE - dk),
+//   d(mass)   = dm.S
+//   d(mom)    = dm (u.S) + m_r (du.S) + dp S
+//   d(energy) = (dE + dp)(u.S) + (E_r + p_r)(du.S).
+// Summed over a closed cell the dropped F(U_r).S terms cancel (sum of S = 0
+// in the FP64 geometry), so the residual is unchanged.
+template <class T, int D>
+struct RefState {
+  T r, m[D], u[D], E, p;
+};
+
+template <class T, int D>
+__device__ __forceinline__ void ref_state(const T* uref, T gamma, RefState<T, D>& R) {
+  R.r = uref[0];
+  T k = T(0);
+  for (int a = 0; a < D; ++a) {
+    R.m[a] = uref[1 + a];
+    R.u[a] = uref[1 + a] / uref[0];
+    k += R.m[a] * R.u[a];
+  }
+  R.E = uref[D + 1];
+  R.p = (gamma - T(1)) * (R.E - T(0.5) * k);
+}
+
+template <class T, int D>
+struct PertState {
+  T r, u[D], du[D], dp, p;
+};
+
+template <class T, int D>
+__device__ __forceinline__ void pert_state(const T* dU, const RefState<T, D>& R, T gamma, PertState<T, D>& P) {
+  P.r = R.r + dU[0];
+  T dk = T(0);
+  for (int a = 0; a < D; ++a) {
+    P.du[a] = (dU[1 + a] - R.u[a] * dU[0]) / P.r;
+    P.u[a] = R.u[a] + P.du[a];
+    dk += dU[1 + a] * P.u[a] + R.m[a] * P.du[a];
+  }
+  P.dp = (gamma - T(1)) * (dU[D + 1] - T(0.5) * dk);
+  P.p = R.p + P.dp;
+}
+
+// F(U).n - F(U_r).n for the (not necessarily unit) vector n
+template <class T, int D>
+__device__ __forceinline__ void pert_flux(const T* dU, const PertState<T, D>& P, const RefState<T, D>& R, const T* n,
+                                          T* dF) {
+  T un = T(0), dun = T(0), dmn = T(0);
+  for (int a = 0; a < D; ++a) {
+    un += P.u[a] * n[a];
+    dun += P.du[a] * n[a];
+    dmn += dU[1 + a] * n[a];
+  }
+  dF[0] = dmn;
+  for (int a = 0; a < D; ++a) dF[1 + a] = dU[1 + a] * un + R.m[a] * dun + P.dp * n[a];
+  dF[D + 1] = (dU[D + 1] + P.dp) * un + (R.E + R.p) * dun;
+}
+
+template <class T, int D>
+__device__ __forceinline__ void flux_rusanov_pert(const T* dL, const T* dR, const T* S, const T* uref, T gamma,
+                                                  T* F) {
+  RefState<T, D> R;
+  ref_state<T, D>(uref, gamma, R);
+  PertState<T, D> PL, PR;
+  pert_state<T, D>(dL, R, gamma, PL);
+  pert_state<T, D>(dR, R, gamma, PR);
+  T area2 = T(0), qL = T(0), qR = T(0);
+  for (int a = 0; a < D; ++a) {
+    area2 += S[a] * S[a];
+    qL += PL.u[a] * S[a];
+    qR += PR.u[a] * S[a];
+  }
+  const T area = sqrt(area2);
+  qL /= area;
+  qR /= area;
+  const T cL = sqrt(gamma * PL.p / PL.r), cR = sqrt(gamma * PR.p / PR.r);
+  const T lam = fmax(fabs(qL) + cL, fabs(qR) + cR);
+  T FL[D + 2], FR[D + 2];
+  pert_flux<T, D>(dL, PL, R, S, FL);
+  pert_flux<T, D>(dR, PR, R, S, FR);
+  const T diss = T(0.5) * lam * area;
+  for (int k = 0; k < D + 2; ++k) F[k] = T(0.5) * (FL[k] + FR[k]) - diss * (dR[k] - dL[k]);
+}
+
+// HLLC with every jump in difference form: S* - q_K from
+//   S* - q_L = (dp_R - dp_L - a_R (q_R - q_L)) / (a_L - a_R),
+//   S* - q_R = (dp_R - dp_L - a_L (q_R - q_L)) / (a_L - a_R),
+// a_K = rho_K (S_K - q_K), and U*_K - U_K written as multiples of S* - q_K.
+template <class T, int D>
+__device__ __forceinline__ void flux_hllc_pert(const T* dL, const T* dR, const T* S, const T* uref, T gamma, T* F) {
+  RefState<T, D> R;
+  ref_state<T, D>(uref, gamma, R);
+  PertState<T, D> PL, PR;
+  pert_state<T, D>(dL, R, gamma, PL);
+  pert_state<T, D>(dR, R, gamma, PR);
+  T area2 = T(0);
+  for (int a = 0; a < D; ++a) area2 += S[a] * S[a];
+  const T area = sqrt(area2);
+  T n[D];
+  for (int a = 0; a < D; ++a) n[a] = S[a] / area;
+  T qL = T(0), qR = T(0), dqLR = T(0);
+  for (int a = 0; a < D; ++a) {
+    qL += PL.u[a] * n[a];
+    qR += PR.u[a] * n[a];
+    dqLR += (PR.du[a] - PL.du[a]) * n[a];
+  }
+  const T cL = sqrt(gamma * PL.p / PL.r), cR = sqrt(gamma * PR.p / PR.r);
+  const T SL = fmin(qL - cL, qR - cR);
+  const T SR = fmax(qL + cL, qR + cR);
+  const T aL = PL.r * (SL - qL), aR = PR.r * (SR - qR);
+  const T dpLR = PR.dp - PL.dp;
+  const T sL = (dpLR - aR * dqLR) / (aL - aR);  // S* - q_L
+  const T sR = (dpLR - aL * dqLR) / (aL - aR);  // S* - q_R
+  const T Ss = qL + sL;
+  const bool left = SL >= T(0) || Ss >= T(0);
+  const T* dK = left ? dL : dR;
+  const PertState<T, D>& PK = left ? PL : PR;
+  T FK[D + 2];
+  pert_flux<T, D>(dK, PK, R, n, FK);
+  const bool star = left ? (SL < T(0)) : (SR > T(0));
+  if (star) {
+    const T SK = left ? SL : SR;
+    const T sK = left ? sL : sR;
+    const T qK = left ? qL : qR;
+    const T EK = R.E + dK[D + 1];
+    const T fr = PK.r * sK / (SK - Ss);  // fac - rho_K
+    const T fac = PK.r + fr;
+    FK[0] += SK * fr;
+    for (int a = 0; a < D; ++a) FK[1 + a] += SK * (fr * PK.u[a] + fac * sK * n[a]);
+    FK[D + 1] += SK * (fr * EK / PK.r + fac * sK * (Ss + PK.p / (PK.r * (SK - qK))));
+  }
+  for (int k = 0; k < D + 2; ++k) F[k] = FK[k] * area;
+}
+
 // ---------------------------------------------------------------- face evaluation
 // Loads one face entry, reconstructs (U_L, U_R) and returns the
 // face-integrated flux F.S (owner -> neighbour).
@@ -190,10 +329,13 @@ __device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T
 #pragma unroll
   for (int k = 0; k < DCS; ++k) dc[k] = dcp[k];
   T uP[NV], uN[NV];
+  // Euler with a reference state: reconstruct perturbations U - U_ref
+  const bool pert = PK >= 2 && a.use_ref;
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
-    uP[v] = a.U[P * NV + v];
-    uN[v] = a.U[N * NV + v];
+    const T r = pert ? a.uref[v] : T(0);
+    uP[v] = a.U[P * NV + v] - r;
+    uN[v] = a.U[N * NV + v] - r;
   }
   T gP[NV], gN[NV], hP[NV], hN[NV];
 #pragma unroll
@@ -282,7 +424,7 @@ __device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T
       fmx = fmax(fmx, T(0));
     }
     F[0] = uL <= uR ? fmn : fmx;
-  } else {
+  } else if (!pert) {
     // positivity: a side with rho <= 0 or p <= 0 falls back to its cell value
     {
       T r, vv[D], E, p;
@@ -297,12 +439,27 @@ __device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T
       flux_rusanov<T, D>(UL, UR, S, a.gamma, F);
     else
       flux_hllc<T, D>(UL, UR, S, a.gamma, F);
-    if (a.use_ref) {
-      T r, vv[D], E, p, Fr[D + 2];
-      euler_prim<T, D>(a.uref, a.gamma, r, vv, E, p);
-      euler_phys<T, D>(a.uref, r, vv, E, p, S, Fr);
+  } else {
+    {
+      RefState<T, D> Rf;
+      ref_state<T, D>(a.uref, a.gamma, Rf);
+      PertState<T, D> Ps;
+      pert_state<T, D>(UL, Rf, a.gamma, Ps);
+      if (!(Ps.r > T(0) && Ps.p > T(0)))
+        for (int v = 0; v < NV; ++v) UL[v] = uP[v];
+      pert_state<T, D>(UR, Rf, a.gamma, Ps);
+      if (!(Ps.r > T(0) && Ps.p > T(0)))
+        for (int v = 0; v < NV; ++v) UR[v] = uN[v];
+    }
+    if constexpr (PK == 2)
+      flux_rusanov_pert<T, D>(UL, UR, S, a.uref, a.gamma, F);
+    else
+      flux_hllc_pert<T, D>(UL, UR, S, a.uref, a.gamma, F);
+    // exported states are full states
 #pragma unroll
-      for (int k = 0; k < NV; ++k) F[k] -= Fr[k];
+    for (int v = 0; v < NV; ++v) {
+      UL[v] += a.uref[v];
+      UR[v] += a.uref[v];
     }
   }
 }

@@ -71,6 +71,10 @@ def burgers_2d(n=256, jitter=0.25, seed=11, split_seed=12, perm_seed=13, scheme=
     return Case("burgers2d", mesh, params, U0, dt, steps, exact=lambda t: fields.burgers_diag(t))
 
 
+# free stream of the vortex workload (rho, rho u, rho v, rho w, rho E)
+VORTEX_REF = (1.0, 1.0, 1.0, 0.0, 1.0 / 0.4 + 1.0)
+
+
 def vortex_3d(n=64, jitter=0.2, seed=21, perm_seed=22, scheme="CSR4", flux="rusanov",
               steps=200, cfl=0.4, quad_pts=3, point_ic=False):
     """3-D Euler isentropic vortex in [0,10]^3 on Kuhn-split tetrahedra."""
