@@ -71,8 +71,19 @@ typedef enum { DOLINC_FP64 = 0, DOLINC_FP32_MIXED = 1 } dolinc_precision;
 /* Blend of the high-order face state with a Van Leer limited second-order
  * state: U = theta_f U_high + (1 - theta_f) U_limited, theta_f = min of the
  * two cells' theta.  THETA takes theta per cell from dolinc_set_theta();
- * CLASSICAL computes it from the DOLINC divided-difference sensor. */
-typedef enum { DOLINC_BLEND_NONE = 0, DOLINC_BLEND_THETA = 1, DOLINC_BLEND_CLASSICAL = 2 } dolinc_blend;
+ * CLASSICAL computes it every stage from the DOLINC divided-difference
+ * sensor (Sec. 2.4, ENO3 indicators); LEARNED computes it every stage with
+ * the indicator network set by dolinc_mlp_set(). */
+typedef enum {
+  DOLINC_BLEND_NONE = 0, DOLINC_BLEND_THETA = 1, DOLINC_BLEND_CLASSICAL = 2, DOLINC_BLEND_LEARNED = 3
+} dolinc_blend;
+
+/* Learned indicator: 24 features per cell -> 64 -> 64 -> 1 (tanh, tanh,
+ * sigmoid).  Parameters packed as W1[64][24], b1[64], W2[64][64], b2[64],
+ * W3[64], b3 (fp32 master copy; the matrix cores use bf16 copies). */
+#define DOLINC_MLP_PARAMS 5825
+#define DOLINC_N_FEATURES 24
+#define DOLINC_FEATURE_STRIDE 32 /* bf16 feature rows are padded to 32 */
 
 typedef struct {
   int32_t dim;                   /* 2 or 3                                          */
@@ -169,11 +180,36 @@ dolinc_status dolinc_geometry(dolinc_ctx ctx, double* V, double* xc, double* S, 
  * min p (Euler; else max u) and the count of non-finite entries.  Blocks on s. */
 dolinc_status dolinc_diagnostics(dolinc_ctx ctx, const void* U, double* out, dolinc_stream s);
 
+/* Features of state U (Euler): X32 device float [n_cells][24] and/or Xbf
+ * device bf16 (uint16) [n_cells][32] (columns 24..31 zero); either may be
+ * NULL.  Internal cell order. */
+dolinc_status dolinc_features(dolinc_ctx ctx, const void* U, float* X32, uint16_t* Xbf, dolinc_stream s);
+
+/* Set (host float[DOLINC_MLP_PARAMS]) or read back the network parameters.
+ * Setting resets the Adam moments and step count.  Both synchronise. */
+dolinc_status dolinc_mlp_set(dolinc_ctx ctx, const float* params);
+dolinc_status dolinc_mlp_get(dolinc_ctx ctx, float* params);
+
+/* theta = network(X) for n rows of bf16 features X (device [n][32]);
+ * theta device float [n]. */
+dolinc_status dolinc_mlp_forward(dolinc_ctx ctx, const uint16_t* X, int64_t n, float* theta, dolinc_stream s);
+
+/* One Adam step (lr, beta1 0.9, beta2 0.999, eps 1e-8) on the mean binary
+ * cross entropy of the batch (X device bf16 [n][32], y device float [n]
+ * soft labels in [0, 1]).  loss (device float, may be NULL) receives the
+ * batch loss before the step. */
+dolinc_status dolinc_mlp_train_step(dolinc_ctx ctx, const uint16_t* X, const float* y, int64_t n, float lr,
+                                    float* loss, dolinc_stream s);
+
+/* Gradient of the same loss without a step: grad device float[DOLINC_MLP_PARAMS]. */
+dolinc_status dolinc_mlp_gradient(dolinc_ctx ctx, const uint16_t* X, const float* y, int64_t n, float* grad,
+                                  float* loss, dolinc_stream s);
+
 /* Kernel timing with HIP events recorded around every launch on the stream
  * the kernel runs on.  enable = 1 clears the accumulators and starts
  * recording, 0 stops.  ms (host double[4]) and count (host int64_t[4]), each
  * may be NULL, receive the accumulated milliseconds and launch counts of the
- * kernel kinds {first gradient, second gradient, sensor, flux + update};
+ * kernel kinds {first gradient, second gradient, sensor or indicator, flux + update};
  * reading waits for the recorded events. */
 dolinc_status dolinc_timing(dolinc_ctx ctx, int32_t enable, double* ms, int64_t* count);
 

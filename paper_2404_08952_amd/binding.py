@@ -19,7 +19,10 @@ PDE = {"advection": 0, "burgers": 1, "euler": 2}
 SCHEME = {"FOU": 1, "CD2": 2, "USR3": 3, "CSR4": 4, "USR5": 5}
 FLUX = {"upwind": 0, "rusanov": 1, "hllc": 2}
 PRECISION = {"fp64": 0, "fp32": 1}
-BLEND = {"none": 0, "theta": 1, "classical": 2}
+BLEND = {"none": 0, "theta": 1, "classical": 2, "learned": 3}
+MLP_PARAMS = 5825
+N_FEATURES = 24
+FEATURE_STRIDE = 32
 
 
 class MeshDesc(C.Structure):
@@ -64,6 +67,12 @@ SIGNATURES = {
     "dolinc_geometry": [C.c_void_p] + [C.c_void_p] * 6 + [C.c_void_p],
     "dolinc_diagnostics": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
     "dolinc_timing": [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p],
+    "dolinc_features": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+    "dolinc_mlp_set": [C.c_void_p, C.c_void_p],
+    "dolinc_mlp_get": [C.c_void_p, C.c_void_p],
+    "dolinc_mlp_forward": [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p],
+    "dolinc_mlp_train_step": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_float, C.c_void_p, C.c_void_p],
+    "dolinc_mlp_gradient": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p],
     "dolinc_destroy": [C.c_void_p],
     "dolinc_last_error": [],
     "dolinc_version": [],
@@ -273,6 +282,46 @@ class Solver:
         n = np.zeros(4, dtype=np.int64)
         _check(self.lib, self.lib.dolinc_timing(self.h, int(bool(enable)), ms.ctypes.data, n.ctypes.data))
         return ms, n
+
+    # -- learned indicator
+    def features(self, U, fp32=True, bf16=True):
+        t = self.torch
+        X32 = t.empty((self.n_cells, N_FEATURES), dtype=t.float32, device=self.device) if fp32 else None
+        Xb = t.empty((self.n_cells, FEATURE_STRIDE), dtype=t.int16, device=self.device) if bf16 else None
+        _check(self.lib, self.lib.dolinc_features(self.h, self._ptr(U), self._ptr(X32), self._ptr(Xb),
+                                                  self._stream()))
+        return X32, Xb
+
+    def mlp_set(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != MLP_PARAMS:
+            raise ValueError(f"expected {MLP_PARAMS} parameters")
+        _check(self.lib, self.lib.dolinc_mlp_set(self.h, p.ctypes.data))
+
+    def mlp_get(self):
+        p = np.empty(MLP_PARAMS, dtype=np.float32)
+        _check(self.lib, self.lib.dolinc_mlp_get(self.h, p.ctypes.data))
+        return p
+
+    def mlp_forward(self, Xb):
+        th = self.torch.empty(Xb.shape[0], dtype=self.torch.float32, device=self.device)
+        _check(self.lib, self.lib.dolinc_mlp_forward(self.h, self._ptr(Xb), Xb.shape[0], self._ptr(th),
+                                                     self._stream()))
+        return th
+
+    def mlp_train_step(self, Xb, y, lr):
+        loss = self.torch.empty(1, dtype=self.torch.float32, device=self.device)
+        _check(self.lib, self.lib.dolinc_mlp_train_step(self.h, self._ptr(Xb), self._ptr(y), Xb.shape[0],
+                                                        float(lr), self._ptr(loss), self._stream()))
+        return loss
+
+    def mlp_gradient(self, Xb, y):
+        t = self.torch
+        g = t.empty(MLP_PARAMS, dtype=t.float32, device=self.device)
+        loss = t.empty(1, dtype=t.float32, device=self.device)
+        _check(self.lib, self.lib.dolinc_mlp_gradient(self.h, self._ptr(Xb), self._ptr(y), Xb.shape[0],
+                                                      self._ptr(g), self._ptr(loss), self._stream()))
+        return g, loss
 
     def stats(self):
         st = MeshStats()

@@ -84,8 +84,11 @@ void free_work(dolinc_ctx c) {
   w.nv = 0;
 }
 
+void free_mlp(dolinc_ctx c);
+
 void free_all(dolinc_ctx c) {
   free_work(c);
+  free_mlp(c);
   DevMesh& m = c->m;
   dfree_t(m.part_ptr); dfree_t(m.ent_face); dfree_t(m.ent_pn); dfree_t(m.slot_ptr); dfree_t(m.slots);
   dfree_t(m.face_ent); dfree_t(m.face_own); dfree_t(m.face_nei);
@@ -101,7 +104,7 @@ dolinc_status check_params(const dolinc_params* p, int dim) {
   if (p->pde < 0 || p->pde > 2) return fail(DOLINC_EINVAL, "unknown pde");
   if (p->scheme < 1 || p->scheme > 5) return fail(DOLINC_EINVAL, "unknown scheme");
   if (p->precision < 0 || p->precision > 1) return fail(DOLINC_EINVAL, "unknown precision");
-  if (p->blend < 0 || p->blend > 2) return fail(DOLINC_EINVAL, "unknown blend");
+  if (p->blend < 0 || p->blend > 3) return fail(DOLINC_EINVAL, "unknown blend");
   if (p->flux < 0 || p->flux > 2) return fail(DOLINC_EINVAL, "unknown flux");
   if (p->pde != DOLINC_EULER && p->flux != DOLINC_FLUX_UPWIND)
     return fail(DOLINC_EINVAL, "scalar equations use the upwind (Godunov) flux");
@@ -175,6 +178,10 @@ hipError_t prepare_stage(dolinc_ctx c, const void* U, hipStream_t s) {
     return c->w.precision == DOLINC_FP64 ? theta_f64(c, U, c->w.G1, c->w.theta, s)
                                          : theta_f32(c, U, c->w.G1, c->w.theta, s);
   }
+  if (c->params.blend == DOLINC_BLEND_LEARNED) {
+    TimedLaunch t(c, s, 2);
+    return indicator_launch(c, U, c->w.theta, s);
+  }
   return hipSuccess;
 }
 
@@ -187,9 +194,40 @@ hipError_t stage(dolinc_ctx c, const void* Us, const void* Un, void* out, int mo
                                        : flux_f32(c, Us, Un, out, mode, al, be, dt, s);
 }
 
-dolinc_status need_ready(dolinc_ctx c) {
+dolinc_status need_ready(dolinc_ctx c, bool need_mlp = true) {
   if (!valid_ctx(c)) return fail(DOLINC_ESTATE, "invalid or destroyed context");
   if (!c->precomputed) return fail(DOLINC_ESTATE, "dolinc_precompute has not been called");
+  if (need_mlp && c->params.blend == DOLINC_BLEND_LEARNED && !c->mlp.p)
+    return fail(DOLINC_ESTATE, "blend mode LEARNED needs dolinc_mlp_set first");
+  return DOLINC_OK;
+}
+
+void free_mlp(dolinc_ctx c) {
+  Mlp& m = c->mlp;
+  dfree_t(m.p); dfree_t(m.m); dfree_t(m.v); dfree_t(m.w1b); dfree_t(m.w2b); dfree_t(m.part);
+  dfree_t(m.loss_part);
+  m.part_blocks = 0;
+  m.step = 0;
+}
+
+constexpr int MLP_N = DOLINC_MLP_PARAMS;
+constexpr int MLP_ROWS_PER_BLOCK = 256;
+
+dolinc_status mlp_batch_check(dolinc_ctx c, const uint16_t* X, const float* y, int64_t n) {
+  if (!valid_ctx(c)) return fail(DOLINC_ESTATE, "invalid or destroyed context");
+  if (!c->mlp.p) return fail(DOLINC_ESTATE, "dolinc_mlp_set has not been called");
+  if (!X || !y) return fail(DOLINC_EINVAL, "NULL batch");
+  if (n <= 0 || n > (int64_t)1 << 30) return fail(DOLINC_EINVAL, "batch size must be in [1, 2^30]");
+  const int64_t nb = (n + MLP_ROWS_PER_BLOCK - 1) / MLP_ROWS_PER_BLOCK;
+  if (nb > c->mlp.part_blocks) {
+    dfree_t(c->mlp.part);
+    dfree_t(c->mlp.loss_part);
+    c->mlp.part_blocks = 0;
+    if (hipMalloc((void**)&c->mlp.part, (size_t)nb * MLP_N * sizeof(float)) != hipSuccess ||
+        hipMalloc((void**)&c->mlp.loss_part, (size_t)nb * sizeof(float)) != hipSuccess)
+      return fail(DOLINC_ENOMEM, "gradient workspace allocation failed");
+    c->mlp.part_blocks = (int)nb;
+  }
   return DOLINC_OK;
 }
 
@@ -432,7 +470,7 @@ dolinc_status dolinc_set_theta(dolinc_ctx c, const float* theta, dolinc_stream s
 }
 
 dolinc_status dolinc_classical_theta(dolinc_ctx c, const void* U, float* theta, dolinc_stream stream) {
-  dolinc_status st = need_ready(c);
+  dolinc_status st = need_ready(c, false);
   if (st != DOLINC_OK) return st;
   if (!U || !theta) return fail(DOLINC_EINVAL, "NULL argument");
   if (!c->w.G1) return fail(DOLINC_ESTATE, "no gradient workspace (scheme of order 0 without blend)");
@@ -443,7 +481,7 @@ dolinc_status dolinc_classical_theta(dolinc_ctx c, const void* U, float* theta, 
 }
 
 dolinc_status dolinc_gradients(dolinc_ctx c, const void* U, void* G1, void* G2, dolinc_stream stream) {
-  dolinc_status st = need_ready(c);
+  dolinc_status st = need_ready(c, false);
   if (st != DOLINC_OK) return st;
   if (!U || !G1) return fail(DOLINC_EINVAL, "NULL argument");
   HIPCHK(grad_dispatch(c, U, G1, G2, (hipStream_t)stream));
@@ -480,7 +518,7 @@ dolinc_status dolinc_geometry(dolinc_ctx c, double* V, double* xc, double* S, do
 }
 
 dolinc_status dolinc_diagnostics(dolinc_ctx c, const void* U, double* out, dolinc_stream stream) {
-  dolinc_status st = need_ready(c);
+  dolinc_status st = need_ready(c, false);
   if (st != DOLINC_OK) return st;
   if (!U || !out) return fail(DOLINC_EINVAL, "NULL argument");
   hipStream_t s = (hipStream_t)stream;
@@ -505,6 +543,89 @@ dolinc_status dolinc_diagnostics(dolinc_ctx c, const void* U, double* out, dolin
     }
     out[k] = acc;
   }
+  return DOLINC_OK;
+}
+
+dolinc_status dolinc_features(dolinc_ctx c, const void* U, float* X32, uint16_t* Xbf, dolinc_stream stream) {
+  dolinc_status st = need_ready(c, false);
+  if (st != DOLINC_OK) return st;
+  if (!U) return fail(DOLINC_EINVAL, "NULL state");
+  if (c->params.pde != DOLINC_EULER) return fail(DOLINC_EUNSUPPORTED, "features are built for the Euler equations");
+  if (!c->w.G1) return fail(DOLINC_ESTATE, "no gradient workspace (scheme of order 0 without blend)");
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHK(grad_dispatch(c, U, c->w.G1, nullptr, s));
+  HIPCHK(features_launch(c, U, X32, (unsigned short*)Xbf, s));
+  return DOLINC_OK;
+}
+
+dolinc_status dolinc_mlp_set(dolinc_ctx c, const float* params) {
+  if (!valid_ctx(c)) return fail(DOLINC_ESTATE, "invalid or destroyed context");
+  if (!params) return fail(DOLINC_EINVAL, "NULL parameters");
+  for (int k = 0; k < MLP_N; ++k)
+    if (!std::isfinite(params[k])) return fail(DOLINC_EINVAL, "non-finite parameter");
+  Mlp& m = c->mlp;
+  if (!m.p) {
+    hipError_t e = hipMalloc((void**)&m.p, MLP_N * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc((void**)&m.m, MLP_N * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc((void**)&m.v, MLP_N * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc((void**)&m.w1b, 64 * 32 * sizeof(unsigned short));
+    if (e == hipSuccess) e = hipMalloc((void**)&m.w2b, 64 * 64 * sizeof(unsigned short));
+    if (e != hipSuccess) {
+      free_mlp(c);
+      return fail(DOLINC_ENOMEM, "network allocation failed");
+    }
+  }
+  HIPCHK(hipMemcpy(m.p, params, MLP_N * sizeof(float), hipMemcpyHostToDevice));
+  HIPCHK(hipMemset(m.m, 0, MLP_N * sizeof(float)));
+  HIPCHK(hipMemset(m.v, 0, MLP_N * sizeof(float)));
+  HIPCHK(mlp_pack_launch(c, nullptr));
+  HIPCHK(hipDeviceSynchronize());
+  m.step = 0;
+  return DOLINC_OK;
+}
+
+dolinc_status dolinc_mlp_get(dolinc_ctx c, float* params) {
+  if (!valid_ctx(c)) return fail(DOLINC_ESTATE, "invalid or destroyed context");
+  if (!c->mlp.p) return fail(DOLINC_ESTATE, "dolinc_mlp_set has not been called");
+  if (!params) return fail(DOLINC_EINVAL, "NULL output");
+  HIPCHK(hipDeviceSynchronize());
+  HIPCHK(hipMemcpy(params, c->mlp.p, MLP_N * sizeof(float), hipMemcpyDeviceToHost));
+  return DOLINC_OK;
+}
+
+dolinc_status dolinc_mlp_forward(dolinc_ctx c, const uint16_t* X, int64_t n, float* theta, dolinc_stream stream) {
+  if (!valid_ctx(c)) return fail(DOLINC_ESTATE, "invalid or destroyed context");
+  if (!c->mlp.p) return fail(DOLINC_ESTATE, "dolinc_mlp_set has not been called");
+  if (!X || !theta) return fail(DOLINC_EINVAL, "NULL argument");
+  if (n < 0) return fail(DOLINC_EINVAL, "n must be >= 0");
+  if (n == 0) return DOLINC_OK;
+  HIPCHK(mlp_forward_launch(c, (const unsigned short*)X, n, theta, (hipStream_t)stream));
+  return DOLINC_OK;
+}
+
+dolinc_status dolinc_mlp_train_step(dolinc_ctx c, const uint16_t* X, const float* y, int64_t n, float lr,
+                                    float* loss, dolinc_stream stream) {
+  dolinc_status st = mlp_batch_check(c, X, y, n);
+  if (st != DOLINC_OK) return st;
+  if (!(std::isfinite(lr) && lr > 0.f)) return fail(DOLINC_EINVAL, "lr must be finite and > 0");
+  const int nb = (int)((n + MLP_ROWS_PER_BLOCK - 1) / MLP_ROWS_PER_BLOCK);
+  const int64_t t = c->mlp.step + 1;
+  const float c1 = (float)(1.0 - std::pow(0.9, (double)t));
+  const float c2 = (float)(1.0 - std::pow(0.999, (double)t));
+  HIPCHK(mlp_grad_launch(c, (const unsigned short*)X, y, n, nb, MLP_ROWS_PER_BLOCK, nullptr, loss, 1, lr, c1, c2,
+                         (hipStream_t)stream));
+  c->mlp.step = t;
+  return DOLINC_OK;
+}
+
+dolinc_status dolinc_mlp_gradient(dolinc_ctx c, const uint16_t* X, const float* y, int64_t n, float* grad,
+                                  float* loss, dolinc_stream stream) {
+  dolinc_status st = mlp_batch_check(c, X, y, n);
+  if (st != DOLINC_OK) return st;
+  if (!grad) return fail(DOLINC_EINVAL, "NULL gradient output");
+  const int nb = (int)((n + MLP_ROWS_PER_BLOCK - 1) / MLP_ROWS_PER_BLOCK);
+  HIPCHK(mlp_grad_launch(c, (const unsigned short*)X, y, n, nb, MLP_ROWS_PER_BLOCK, grad, loss, 0, 0.f, 1.f, 1.f,
+                         (hipStream_t)stream));
   return DOLINC_OK;
 }
 

@@ -1,0 +1,73 @@
+// Launchers of the learned-indicator kernels (features, MLP forward,
+// gradients, Adam) and the fused per-stage indicator.
+#include "dispatch_impl.hpp"
+#include "indicator_impl.hpp"
+
+namespace dolinc {
+
+hipError_t features_launch(dolinc_ctx_s* c, const void* U, float* X32, unsigned short* Xb, hipStream_t s) {
+  const int dcs = dc_stride(c->params.scheme);
+  if (c->w.precision == DOLINC_FP64) {
+    KArgs<double> a = base_args<double>(c);
+    a.U = (const double*)U;
+    hipLaunchKernelGGL((k_features<double, 3>), dim3(8 * a.cell_per_xcd), dim3(KTPB), 0, s, a, dcs, X32, Xb);
+  } else {
+    KArgs<float> a = base_args<float>(c);
+    a.U = (const float*)U;
+    hipLaunchKernelGGL((k_features<float, 3>), dim3(8 * a.cell_per_xcd), dim3(KTPB), 0, s, a, dcs, X32, Xb);
+  }
+  return hipGetLastError();
+}
+
+static MlpDev mlp_dev(dolinc_ctx_s* c) {
+  MlpDev m;
+  m.p = c->mlp.p;
+  m.w1b = c->mlp.w1b;
+  m.w2b = c->mlp.w2b;
+  return m;
+}
+
+hipError_t indicator_launch(dolinc_ctx_s* c, const void* U, float* theta, hipStream_t s) {
+  const int dcs = dc_stride(c->params.scheme);
+  const MlpDev m = mlp_dev(c);
+  if (c->w.precision == DOLINC_FP64) {
+    KArgs<double> a = base_args<double>(c);
+    a.U = (const double*)U;
+    hipLaunchKernelGGL((k_indicator<double, 3>), dim3(8 * a.cell_per_xcd), dim3(KTPB), 0, s, a, dcs, m, theta);
+  } else {
+    KArgs<float> a = base_args<float>(c);
+    a.U = (const float*)U;
+    hipLaunchKernelGGL((k_indicator<float, 3>), dim3(8 * a.cell_per_xcd), dim3(KTPB), 0, s, a, dcs, m, theta);
+  }
+  return hipGetLastError();
+}
+
+hipError_t mlp_pack_launch(dolinc_ctx_s* c, hipStream_t s) {
+  hipLaunchKernelGGL(k_mlp_pack, dim3((MLP_H * MLP_H + 255) / 256), dim3(256), 0, s, c->mlp.p, c->mlp.w1b,
+                     c->mlp.w2b);
+  return hipGetLastError();
+}
+
+hipError_t mlp_forward_launch(dolinc_ctx_s* c, const unsigned short* X, int64_t n, float* theta, hipStream_t s) {
+  const int64_t tiles = (n + 15) / 16;
+  int64_t blocks = (tiles + 3) / 4;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_mlp_fwd, dim3((unsigned)blocks), dim3(256), 0, s, mlp_dev(c), X, n, theta);
+  return hipGetLastError();
+}
+
+hipError_t mlp_grad_launch(dolinc_ctx_s* c, const unsigned short* X, const float* y, int64_t n, int nblocks,
+                           int rows_per_block, float* grad_out, float* loss_out, int do_step, float lr, float c1,
+                           float c2, hipStream_t s) {
+  hipLaunchKernelGGL(k_mlp_grad, dim3(nblocks), dim3(256), 0, s, mlp_dev(c), X, y, n, rows_per_block, c->mlp.part,
+                     c->mlp.loss_part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_mlp_adam, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, s, nblocks, c->mlp.part,
+                     c->mlp.loss_part, c->mlp.p, c->mlp.m, c->mlp.v, c->mlp.w1b, c->mlp.w2b, grad_out, loss_out,
+                     do_step, lr, 0.9f, 0.999f, c1, c2, 1e-8f);
+  return hipGetLastError();
+}
+
+}  // namespace dolinc

@@ -1,0 +1,470 @@
+// Learned smoothness indicator: per-cell features and the 24-64-64-1 MLP.
+//
+// Features (24 per cell): channels q in {rho, p, rho E, |rho u|}, six
+// statistics each over the cell's faces in the frame where the cell is
+// upwind: Delta = q_N - q_P, g0 = 2 d0 . grad q (DOLINC differential),
+// s = g0 - Delta, beta = |s - Delta| / (|s| + |Delta| + eps),
+// scale = |q| + mean |Delta|:
+//   max|g0|/scale, max|Delta|/scale, max beta, mean beta,
+//   min clip(s Delta / (Delta^2 + eps^2), -2, 2), max|s - Delta|/scale,
+// each clipped to [-8, 8].  grad p and grad|rho u| by the chain rule.
+//
+// Network: theta = sigmoid(W3 . tanh(W2 tanh(W1 x + b1) + b2) + b3).
+// Matrix-core formulation (v_mfma_f32_16x16x16_bf16, wave64): each wave
+// carries 16 cells as the N dimension of Z^T = W X^T, so the accumulator
+// tile of one layer (lane l holds units 4(l/16)..4(l/16)+3 of cell l%16) is
+// exactly the B operand of the next layer.  bf16 operands (round to nearest
+// even), fp32 accumulation, fp32 biases, last layer on the vector ALU.
+#pragma once
+#include "residual_impl.hpp"
+
+namespace dolinc {
+
+constexpr int MLP_IN = 24, MLP_INP = 32, MLP_H = 64;
+constexpr int MLP_NPARAM = MLP_H * MLP_IN + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1;
+// offsets into the packed parameter vector
+constexpr int OFF_W1 = 0, OFF_B1 = MLP_H * MLP_IN, OFF_W2 = OFF_B1 + MLP_H, OFF_B2 = OFF_W2 + MLP_H * MLP_H,
+              OFF_W3 = OFF_B2 + MLP_H, OFF_B3 = OFF_W3 + MLP_H;
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short f2bf(float x) {
+  unsigned u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(unsigned short b) { return __uint_as_float(((unsigned)b) << 16); }
+
+__device__ __forceinline__ v4f mfma16(v4s a, v4s b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+struct MlpDev {
+  const float* p;                // fp32 master parameters (packed)
+  const unsigned short* w1b;     // bf16 W1 [64][32] (K padded with zeros)
+  const unsigned short* w2b;     // bf16 W2 [64][64]
+};
+
+// ---------------------------------------------------------------- features
+template <class T, int D>
+__device__ __forceinline__ void cell_channels(const T* U, const T* G, T gamma, T* q, T (*gq)[D]) {
+  const T rho = U[0];
+  T u[D], ke = T(0), mag2 = T(0);
+  for (int a = 0; a < D; ++a) {
+    u[a] = U[1 + a] / rho;
+    ke += U[1 + a] * u[a];
+    mag2 += U[1 + a] * U[1 + a];
+  }
+  const T E = U[D + 1];
+  const T mag = sqrt(mag2);
+  q[0] = rho;
+  q[1] = (gamma - T(1)) * (E - T(0.5) * ke);
+  q[2] = E;
+  q[3] = mag;
+  T uu = T(0);
+  for (int a = 0; a < D; ++a) uu += u[a] * u[a];
+  for (int x = 0; x < D; ++x) {
+    const T gr = G[0 * D + x], gE = G[(D + 1) * D + x];
+    T ugm = T(0), mgm = T(0);
+    for (int a = 0; a < D; ++a) {
+      ugm += u[a] * G[(1 + a) * D + x];
+      mgm += U[1 + a] * G[(1 + a) * D + x];
+    }
+    gq[0][x] = gr;
+    gq[1][x] = (gamma - T(1)) * (gE - ugm + T(0.5) * uu * gr);
+    gq[2][x] = gE;
+    gq[3][x] = mag > T(1e-30) ? mgm / mag : T(0);
+  }
+}
+
+template <class T, int D>
+__device__ void cell_features(const KArgs<T>& a, int dcs, int64_t c, float* feat) {
+  constexpr int NV = D + 2;
+  const int e0 = a.part_ptr[c / a.B];
+  const int s0 = a.slot_ptr[c], s1 = a.slot_ptr[c + 1];
+  T qc[4], gqc[4][D];
+  cell_channels<T, D>(a.U + c * NV, a.G1 + c * NV * D, a.gamma, qc, gqc);
+  T mx_g0[4], mx_dl[4], mx_b[4], sm_b[4], mn_r[4], mx_sd[4], sm_dl[4];
+  for (int k = 0; k < 4; ++k) {
+    mx_g0[k] = mx_dl[k] = mx_b[k] = sm_b[k] = mx_sd[k] = sm_dl[k] = T(0);
+    mn_r[k] = T(2);
+  }
+  for (int s = s0; s < s1; ++s) {
+    const uint16_t sl = a.slots[s];
+    const int64_t e = e0 + (sl & 0x7fff);
+    const bool nb = (sl >> 15) != 0;
+    const int2 pn = a.ent_pn[e];
+    const int64_t o = nb ? pn.x : pn.y;
+    const T* dcp = a.dc + (int64_t)dcs * e;
+    const T sg = nb ? T(-1) : T(1);
+    // neighbour channel values
+    const T* Uo = a.U + o * NV;
+    T qo[4];
+    {
+      const T rho = Uo[0];
+      T ke = T(0), m2 = T(0);
+      for (int x = 0; x < D; ++x) {
+        ke += Uo[1 + x] * Uo[1 + x] / rho;
+        m2 += Uo[1 + x] * Uo[1 + x];
+      }
+      qo[0] = rho;
+      qo[1] = (a.gamma - T(1)) * (Uo[D + 1] - T(0.5) * ke);
+      qo[2] = Uo[D + 1];
+      qo[3] = sqrt(m2);
+    }
+    for (int k = 0; k < 4; ++k) {
+      T g0 = T(0);
+      for (int x = 0; x < D; ++x) g0 += dcp[x] * gqc[k][x];
+      g0 *= T(2) * sg;
+      const T delta = qo[k] - qc[k];
+      const T sd = g0 - delta;
+      const T eps = T(1e-8) * (fabs(qc[k]) + fabs(qo[k])) + T(1e-30);
+      const T beta = fabs(sd - delta) / (fabs(sd) + fabs(delta) + eps);
+      T r = sd * delta / (delta * delta + eps * eps);
+      r = r < T(-2) ? T(-2) : (r > T(2) ? T(2) : r);
+      mx_g0[k] = fmax(mx_g0[k], fabs(g0));
+      mx_dl[k] = fmax(mx_dl[k], fabs(delta));
+      mx_b[k] = fmax(mx_b[k], beta);
+      sm_b[k] += beta;
+      mn_r[k] = fmin(mn_r[k], r);
+      mx_sd[k] = fmax(mx_sd[k], fabs(sd - delta));
+      sm_dl[k] += fabs(delta);
+    }
+  }
+  const T inv = T(1) / (T)(s1 - s0);
+  for (int k = 0; k < 4; ++k) {
+    const T scale = fabs(qc[k]) + sm_dl[k] * inv + T(1e-8);
+    T f[6] = {mx_g0[k] / scale, mx_dl[k] / scale, mx_b[k], sm_b[k] * inv, mn_r[k], mx_sd[k] / scale};
+    for (int j = 0; j < 6; ++j) {
+      T v = f[j] < T(-8) ? T(-8) : (f[j] > T(8) ? T(8) : f[j]);
+      feat[6 * k + j] = (float)v;
+    }
+  }
+}
+
+template <class T, int D>
+__global__ __launch_bounds__(KTPB) void k_features(KArgs<T> a, int dcs, float* __restrict__ X32,
+                                                    unsigned short* __restrict__ Xb) {
+  const int b = xcd_remap(blockIdx.x, a.cell_per_xcd, a.n_cell_blocks);
+  if (b < 0) return;
+  const int64_t c = (int64_t)b * KTPB + threadIdx.x;
+  if (c >= a.nc) return;
+  float f[MLP_IN];
+  cell_features<T, D>(a, dcs, c, f);
+  if (X32)
+    for (int j = 0; j < MLP_IN; ++j) X32[c * MLP_IN + j] = f[j];
+  if (Xb) {
+    for (int j = 0; j < MLP_IN; ++j) Xb[c * MLP_INP + j] = f2bf(f[j]);
+    for (int j = MLP_IN; j < MLP_INP; ++j) Xb[c * MLP_INP + j] = 0;
+  }
+}
+
+// ---------------------------------------------------------------- forward
+// Weights in A-operand layout: lane l holds rows (units) 16 t + l % 16,
+// K columns 16 kk + 4 (l / 16) .. + 3.
+struct MlpRegs {
+  v4s w1[4][2];
+  v4s w2[4][4];
+};
+
+__device__ __forceinline__ v4s load4(const unsigned short* p) {
+  v4s r;
+  r.x = (short)p[0];
+  r.y = (short)p[1];
+  r.z = (short)p[2];
+  r.w = (short)p[3];
+  return r;
+}
+
+__device__ __forceinline__ void load_weights(const MlpDev& m, MlpRegs& R) {
+  const int l = threadIdx.x & 63;
+  const int r = l & 15, g = l >> 4;
+  for (int t = 0; t < 4; ++t) {
+    for (int kk = 0; kk < 2; ++kk) R.w1[t][kk] = load4(m.w1b + (16 * t + r) * MLP_INP + 16 * kk + 4 * g);
+    for (int kk = 0; kk < 4; ++kk) R.w2[t][kk] = load4(m.w2b + (16 * t + r) * MLP_H + 16 * kk + 4 * g);
+  }
+}
+
+// Forward of 16 cells whose bf16 features are at X (row stride 32; rows
+// beyond nrow read as zero).  Outputs in D layout (lane: units 16t+4g+i of
+// cell l%16): H1 (fp32), H2 (fp32); returns theta of cell l % 16.
+__device__ __forceinline__ float mlp_tile_fwd(const MlpDev& m, const MlpRegs& R, const unsigned short* X, int nrow,
+                                              v4f* H1, v4f* H2, float* z3out) {
+  const int l = threadIdx.x & 63;
+  const int r = l & 15, g = l >> 4;
+  v4s xb[2];
+  for (int kk = 0; kk < 2; ++kk) {
+    if (r < nrow)
+      xb[kk] = load4(X + r * MLP_INP + 16 * kk + 4 * g);
+    else
+      xb[kk] = v4s{0, 0, 0, 0};
+  }
+  v4s h1b[4];
+  for (int t = 0; t < 4; ++t) {
+    v4f acc;
+    for (int i = 0; i < 4; ++i) acc[i] = m.p[OFF_B1 + 16 * t + 4 * g + i];
+    for (int kk = 0; kk < 2; ++kk) acc = mfma16(R.w1[t][kk], xb[kk], acc);
+    v4f h;
+    for (int i = 0; i < 4; ++i) h[i] = tanhf(acc[i]);
+    H1[t] = h;
+    h1b[t] = v4s{(short)f2bf(h[0]), (short)f2bf(h[1]), (short)f2bf(h[2]), (short)f2bf(h[3])};
+  }
+  float part = 0.f;
+  for (int t = 0; t < 4; ++t) {
+    v4f acc;
+    for (int i = 0; i < 4; ++i) acc[i] = m.p[OFF_B2 + 16 * t + 4 * g + i];
+    for (int kk = 0; kk < 4; ++kk) acc = mfma16(R.w2[t][kk], h1b[kk], acc);
+    v4f h;
+    for (int i = 0; i < 4; ++i) {
+      h[i] = tanhf(acc[i]);
+      part += m.p[OFF_W3 + 16 * t + 4 * g + i] * h[i];
+    }
+    H2[t] = h;
+  }
+  part += __shfl_xor(part, 16, 64);
+  part += __shfl_xor(part, 32, 64);
+  const float z3 = part + m.p[OFF_B3];
+  *z3out = z3;
+  return 1.f / (1.f + expf(-z3));
+}
+
+__global__ __launch_bounds__(256) void k_mlp_fwd(MlpDev m, const unsigned short* __restrict__ X, int64_t n,
+                                                 float* __restrict__ theta) {
+  MlpRegs R;
+  load_weights(m, R);
+  const int l = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const int64_t ntile = (n + 15) / 16;
+  for (int64_t t = wave; t < ntile; t += nwaves) {
+    const int64_t row0 = t * 16;
+    const int nrow = (int)((n - row0) < 16 ? (n - row0) : 16);
+    v4f H1[4], H2[4];
+    float z3;
+    const float th = mlp_tile_fwd(m, R, X + row0 * MLP_INP, nrow, H1, H2, &z3);
+    if (l < nrow) theta[row0 + l] = th;
+  }
+}
+
+// ---------------------------------------------------------------- backward
+// Per-block partial gradients (packed parameter order) and partial loss.
+// Rows [blk * rows_per_block, ...) of the batch; 4 waves per block.
+__global__ __launch_bounds__(256) void k_mlp_grad(MlpDev m, const unsigned short* __restrict__ X,
+                                                  const float* __restrict__ y, int64_t n, int rows_per_block,
+                                                  float* __restrict__ part, float* __restrict__ loss_part) {
+  __shared__ unsigned short sd2[4][16 * MLP_H];   // delta2 [row][u2], bf16
+  __shared__ unsigned short sh1[4][16 * MLP_H];   // H1 [row][u1], bf16
+  __shared__ unsigned short sd1[4][16 * MLP_H];   // delta1 [row][u1], bf16
+  __shared__ float red[MLP_NPARAM + 1];
+  MlpRegs R;
+  load_weights(m, R);
+  const int l = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int r = l & 15, g = l >> 4;
+  // W2^T in A layout for delta1 = W2^T delta2: A[m=u1][k=u2] = W2[u2][u1]
+  v4s w2t[4][4];
+  for (int t = 0; t < 4; ++t)
+    for (int kk = 0; kk < 4; ++kk) {
+      v4s v;
+      for (int i = 0; i < 4; ++i) v[i] = (short)m.w2b[(16 * kk + 4 * g + i) * MLP_H + 16 * t + r];
+      w2t[t][kk] = v;
+    }
+  v4f dW2[4][4], dW1[4][2];
+  for (int a = 0; a < 4; ++a) {
+    for (int b = 0; b < 4; ++b) dW2[a][b] = v4f{0, 0, 0, 0};
+    for (int b = 0; b < 2; ++b) dW1[a][b] = v4f{0, 0, 0, 0};
+  }
+  float dW3[16], db2[16], db1[16], db3 = 0.f, lsum = 0.f;
+  for (int k = 0; k < 16; ++k) dW3[k] = db2[k] = db1[k] = 0.f;
+  const float invn = 1.f / (float)n;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+  const int64_t r1 = r0 + rows_per_block < n ? r0 + rows_per_block : n;
+  for (int64_t row0 = r0 + 16 * w; row0 < r1; row0 += 64) {
+    const int nrow = (int)((r1 - row0) < 16 ? (r1 - row0) : 16);
+    v4f H1[4], H2[4];
+    float z3;
+    const float th = mlp_tile_fwd(m, R, X + row0 * MLP_INP, nrow, H1, H2, &z3);
+    const bool valid = r < nrow;
+    const float yy = valid ? y[row0 + r] : 0.f;
+    const float g3 = valid ? (th - yy) * invn : 0.f;
+    if (valid && g == 0) {  // BCE through the logit: softplus(z) - y z
+      const float sp = fmaxf(z3, 0.f) + log1pf(expf(-fabsf(z3)));
+      lsum += (sp - yy * z3) * invn;
+    }
+    if (g == 0) db3 += g3;
+    // delta2 = g3 W3 (1 - H2^2) in D layout; write bf16 copies to LDS
+    v4s d2b[4];
+    for (int t = 0; t < 4; ++t) {
+      for (int i = 0; i < 4; ++i) {
+        const int u = 16 * t + 4 * g + i;
+        const float h2 = H2[t][i];
+        dW3[4 * t + i] += g3 * h2;
+        const float d2 = g3 * m.p[OFF_W3 + u] * (1.f - h2 * h2);
+        db2[4 * t + i] += d2;
+        const unsigned short bb = f2bf(d2);
+        d2b[t][i] = (short)bb;
+        sd2[w][r * MLP_H + u] = bb;
+        sh1[w][r * MLP_H + u] = f2bf(H1[t][i]);
+      }
+    }
+    // delta1 = (W2^T delta2) (1 - H1^2)
+    for (int t = 0; t < 4; ++t) {
+      v4f acc = v4f{0, 0, 0, 0};
+      for (int kk = 0; kk < 4; ++kk) acc = mfma16(w2t[t][kk], d2b[kk], acc);
+      for (int i = 0; i < 4; ++i) {
+        const int u = 16 * t + 4 * g + i;
+        const float h1 = H1[t][i];
+        const float d1 = acc[i] * (1.f - h1 * h1);
+        db1[4 * t + i] += d1;
+        sd1[w][r * MLP_H + u] = f2bf(d1);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // dW2[u2][u1] += sum_rows delta2[row][u2] H1[row][u1]
+    for (int t = 0; t < 4; ++t) {
+      v4s A;
+      for (int i = 0; i < 4; ++i) A[i] = (short)sd2[w][(4 * g + i) * MLP_H + 16 * t + r];
+      for (int t2 = 0; t2 < 4; ++t2) {
+        v4s Bv;
+        for (int i = 0; i < 4; ++i) Bv[i] = (short)sh1[w][(4 * g + i) * MLP_H + 16 * t2 + r];
+        dW2[t][t2] = mfma16(A, Bv, dW2[t][t2]);
+      }
+      // dW1[u1][k] += sum_rows delta1[row][u1] X[row][k]
+      v4s A1;
+      for (int i = 0; i < 4; ++i) A1[i] = (short)sd1[w][(4 * g + i) * MLP_H + 16 * t + r];
+      for (int t2 = 0; t2 < 2; ++t2) {
+        v4s Bv;
+        for (int i = 0; i < 4; ++i) {
+          const int rr = 4 * g + i;
+          Bv[i] = rr < nrow ? (short)X[(row0 + rr) * MLP_INP + 16 * t2 + r] : (short)0;
+        }
+        dW1[t][t2] = mfma16(A1, Bv, dW1[t][t2]);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  // block reduction of the four waves' partials in LDS (fixed order)
+  for (int k = threadIdx.x; k < MLP_NPARAM + 1; k += blockDim.x) red[k] = 0.f;
+  __syncthreads();
+  for (int ww = 0; ww < 4; ++ww) {
+    if (w == ww) {
+      for (int t = 0; t < 4; ++t) {
+        for (int t2 = 0; t2 < 4; ++t2)
+          for (int i = 0; i < 4; ++i) red[OFF_W2 + (16 * t + 4 * g + i) * MLP_H + 16 * t2 + r] += dW2[t][t2][i];
+        for (int t2 = 0; t2 < 2; ++t2)
+          for (int i = 0; i < 4; ++i) {
+            const int k = 16 * t2 + r;
+            if (k < MLP_IN) red[OFF_W1 + (16 * t + 4 * g + i) * MLP_IN + k] += dW1[t][t2][i];
+          }
+      }
+      // lane-local sums over the wave's cells: reduce lanes with equal g
+      for (int k = 0; k < 16; ++k) {
+        float a3 = dW3[k], a2 = db2[k], a1 = db1[k];
+        for (int off = 1; off < 16; off <<= 1) {
+          a3 += __shfl_xor(a3, off, 64);
+          a2 += __shfl_xor(a2, off, 64);
+          a1 += __shfl_xor(a1, off, 64);
+        }
+        if (r == 0) {
+          const int u = 16 * (k >> 2) + 4 * g + (k & 3);
+          red[OFF_W3 + u] += a3;
+          red[OFF_B2 + u] += a2;
+          red[OFF_B1 + u] += a1;
+        }
+      }
+      float b3 = db3, ls = lsum;
+      for (int off = 1; off < 64; off <<= 1) {
+        b3 += __shfl_xor(b3, off, 64);
+        ls += __shfl_xor(ls, off, 64);
+      }
+      if (l == 0) {
+        red[OFF_B3] += b3;
+        red[MLP_NPARAM] += ls;
+      }
+    }
+    __syncthreads();
+  }
+  for (int k = threadIdx.x; k < MLP_NPARAM; k += blockDim.x) part[(int64_t)blockIdx.x * MLP_NPARAM + k] = red[k];
+  if (threadIdx.x == 0) loss_part[blockIdx.x] = red[MLP_NPARAM];
+}
+
+// Sum partial gradients in block order; optional Adam step on the fp32
+// master parameters with bf16 refresh of W1, W2.
+__global__ __launch_bounds__(256) void k_mlp_adam(int nparts, const float* __restrict__ part,
+                                                  const float* __restrict__ loss_part, float* __restrict__ p,
+                                                  float* __restrict__ mom, float* __restrict__ vel,
+                                                  unsigned short* __restrict__ w1b, unsigned short* __restrict__ w2b,
+                                                  float* __restrict__ grad_out, float* __restrict__ loss_out,
+                                                  int do_step, float lr, float b1, float b2, float c1, float c2,
+                                                  float eps) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k == 0 && loss_out) {
+    float s = 0.f;
+    for (int b = 0; b < nparts; ++b) s += loss_part[b];
+    *loss_out = s;
+  }
+  if (k >= MLP_NPARAM) return;
+  float gsum = 0.f;
+  for (int b = 0; b < nparts; ++b) gsum += part[(int64_t)b * MLP_NPARAM + k];
+  if (grad_out) grad_out[k] = gsum;
+  if (!do_step) return;
+  const float mk = b1 * mom[k] + (1.f - b1) * gsum;
+  const float vk = b2 * vel[k] + (1.f - b2) * gsum * gsum;
+  mom[k] = mk;
+  vel[k] = vk;
+  const float pk = p[k] - lr * (mk / c1) / (sqrtf(vk / c2) + eps);
+  p[k] = pk;
+  if (k < OFF_B1) {
+    const int u = k / MLP_IN, j = k % MLP_IN;
+    w1b[u * MLP_INP + j] = f2bf(pk);
+  } else if (k >= OFF_W2 && k < OFF_B2) {
+    w2b[k - OFF_W2] = f2bf(pk);
+  }
+}
+
+__global__ void k_mlp_pack(const float* __restrict__ p, unsigned short* __restrict__ w1b,
+                           unsigned short* __restrict__ w2b) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < MLP_H * MLP_INP) {
+    const int u = k / MLP_INP, j = k % MLP_INP;
+    w1b[k] = j < MLP_IN ? f2bf(p[OFF_W1 + u * MLP_IN + j]) : (unsigned short)0;
+  }
+  if (k < MLP_H * MLP_H) w2b[k] = f2bf(p[OFF_W2 + k]);
+}
+
+// Learned blend weights: features of the block's cells into LDS, then the
+// MLP on 16-cell tiles by each wave.
+template <class T, int D>
+__global__ __launch_bounds__(KTPB) void k_indicator(KArgs<T> a, int dcs, MlpDev m, float* __restrict__ theta) {
+  __shared__ unsigned short xs[KTPB * MLP_INP];
+  const int b = xcd_remap(blockIdx.x, a.cell_per_xcd, a.n_cell_blocks);
+  if (b < 0) return;
+  const int64_t c0 = (int64_t)b * KTPB;
+  const int64_t c = c0 + threadIdx.x;
+  if (c < a.nc) {
+    float f[MLP_IN];
+    cell_features<T, D>(a, dcs, c, f);
+    for (int j = 0; j < MLP_IN; ++j) xs[threadIdx.x * MLP_INP + j] = f2bf(f[j]);
+  } else {
+    for (int j = 0; j < MLP_IN; ++j) xs[threadIdx.x * MLP_INP + j] = 0;
+  }
+  for (int j = MLP_IN; j < MLP_INP; ++j) xs[threadIdx.x * MLP_INP + j] = 0;
+  __syncthreads();
+  MlpRegs R;
+  load_weights(m, R);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  for (int t = 0; t < 4; ++t) {
+    const int64_t row0 = c0 + 64 * w + 16 * t;
+    if (row0 >= a.nc) break;
+    const int nrow = (int)((a.nc - row0) < 16 ? (a.nc - row0) : 16);
+    v4f H1[4], H2[4];
+    float z3;
+    const float th = mlp_tile_fwd(m, R, xs + (64 * w + 16 * t) * MLP_INP, nrow, H1, H2, &z3);
+    if (l < nrow) theta[row0 + l] = th;
+  }
+}
+
+}  // namespace dolinc

@@ -49,6 +49,18 @@ struct DevMesh {
   double* dvec = nullptr;
 };
 
+struct Mlp {
+  float* p = nullptr;              // fp32 master parameters
+  float* m = nullptr;              // Adam first moment
+  float* v = nullptr;              // Adam second moment
+  unsigned short* w1b = nullptr;   // bf16 W1 [64][32]
+  unsigned short* w2b = nullptr;   // bf16 W2 [64][64]
+  float* part = nullptr;           // per-block partial gradients
+  float* loss_part = nullptr;
+  int part_blocks = 0;             // capacity of part in blocks
+  int64_t step = 0;
+};
+
 struct Work {
   void* sw = nullptr;
   void* dc = nullptr;
@@ -74,6 +86,7 @@ struct dolinc_ctx_s {
   std::vector<int32_t> new_of_old;
   dolinc::DevMesh m;
   dolinc::Work w;
+  dolinc::Mlp mlp;
   dolinc_params params{};
   bool geometry_done = false;
   bool precomputed = false;
@@ -99,5 +112,12 @@ hipError_t launch_flux(dolinc_ctx_s* c, const void* Us, const void* Un, void* ou
 hipError_t launch_face_export(dolinc_ctx_s* c, const void* U, void* UL, void* UR, void* F, hipStream_t s);
 hipError_t launch_diagnostics(dolinc_ctx_s* c, const void* U, double* out_host, hipStream_t s);
 bool flux_supported(const dolinc_params& p, int dim);
+hipError_t features_launch(dolinc_ctx_s* c, const void* U, float* X32, unsigned short* Xb, hipStream_t s);
+hipError_t indicator_launch(dolinc_ctx_s* c, const void* U, float* theta, hipStream_t s);
+hipError_t mlp_pack_launch(dolinc_ctx_s* c, hipStream_t s);
+hipError_t mlp_forward_launch(dolinc_ctx_s* c, const unsigned short* X, int64_t n, float* theta, hipStream_t s);
+hipError_t mlp_grad_launch(dolinc_ctx_s* c, const unsigned short* X, const float* y, int64_t n, int nblocks,
+                           int rows_per_block, float* grad_out, float* loss_out, int do_step, float lr, float c1,
+                           float c2, hipStream_t s);
 
 }  // namespace dolinc

@@ -1,0 +1,137 @@
+"""Parity of the learned-indicator kernels (features, bf16 matrix-core MLP
+forward / gradient, Adam, learned blend) with the FP64 oracle.
+
+The oracle is run in its bfloat16 mode, which rounds the same operands the
+kernels feed to the matrix cores; what remains is fp32 accumulation and fp32
+tanh / exp: forward within 1e-5, gradients within 1e-3 relative.  Against
+the unrounded FP64 network the forward agrees within 2e-2 (bf16 epsilon).
+"""
+import numpy as np
+import pytest
+
+from oracle import geometry as OG
+from oracle import indicator as OI
+from oracle import scheme as OS
+from oracle import solver as SV
+from synth import fields
+from synth import mesh as M
+
+from .helpers import oracle_params
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(amp=0.5, seed=3):
+    mesh = M.periodic_3d(6, 5, 5, jitter=0.2, seed=9, kinds=M.mixed_kinds(6, 5, 5, 0.4, seed=10), perm_seed=11)
+    geo = OG.geometry(mesh)
+    rng = np.random.default_rng(seed)
+    n = mesh.n_cells
+    U = fields.prim_to_cons(1.0 + amp * (rng.random(n) - 0.5), 0.3 * rng.normal(size=(n, 3)),
+                            1.0 + amp * (rng.random(n) - 0.5))
+    return mesh, geo, U
+
+
+def _bf16_agree(th, ref, params):
+    """Rows agree to 1e-5 except where a hidden activation sits on a bf16
+    rounding boundary (fp32 on the GPU vs fp64 in the oracle).  One such
+    one-ulp flip of H1_u (|H1| <= 1, ulp <= 2^-8) moves theta by at most
+    1/4 sum_j |W3_j W2_ju| 2^-8; allow two of them in a row."""
+    _W1, _b1, W2, _b2, W3, _b3 = OI.unpack(params)
+    bound = 0.25 * 2.0 ** -8 * 2 * np.max(np.abs(W3) @ np.abs(W2))
+    err = np.abs(np.asarray(th, dtype=np.float64) - ref)
+    assert err.max() <= bound, (err.max(), bound)
+    assert np.mean(err < 1e-5) > 0.99, np.mean(err < 1e-5)
+
+
+def _bf16_rows(t):
+    """int16 bf16 rows [n][32] (device) -> float64 [n][24] on the host."""
+    a = t.cpu().numpy().astype(np.uint16).astype(np.uint32) << 16
+    return a.view(np.float32)[:, :24].astype(np.float64)
+
+
+def test_feature_parity():
+    from paper_2404_08952_amd import Solver
+    mesh, geo, U = _setup()
+    s = Solver(mesh, pde="euler", scheme="USR3", flux="rusanov", blend="classical")
+    X32, Xb = s.features(s.to_internal(U))
+    ref = OI.features(mesh, geo, U, OS.gauss_linear(mesh, geo, U))
+    got = X32.cpu().numpy()[s.perm]
+    np.testing.assert_allclose(got, ref, rtol=1e-5, atol=1e-6)
+    np.testing.assert_array_equal(_bf16_rows(Xb)[s.perm], OI.bf16_round(got))
+
+
+def test_mlp_forward_gradient_and_adam():
+    import torch
+
+    from paper_2404_08952_amd import Solver
+    mesh, geo, U = _setup()
+    s = Solver(mesh, pde="euler", scheme="USR3", flux="rusanov", blend="learned")
+    _X32, Xb = s.features(s.to_internal(U))
+    X = _bf16_rows(Xb)
+    rng = np.random.default_rng(4)
+    p0 = (OI.xavier_init(7) + 0.1 * rng.normal(size=OI.N_PARAMS)).astype(np.float32)
+    s.mlp_set(p0)
+    np.testing.assert_array_equal(s.mlp_get(), p0)
+    p = p0.astype(np.float64)
+    th = s.mlp_forward(Xb).cpu().numpy()
+    ref_bf, _ = OI.forward(p, X, bf16=True)
+    _bf16_agree(th, ref_bf, p)
+    ref64, _ = OI.forward(p, X)
+    assert np.abs(th - ref64).max() < 2e-2
+    # gradient of the mean binary cross entropy
+    y = rng.random(mesh.n_cells).astype(np.float32)
+    yd = torch.from_numpy(y).cuda()
+    g, loss = s.mlp_gradient(Xb, yd)
+    rl, rg = OI.loss_and_grad(p, X, y.astype(np.float64), bf16=True)
+    g = g.cpu().numpy()
+    assert abs(loss.item() - rl) < 1e-5 * max(1.0, abs(rl))
+    assert np.linalg.norm(g - rg) <= 1e-3 * np.linalg.norm(rg), np.linalg.norm(g - rg) / np.linalg.norm(rg)
+    for blk in (slice(0, 1536), slice(1600, 5696), slice(5760, 5825)):
+        assert np.linalg.norm(g[blk] - rg[blk]) <= 1e-3 * np.linalg.norm(rg[blk]) + 1e-7
+    # three Adam steps against the oracle's Adam on its bf16 gradients
+    mo, vo = np.zeros(OI.N_PARAMS), np.zeros(OI.N_PARAMS)
+    for t in range(1, 4):
+        s.mlp_train_step(Xb, yd, 1e-2)
+        _l, rg = OI.loss_and_grad(p, X, y.astype(np.float64), bf16=True)
+        p, mo, vo = OI.adam_step(p, rg, mo, vo, t, 1e-2)
+    pg = s.mlp_get().astype(np.float64)
+    assert np.abs(pg - p).max() < 2e-4, np.abs(pg - p).max()
+    # the learned blend uses exactly these kernels: residual equals the
+    # THETA-mode residual with theta from features + forward, and the oracle
+    th_l = s.mlp_forward(s.features(s.to_internal(U))[1])
+    R_l = s.to_external(s.residual(s.to_internal(U)))
+    t2 = Solver(mesh, pde="euler", scheme="USR3", flux="rusanov", blend="theta")
+    t2.set_theta(th_l)
+    R_t = t2.to_external(t2.residual(t2.to_internal(U)))
+    np.testing.assert_array_equal(R_l, R_t)
+    thx = th_l.cpu().numpy()[s.perm].astype(np.float64)
+    kw = dict(pde="euler", scheme="USR3", flux="rusanov")
+    ref = SV.residual(mesh, geo, U, oracle_params(kw), theta=thx)
+    np.testing.assert_allclose(R_l, ref, rtol=1e-10, atol=1e-12 * np.abs(ref).max())
+
+
+def test_mlp_forward_large_ragged_batch():
+    """A batch that is not a multiple of the 16-row tile and spans many
+    blocks: every row against the oracle."""
+    import torch
+
+    from paper_2404_08952_amd import Solver
+    mesh, geo, U = _setup()
+    s = Solver(mesh, pde="euler", scheme="USR3", flux="rusanov", blend="learned")
+    p = OI.xavier_init(8).astype(np.float32)
+    s.mlp_set(p)
+    rng = np.random.default_rng(5)
+    n = 70001
+    Xh = OI.bf16_round(rng.normal(size=(n, 24)).clip(-8, 8)).astype(np.float32)
+    bits = (Xh.view(np.uint32) >> 16).astype(np.uint16)
+    Xb = np.zeros((n, 32), dtype=np.uint16)
+    Xb[:, :24] = bits
+    Xd = torch.from_numpy(Xb.view(np.int16)).cuda()
+    th = s.mlp_forward(Xd).cpu().numpy()
+    ref, _ = OI.forward(p.astype(np.float64), Xh.astype(np.float64), bf16=True)
+    _bf16_agree(th, ref, p.astype(np.float64))
+    y = torch.from_numpy(rng.random(n).astype(np.float32)).cuda()
+    g, _loss = s.mlp_gradient(Xd, y)
+    _rl, rg = OI.loss_and_grad(p.astype(np.float64), Xh.astype(np.float64), y.cpu().numpy().astype(np.float64),
+                               bf16=True)
+    assert np.linalg.norm(g.cpu().numpy() - rg) <= 1e-3 * np.linalg.norm(rg)
