@@ -31,16 +31,22 @@ def log(*a):
 def make_case(workload):
     from synth import configs
     if workload == "vortex3d":
-        case = configs.vortex_3d(point_ic=True)
+        case = configs.vortex_3d(point_ic=True, scheme="USR3")
         desc = ("3-D Euler isentropic vortex, [0,10]^3 periodic, 64^3 jittered hexes x 6 Kuhn tets "
-                f"({case.mesh.n_cells:,} cells, {case.mesh.n_faces:,} faces), CSR4 DOLINC, Rusanov, SSP-RK3")
-    elif workload == "tgv3d":
+                f"({case.mesh.n_cells:,} cells, {case.mesh.n_faces:,} faces), USR3 DOLINC, Rusanov, SSP-RK3")
+        return case, desc, dict(blend="none"), dict(u_ref=configs.VORTEX_REF)
+    if workload == "tgv3d":
         case = configs.taylor_green_3d()
         desc = ("3-D Euler Taylor-Green vortex Mach 0.1, [0,2pi]^3 periodic, 288^3 jittered hexes "
-                f"({case.mesh.n_cells:,} cells, {case.mesh.n_faces:,} faces), USR5 DOLINC, HLLC, SSP-RK3")
-    else:
-        raise SystemExit(f"unknown workload {workload}")
-    return case, desc
+                f"({case.mesh.n_cells:,} cells, {case.mesh.n_faces:,} faces), USR5 DOLINC, HLLC, "
+                "learned-indicator blend with Van Leer, SSP-RK3")
+        return case, desc, dict(blend="learned"), dict(u_ref=configs.TGV_REF)
+    raise SystemExit(f"unknown workload {workload}")
+
+
+def indicator_weights():
+    import numpy as np
+    return np.load(os.path.join(ROOT, "paper_2404_08952_amd", "data", "indicator_weights.npy"))
 
 
 def flux_kernel_bytes(nc, nf, nv, dim, el, scheme, blend=False):
@@ -61,13 +67,13 @@ def grad_kernel_bytes(nc, nf, nq, dim, el, out_per_cell):
     return nc * (nq * el + out_per_cell * el + el + 4) + nf * (8 + 4 * el + 4)
 
 
-def time_path(case, precision, steps, warmup):
+def time_path(s, case, precision, extra, steps, warmup):
     import torch
-
-    from paper_2404_08952_amd import Solver
     t0 = time.time()
-    s = Solver(case.mesh, **case.params, precision=precision)
-    log(f"[bench] {precision}: create + precompute {time.time() - t0:.1f} s")
+    s.configure(**case.params, precision=precision, **extra)
+    if extra.get("blend") == "learned":
+        s.mlp_set(indicator_weights())
+    log(f"[bench] {precision}: precompute {time.time() - t0:.1f} s")
     U = s.to_internal(case.U0)
     torch.cuda.synchronize()
     for _ in range(warmup):
@@ -87,7 +93,6 @@ def time_path(case, precision, steps, warmup):
     diag = s.diagnostics(U)
     out = dict(ms_total=ms, ms_per_step=ms / steps, kernel_ms=ms_k.tolist(), kernel_n=n_k.tolist(),
                stats=s.stats(), finite=bool(diag[-1] == 0), min_rho=float(diag[s.nv]), min_p=float(diag[s.nv + 1]))
-    s.close()
     del U
     torch.cuda.empty_cache()
     return out
@@ -116,29 +121,47 @@ def copy_bandwidth():
     return gbps
 
 
-def cpu_baseline_leg(budget_s):
-    """The FP64 oracle, single-threaded, on a bounded sample of the workload."""
+def cpu_baseline_leg(budget_s, workload):
+    """The FP64 oracle, single-threaded, on a bounded sample of the workload:
+    the same pipeline (for the Taylor-Green workload: features, indicator
+    network, blended USR5 + HLLC residual) on a smaller lattice."""
     import numpy as np
 
     from oracle import geometry as OG
+    from oracle import indicator as OI
+    from oracle import scheme as OS
     from oracle import solver as SV
     from synth import configs
-    case = configs.vortex_3d(n=24, point_ic=True)
+    if workload == "tgv3d":
+        case = configs.taylor_green_3d(n=24)
+        params = indicator_weights().astype(np.float64)
+    else:
+        case = configs.vortex_3d(n=24, point_ic=True, scheme="USR3")
+        params = None
     geo = OG.geometry(case.mesh)
     U = case.U0
-    SV.residual(case.mesh, geo, U, case.params)  # warm
+
+    def stage():
+        th = None
+        if params is not None:
+            X = OI.features(case.mesh, geo, U, OS.gauss_linear(case.mesh, geo, U))
+            th, _ = OI.forward(params, X)
+        return SV.residual(case.mesh, geo, U, case.params, theta=th)
+    stage()  # warm
     n, t0 = 0, time.perf_counter()
     while True:
-        SV.residual(case.mesh, geo, U, case.params)
+        stage()
         n += 1
         if time.perf_counter() - t0 >= budget_s:
             break
     dt = time.perf_counter() - t0
+    lat = case.mesh.info["lattice"][0]
     return dict(value=case.mesh.n_cells * n / dt, unit="cell-updates/s", cores=1, kind="oracle",
-                sample=(f"oracle.solver.residual (FP64 NumPy) on the same workload at a 24^3 x 6 lattice "
-                        f"({case.mesh.n_cells:,} tets), {n} stages in {dt:.1f} s, one thread"),
-                cpu=_cpu_model(), host_cpus=os.cpu_count(), stages=n, seconds=dt,
-                _np=np.__version__)
+                sample=(f"oracle residual stages (FP64 NumPy, same scheme and flux"
+                        f"{', indicator features + network + blend' if params is not None else ''}) on the "
+                        f"same workload at a {lat}^3 lattice ({case.mesh.n_cells:,} cells), {n} stages in "
+                        f"{dt:.1f} s, one thread"),
+                cpu=_cpu_model(), host_cpus=os.cpu_count(), stages=n, seconds=dt)
 
 
 def _cpu_model():
@@ -151,50 +174,57 @@ def _cpu_model():
     return "unknown"
 
 
-def run_cpu_baseline(budget_s):
+def run_cpu_baseline(budget_s, workload):
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1",
                NUMEXPR_NUM_THREADS="1")
-    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-only", "--cpu-budget", str(budget_s)]
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-only", "--cpu-budget", str(budget_s),
+           "--workload", workload]
     r = subprocess.run(cmd, env=env, capture_output=True, text=True, timeout=600)
     if r.returncode != 0:
         log(r.stderr[-2000:])
         return None
-    res = json.loads(r.stdout.strip().splitlines()[-1])
-    res.pop("_np", None)
-    return res
+    return json.loads(r.stdout.strip().splitlines()[-1])
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="vortex3d", choices=["vortex3d", "tgv3d"])
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="tgv3d", choices=["vortex3d", "tgv3d"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--cpu-baseline-only", action="store_true")
     args = ap.parse_args()
 
     if args.cpu_baseline_only:
-        print(json.dumps(cpu_baseline_leg(args.cpu_budget)))
+        print(json.dumps(cpu_baseline_leg(args.cpu_budget, args.workload)))
         return
     if args.gpus != 1:
         raise SystemExit("this benchmark runs on one GPU only (no multi-GPU path is built); use --gpus 1")
 
     import torch
+
+    from paper_2404_08952_amd import Solver
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     dev = torch.cuda.get_device_name(0)
     t0 = time.time()
-    case, desc = make_case(args.workload)
+    case, desc, extra, fp32_extra = make_case(args.workload)
     log(f"[bench] {args.workload}: mesh + initial data {time.time() - t0:.1f} s")
     nc, nf = case.mesh.n_cells, case.mesh.n_faces
     nv, dim = 5, 3
     scheme = case.params["scheme"]
+    blend = extra.get("blend", "none") != "none"
+    t0 = time.time()
+    solver = Solver(case.mesh, **case.params, **extra, precision="fp64")
+    log(f"[bench] create (renumber, partitions, upload, FP64 geometry) {time.time() - t0:.1f} s")
     res = {}
     for prec in ("fp32", "fp64"):
-        res[prec] = time_path(case, prec, args.steps, args.warmup)
+        ex = dict(extra, **(fp32_extra if prec == "fp32" else {}))
+        res[prec] = time_path(solver, case, prec, ex, args.steps, args.warmup)
         log(f"[bench] {prec}: {res[prec]['ms_per_step']:.3f} ms/step, kernels ms {res[prec]['kernel_ms']}")
+    solver.close()
     gbps_copy = copy_bandwidth()
     log(f"[bench] device-to-device copy: {gbps_copy:.0f} GB/s")
 
@@ -203,14 +233,15 @@ def main():
         el = 4 if prec == "fp32" else 8
         stages = 3 * args.steps
         cups = nc * stages / (r["ms_total"] * 1e-3)
-        fb, fpc, fpf = flux_kernel_bytes(nc, nf, nv, dim, el, scheme)
+        fb, fpc, fpf = flux_kernel_bytes(nc, nf, nv, dim, el, scheme, blend)
         gb = grad_kernel_bytes(nc, nf, nv, dim, el, nv * dim)
-        ms_flux = r["kernel_ms"][3] / max(r["kernel_n"][3], 1)
-        ms_grad = r["kernel_ms"][0] / max(r["kernel_n"][0], 1)
+        per = lambda k: r["kernel_ms"][k] / max(r["kernel_n"][k], 1)  # noqa: E731
         return dict(value=cups, ms_per_step=r["ms_per_step"], ms_per_stage=r["ms_per_step"] / 3,
-                    flux_kernel=dict(avg_ms=ms_flux, alg_bytes=fb, gbps=fb / (ms_flux * 1e-3) / 1e9,
+                    flux_kernel=dict(avg_ms=per(3), alg_bytes=fb, gbps=fb / (per(3) * 1e-3) / 1e9,
                                      bytes_per_cell=fpc, bytes_per_face=fpf),
-                    grad_kernel=dict(avg_ms=ms_grad, alg_bytes=gb, gbps=gb / (ms_grad * 1e-3) / 1e9),
+                    grad_kernel=dict(avg_ms=per(0), alg_bytes=gb, gbps=gb / (per(0) * 1e-3) / 1e9),
+                    grad2_kernel_ms=per(1), indicator_kernel_ms=per(2),
+                    stage_kernel_ms=sum(per(k) for k in range(4) if r["kernel_n"][k]),
                     finite=r["finite"], min_rho=r["min_rho"], min_p=r["min_p"], partitions=r["stats"])
 
     s32, s64 = summarize("fp32"), summarize("fp64")
@@ -229,10 +260,10 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": desc, "cells": nc, "faces": nf, "stages_per_step": 3,
-                   "precision": "FP32 bulk, coefficients precomputed in FP64"},
+                   "precision": "FP32 bulk (reference-state flux form), coefficients precomputed in FP64"},
         "roofline": {"bound": "hbm", "achieved": fk["gbps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": fk["gbps"] / HBM_PEAK_GBPS, "traffic": None,
-                     "kernel": "k_flux (reconstruction + Riemann flux + segmented accumulation + RK update)",
+                     "kernel": "k_flux (reconstruction + blend + Riemann flux + segmented accumulation + RK update)",
                      "alg_bytes_per_launch": fk["alg_bytes"], "avg_launch_ms": fk["avg_ms"]},
         "fp64": {"value": s64["value"], "ms_per_step": s64["ms_per_step"], "dtype": "f64",
                  "flux_kernel_gbps": s64["flux_kernel"]["gbps"],
@@ -245,7 +276,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline ...")
-        out["cpu_baseline"] = run_cpu_baseline(args.cpu_budget)
+        out["cpu_baseline"] = run_cpu_baseline(args.cpu_budget, args.workload)
     print(json.dumps(out))
 
 

@@ -2,14 +2,54 @@
 #include "mesh_prep.hpp"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <queue>
+#include <thread>
 
 namespace dolinc {
 
 namespace {
+
+// Phase timing to stderr when DOLINC_PREP_TIMING is set.
+struct PhaseClock {
+  bool on = std::getenv("DOLINC_PREP_TIMING") != nullptr;
+  std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+  void lap(const char* what) {
+    auto now = std::chrono::steady_clock::now();
+    if (on) std::fprintf(stderr, "[prepare] %-22s %8.3f s\n", what, std::chrono::duration<double>(now - t).count());
+    t = now;
+  }
+};
+
+int n_workers() {
+  unsigned h = std::thread::hardware_concurrency();
+  if (const char* e = std::getenv("DOLINC_PREP_THREADS")) h = (unsigned)std::atoi(e);
+  if (h < 1) h = 1;
+  if (h > 16) h = 16;
+  return (int)h;
+}
+
+// Runs fn(begin, end) over [0, n) in contiguous chunks on worker threads.
+template <class F>
+void parallel_for(int64_t n, F fn) {
+  const int T = n < 1024 ? 1 : n_workers();
+  if (T == 1) {
+    fn((int64_t)0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  th.reserve(T);
+  for (int t = 0; t < T; ++t) {
+    const int64_t a = n * t / T, b = n * (t + 1) / T;
+    th.emplace_back([=] { fn(a, b); });
+  }
+  for (auto& x : th) x.join();
+}
 
 struct CellFaces {
   std::vector<int64_t> ptr;   // [n_cells + 1]
@@ -81,17 +121,41 @@ void hilbert_order(int dim, int64_t n, const std::vector<double>& pts, std::vect
   for (int a = 0; a < dim; ++a) span = std::max(span, hi[a] - lo[a]);
   if (span <= 0.0) span = 1.0;
   const double scale = (double)((1u << b) - 1) / span;
-  std::vector<uint64_t> key(n);
-  for (int64_t c = 0; c < n; ++c) {
-    uint32_t X[3] = {0, 0, 0};
-    for (int a = 0; a < dim; ++a) X[a] = (uint32_t)std::llround((pts[c * dim + a] - lo[a]) * scale);
-    key[c] = hilbert_key(X, dim, b);
+  struct KeyIdx {
+    uint64_t key;
+    int32_t idx;
+    bool operator<(const KeyIdx& o) const { return key < o.key || (key == o.key && idx < o.idx); }
+  };
+  std::vector<KeyIdx> ki(n);
+  parallel_for(n, [&](int64_t a0, int64_t a1) {
+    for (int64_t c = a0; c < a1; ++c) {
+      uint32_t X[3] = {0, 0, 0};
+      for (int a = 0; a < dim; ++a) X[a] = (uint32_t)std::llround((pts[c * dim + a] - lo[a]) * scale);
+      ki[c] = KeyIdx{hilbert_key(X, dim, b), (int32_t)c};
+    }
+  });
+  // chunked sort on worker threads, then pairwise merges; (key, index) is
+  // a strict total order, so the result does not depend on the split
+  const int T = n < 65536 ? 1 : n_workers();
+  std::vector<int64_t> bnd(T + 1);
+  for (int t = 0; t <= T; ++t) bnd[t] = n * t / T;
+  {
+    std::vector<std::thread> th;
+    for (int t = 0; t < T; ++t) th.emplace_back([&, t] { std::sort(ki.begin() + bnd[t], ki.begin() + bnd[t + 1]); });
+    for (auto& x : th) x.join();
   }
-  std::vector<int32_t> order(n);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return key[x] < key[y]; });
+  for (int w = 1; w < T; w *= 2) {
+    std::vector<std::thread> th;
+    for (int t = 0; t + w < T; t += 2 * w) {
+      const int64_t a = bnd[t], m = bnd[t + w], e = bnd[std::min(t + 2 * w, T)];
+      th.emplace_back([&, a, m, e] { std::inplace_merge(ki.begin() + a, ki.begin() + m, ki.begin() + e); });
+    }
+    for (auto& x : th) x.join();
+  }
   new_of_old.resize(n);
-  for (int64_t i = 0; i < n; ++i) new_of_old[order[i]] = (int32_t)i;
+  parallel_for(n, [&](int64_t a0, int64_t a1) {
+    for (int64_t i = a0; i < a1; ++i) new_of_old[ki[i].idx] = (int32_t)i;
+  });
 }
 
 void rcm_order(int64_t n, const std::vector<int64_t>& ptr, const std::vector<int32_t>& adj,
@@ -163,6 +227,7 @@ dolinc_status prepare_mesh(const dolinc_mesh_desc& d, Prepared& P, std::string& 
   if (B < 32 || B > 1024) { msg = "part_cells must be in [32, 1024]"; return DOLINC_EINVAL; }
   const int dim = d.dim;
   const int64_t nc = d.n_cells, nf = d.n_faces, nn = d.n_nodes;
+  PhaseClock clk;
   if (d.face_node_ptr[0] != 0) { msg = "face_node_ptr[0] must be 0"; return DOLINC_EMESH; }
   for (int64_t f = 0; f < nf; ++f) {
     int64_t m = d.face_node_ptr[f + 1] - d.face_node_ptr[f];
@@ -181,8 +246,10 @@ dolinc_status prepare_mesh(const dolinc_mesh_desc& d, Prepared& P, std::string& 
   for (int64_t i = 0; i < nn * dim; ++i)
     if (!std::isfinite(d.node_xyz[i])) { msg = "non-finite node coordinate"; return DOLINC_EMESH; }
 
+  clk.lap("validate");
   CellFaces cf;
   build_cell_faces(d, cf);
+  clk.lap("cell faces");
   int64_t maxcf = 0;
   for (int64_t c = 0; c < nc; ++c) {
     int64_t k = cf.ptr[c + 1] - cf.ptr[c];
@@ -209,59 +276,108 @@ dolinc_status prepare_mesh(const dolinc_mesh_desc& d, Prepared& P, std::string& 
   } else {
     // cell position estimate: mean of its faces' vertex averages (own frame)
     std::vector<double> fc(nf * dim, 0.0);
-    for (int64_t f = 0; f < nf; ++f) {
-      int64_t a = d.face_node_ptr[f], b = d.face_node_ptr[f + 1];
-      for (int64_t k = a; k < b; ++k)
-        for (int ax = 0; ax < dim; ++ax) fc[f * dim + ax] += d.node_xyz[(int64_t)d.face_nodes[k] * dim + ax];
-      for (int ax = 0; ax < dim; ++ax) fc[f * dim + ax] /= (double)(b - a);
-    }
-    std::vector<double> pts(nc * dim, 0.0);
-    for (int64_t c = 0; c < nc; ++c) {
-      for (int64_t k = cf.ptr[c]; k < cf.ptr[c + 1]; ++k) {
-        int32_t f = cf.face[k];
-        for (int ax = 0; ax < dim; ++ax)
-          pts[c * dim + ax] += fc[f * dim + ax] - (cf.side[k] ? d.neigh_shift[f * dim + ax] : 0.0);
+    parallel_for(nf, [&](int64_t f0, int64_t f1) {
+      for (int64_t f = f0; f < f1; ++f) {
+        int64_t a = d.face_node_ptr[f], b = d.face_node_ptr[f + 1];
+        for (int64_t k = a; k < b; ++k)
+          for (int ax = 0; ax < dim; ++ax) fc[f * dim + ax] += d.node_xyz[(int64_t)d.face_nodes[k] * dim + ax];
+        for (int ax = 0; ax < dim; ++ax) fc[f * dim + ax] /= (double)(b - a);
       }
-      for (int ax = 0; ax < dim; ++ax) pts[c * dim + ax] /= (double)(cf.ptr[c + 1] - cf.ptr[c]);
-    }
+    });
+    std::vector<double> pts(nc * dim, 0.0);
+    parallel_for(nc, [&](int64_t c0, int64_t c1) {
+      for (int64_t c = c0; c < c1; ++c) {
+        for (int64_t k = cf.ptr[c]; k < cf.ptr[c + 1]; ++k) {
+          int32_t f = cf.face[k];
+          for (int ax = 0; ax < dim; ++ax)
+            pts[c * dim + ax] += fc[f * dim + ax] - (cf.side[k] ? d.neigh_shift[f * dim + ax] : 0.0);
+        }
+        for (int ax = 0; ax < dim; ++ax) pts[c * dim + ax] /= (double)(cf.ptr[c + 1] - cf.ptr[c]);
+      }
+    });
     hilbert_order(dim, nc, pts, P.new_of_old);
   }
+  clk.lap("renumber");
   P.old_of_new.resize(nc);
   for (int64_t c = 0; c < nc; ++c) P.old_of_new[P.new_of_old[c]] = (int32_t)c;
 
-  // partitions, entries, slots
+  // partitions, entries, slots: every partition is built independently
+  // (its faces in order of first touch by its cells, cells in order, each
+  // cell's faces by id) and the pieces are concatenated in partition order
   P.n_parts = (nc + B - 1) / B;
   P.part_ent_ptr.assign(P.n_parts + 1, 0);
-  P.ent_face.reserve((size_t)(nf * 1.3) + 16);
   P.slot_ptr.assign(nc + 1, 0);
   P.slots.resize(2 * nf);
   P.face_first_ent.assign(nf, -1);
-  std::vector<int32_t> mark(nf, -1), loc(nf, 0);
-  int64_t s = 0;
-  for (int64_t p = 0; p < P.n_parts; ++p) {
-    int32_t nloc = 0;
-    const int64_t c0 = p * B, c1 = std::min<int64_t>(c0 + B, nc);
-    for (int64_t c = c0; c < c1; ++c) {
-      const int32_t oc = P.old_of_new[c];
-      P.slot_ptr[c] = (int32_t)s;
-      for (int64_t k = cf.ptr[oc]; k < cf.ptr[oc + 1]; ++k) {
-        const int32_t f = cf.face[k];
-        if (mark[f] != (int32_t)p) {
-          mark[f] = (int32_t)p;
-          loc[f] = nloc++;
-          if (P.face_first_ent[f] < 0) P.face_first_ent[f] = (int32_t)P.ent_face.size();
-          P.ent_face.push_back(f);
-          P.ent_p.push_back(P.new_of_old[d.owner[f]]);
-          P.ent_n.push_back(P.new_of_old[d.neighbour[f]]);
-        }
-        P.slots[s++] = (uint16_t)(loc[f] | (cf.side[k] << 15));
+  std::vector<std::vector<int32_t>> pfaces(P.n_parts);
+  std::vector<int64_t> maxloc(P.n_parts, 0);
+  bool too_many = false;
+  parallel_for(P.n_parts, [&](int64_t p0, int64_t p1) {
+    std::vector<std::pair<int32_t, int32_t>> seen;  // (face, first-touch order)
+    for (int64_t p = p0; p < p1; ++p) {
+      const int64_t c0 = p * B, c1 = std::min<int64_t>(c0 + B, nc);
+      seen.clear();
+      for (int64_t c = c0; c < c1; ++c) {
+        const int32_t oc = P.old_of_new[c];
+        for (int64_t k = cf.ptr[oc]; k < cf.ptr[oc + 1]; ++k) seen.emplace_back(cf.face[k], (int32_t)seen.size());
+      }
+      std::sort(seen.begin(), seen.end());
+      // keep the first touch of every face; order the faces by first touch
+      std::vector<std::pair<int32_t, int32_t>> firsts;  // (first touch, face)
+      for (size_t i = 0; i < seen.size(); ++i)
+        if (i == 0 || seen[i].first != seen[i - 1].first) firsts.emplace_back(seen[i].second, seen[i].first);
+      std::sort(firsts.begin(), firsts.end());
+      std::vector<int32_t>& fl = pfaces[p];
+      fl.resize(firsts.size());
+      for (size_t i = 0; i < firsts.size(); ++i) fl[i] = firsts[i].second;
+      maxloc[p] = (int64_t)fl.size();
+      if (fl.size() >= 32768) too_many = true;
+      for (int64_t c = c0; c < c1; ++c) {
+        const int32_t oc = P.old_of_new[c];
+        P.slot_ptr[c + 1] = (int32_t)(cf.ptr[oc + 1] - cf.ptr[oc]);
       }
     }
-    if (nloc >= 32768) { msg = "partition has too many faces"; return DOLINC_EMESH; }
-    P.part_ent_ptr[p + 1] = (int32_t)P.ent_face.size();
-    P.max_entries = std::max<int64_t>(P.max_entries, nloc);
+  });
+  if (too_many) { msg = "partition has too many faces"; return DOLINC_EMESH; }
+  for (int64_t c = 0; c < nc; ++c) P.slot_ptr[c + 1] += P.slot_ptr[c];
+  for (int64_t p = 0; p < P.n_parts; ++p) {
+    P.part_ent_ptr[p + 1] = P.part_ent_ptr[p] + (int32_t)pfaces[p].size();
+    P.max_entries = std::max(P.max_entries, maxloc[p]);
   }
-  P.slot_ptr[nc] = (int32_t)s;
+  if ((int64_t)P.part_ent_ptr[P.n_parts] >= (int64_t)INT32_MAX) { msg = "too many face entries"; return DOLINC_EMESH; }
+  const int64_t ne = P.part_ent_ptr[P.n_parts];
+  P.ent_face.resize(ne);
+  P.ent_p.resize(ne);
+  P.ent_n.resize(ne);
+  parallel_for(P.n_parts, [&](int64_t p0, int64_t p1) {
+    std::vector<std::pair<int32_t, int32_t>> byface;
+    for (int64_t p = p0; p < p1; ++p) {
+      const std::vector<int32_t>& fl = pfaces[p];
+      const int64_t e0 = P.part_ent_ptr[p];
+      byface.resize(fl.size());
+      for (size_t i = 0; i < fl.size(); ++i) {
+        const int32_t f = fl[i];
+        P.ent_face[e0 + i] = f;
+        P.ent_p[e0 + i] = P.new_of_old[d.owner[f]];
+        P.ent_n[e0 + i] = P.new_of_old[d.neighbour[f]];
+        byface[i] = std::make_pair(f, (int32_t)i);
+      }
+      std::sort(byface.begin(), byface.end());
+      const int64_t c0 = p * B, c1 = std::min<int64_t>(c0 + B, nc);
+      for (int64_t c = c0; c < c1; ++c) {
+        const int32_t oc = P.old_of_new[c];
+        int64_t s = P.slot_ptr[c];
+        for (int64_t k = cf.ptr[oc]; k < cf.ptr[oc + 1]; ++k) {
+          const int32_t f = cf.face[k];
+          auto it = std::lower_bound(byface.begin(), byface.end(), std::make_pair(f, (int32_t)-1));
+          P.slots[s++] = (uint16_t)(it->second | (cf.side[k] << 15));
+        }
+      }
+    }
+  });
+  // first entry of every face (lowest partition wins)
+  for (int64_t e = ne - 1; e >= 0; --e) P.face_first_ent[P.ent_face[e]] = (int32_t)e;
+  clk.lap("partitions");
   if ((int64_t)P.ent_face.size() >= (int64_t)INT32_MAX) { msg = "too many face entries"; return DOLINC_EMESH; }
   return DOLINC_OK;
 }

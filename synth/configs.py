@@ -105,13 +105,17 @@ def shocks_3d(n=200, jitter=0.2, seed=31, split_seed=32, perm_seed=33, problem="
     return Case("shocks3d_" + problem, mesh, params, U0, dt, steps)
 
 
+# reference state of the Taylor-Green workload at Mach 0.1 (rest, p0 = 1 / (gamma M^2))
+TGV_REF = (1.0, 0.0, 0.0, 0.0, 1.0 / (1.4 * 0.01) / 0.4)
+
+
 def taylor_green_3d(n=288, jitter=0.2, seed=41, perm_seed=42, scheme="USR5", flux="hllc",
                     steps=100, cfl=0.4, mach=0.1):
     """3-D Euler Taylor-Green vortex at Mach 0.1 in [0, 2 pi]^3 on jittered hexes."""
     L = 2 * np.pi
     mesh = periodic_3d(n, lengths=(L, L, L), jitter=jitter, seed=seed, kinds=HEX,
                        perm_seed=perm_seed)
-    U0 = fields.taylor_green(mach)(fields.cell_points(mesh))
+    U0 = fields.taylor_green(mach)(fields.parent_hex_points(mesh))
     dt = nominal_dt(mesh, "euler", U0, cfl)
     params = dict(pde="euler", scheme=scheme, flux=flux, gamma=fields.GAMMA)
     return Case("taylor_green3d", mesh, params, U0, dt, steps)

@@ -122,6 +122,22 @@ def cell_points(mesh):
     return _interior_points(mesh)[0]
 
 
+def parent_hex_points(mesh):
+    """Corner average of each cell's parent lattice hex (3-D lattice meshes):
+    a cheap sample point for large meshes (exact centre for unsplit hexes
+    up to jitter curvature, the parent's centre for split cells)."""
+    nx, ny, nz = mesh.info["lattice"]
+    h = mesh.info["parent_hex"].astype(np.int64)
+    i, j, k = h % nx, (h // nx) % ny, h // (nx * ny)
+    NX, NY = nx + 1, ny + 1
+    out = np.zeros((h.size, 3))
+    for dk in (0, 1):
+        for dj in (0, 1):
+            for di in (0, 1):
+                out += mesh.nodes[(i + di) + NX * ((j + dj) + NY * (k + dk))]
+    return out / 8.0
+
+
 # --------------------------------------------------------------------------
 # closed-form fields
 # --------------------------------------------------------------------------

@@ -51,9 +51,14 @@ class Mesh:
     def permuted(self, new_of_old: np.ndarray) -> "Mesh":
         """The same mesh with cells relabelled ``c -> new_of_old[c]``."""
         p = np.asarray(new_of_old, dtype=np.int64)
+        info = dict(self.info)
+        if "parent_hex" in info:
+            ph = np.empty_like(info["parent_hex"])
+            ph[p] = info["parent_hex"]
+            info["parent_hex"] = ph
         return Mesh(self.dim, self.nodes, self.face_ptr, self.face_nodes,
                     p[self.owner].astype(np.int32), p[self.neighbour].astype(np.int32),
-                    self.shift, self.n_cells, self.lengths, dict(self.info))
+                    self.shift, self.n_cells, self.lengths, info)
 
 
 def _lattice_coords(n, L, coords):
@@ -448,8 +453,9 @@ def periodic_3d(nx, ny=None, nz=None, lengths=(1.0, 1.0, 1.0), jitter=0.0, seed=
         off += m
     shift = np.concatenate(f_shift)
     counts = np.bincount(kinds, minlength=5)
+    parent = np.repeat(np.arange(nx * ny * nz, dtype=np.int32), nsub[kinds])
     info = {"lattice": n, "n_hex_unsplit": int(counts[HEX]), "n_hex_kuhn": int(counts[KUHN6]),
-            "n_hex_prism": int(counts[PRISM_X:].sum())}
+            "n_hex_prism": int(counts[PRISM_X:].sum()), "parent_hex": parent}
     mesh = Mesh(3, nodes, face_ptr, fn, owner.astype(np.int32), neigh.astype(np.int32),
                 shift, n_cells, tuple(float(x) for x in L), info)
     if perm_seed is not None:
