@@ -3,6 +3,7 @@
 // kernel enqueued on the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -78,7 +79,7 @@ void dfree_t(X*& p) {
 
 void free_work(dolinc_ctx c) {
   Work& w = c->w;
-  dfree(w.sw); dfree(w.dc); dfree(w.rV); dfree(w.G1); dfree(w.G2); dfree(w.W1); dfree(w.W2);
+  dfree(w.sw); dfree(w.ssw); dfree(w.dc); dfree(w.rV); dfree(w.G1); dfree(w.G2); dfree(w.W1); dfree(w.W2);
   dfree_t(w.theta);
   w.scheme = w.precision = -1;
   w.nv = 0;
@@ -91,6 +92,7 @@ void free_all(dolinc_ctx c) {
   free_mlp(c);
   DevMesh& m = c->m;
   dfree_t(m.part_ptr); dfree_t(m.ent_face); dfree_t(m.ent_pn); dfree_t(m.slot_ptr); dfree_t(m.slots);
+  dfree_t(m.slot_o);
   dfree_t(m.face_ent); dfree_t(m.face_own); dfree_t(m.face_nei);
   dfree_t(m.nodes); dfree_t(m.fptr); dfree_t(m.fnodes); dfree_t(m.shift);
   dfree_t(m.V); dfree_t(m.xc); dfree_t(m.S); dfree_t(m.xf); dfree_t(m.fanc); dfree_t(m.omega); dfree_t(m.g);
@@ -169,6 +171,17 @@ hipError_t grad_dispatch(dolinc_ctx c, const void* U, void* G1, void* G2, hipStr
 hipError_t prepare_stage(dolinc_ctx c, const void* U, hipStream_t s) {
   const int ord = scheme_order(c->params.scheme);
   const bool bl = c->params.blend != DOLINC_BLEND_NONE;
+  if (c->params.blend == DOLINC_BLEND_LEARNED && c->dim == 3) {
+    // first gradient fused with the indicator (timed as the indicator)
+    {
+      TimedLaunch t(c, s, 2);
+      hipError_t e = grad_indicator_launch(c, U, c->w.G1, c->w.theta, s);
+      if (e != hipSuccess) return e;
+    }
+    if (ord < 2) return hipSuccess;
+    TimedLaunch t(c, s, 1);
+    return c->w.precision == DOLINC_FP64 ? grad2_f64(c, c->w.G1, c->w.G2, s) : grad2_f32(c, c->w.G1, c->w.G2, s);
+  }
   if (ord >= 1 || bl) {
     hipError_t e = grad_dispatch(c, U, c->w.G1, ord >= 2 ? c->w.G2 : nullptr, s);
     if (e != hipSuccess) return e;
@@ -311,6 +324,7 @@ dolinc_status dolinc_create(const dolinc_mesh_desc* mesh, dolinc_ctx* out) {
     auto dm = [&](double** p, size_t n) {
       if (e == hipSuccess) e = hipMalloc((void**)p, n * sizeof(double));
     };
+    if (e == hipSuccess) e = hipMalloc((void**)&m.slot_o, std::max<size_t>(P.slots.size(), 1) * sizeof(int32_t));
     dm(&m.V, nc);
     dm(&m.xc, 3 * nc);
     dm(&m.S, 3 * (size_t)nf);
@@ -395,6 +409,7 @@ dolinc_status dolinc_precompute(dolinc_ctx c, const dolinc_params* p, dolinc_str
       if (e == hipSuccess) e = hipMalloc(q, bytes ? bytes : 16);
     };
     al(&c->w.sw, ne * 4 * el);
+    al(&c->w.ssw, (size_t)(2 * c->n_faces) * 4 * el);
     al(&c->w.dc, ne * (size_t)dc_stride(p->scheme) * el);
     al(&c->w.rV, nc * el);
     if (ord >= 1 || bl) al(&c->w.G1, nc * nv * c->dim * el);

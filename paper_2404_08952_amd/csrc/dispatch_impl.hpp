@@ -1,6 +1,8 @@
 // Launch-side dispatch from runtime parameters to kernel instantiations.
 // Included once per working type (kernels_f64.hip, kernels_f32.hip).
 #pragma once
+#include <cstdlib>
+
 #include "residual_impl.hpp"
 
 namespace dolinc {
@@ -18,7 +20,9 @@ KArgs<T> base_args(dolinc_ctx_s* c) {
   a.ent_pn = c->m.ent_pn;
   a.slot_ptr = c->m.slot_ptr;
   a.slots = c->m.slots;
+  a.slot_o = c->m.slot_o;
   a.sw = (const T*)c->w.sw;
+  a.ssw = (const T*)c->w.ssw;
   a.dc = (const T*)c->w.dc;
   a.rV = (const T*)c->w.rV;
   a.G1 = (const T*)c->w.G1;
@@ -36,6 +40,18 @@ KArgs<T> base_args(dolinc_ctx_s* c) {
   return a;
 }
 
+// LDS one workgroup may use on the current device (queried once per process).
+inline size_t flux_lds_limit() {
+  static size_t lim = [] {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+      v = 64 * 1024;
+    return (size_t)v;
+  }();
+  return lim;
+}
+
 // pk: 0 advection, 1 Burgers, 2 Euler-Rusanov, 3 Euler-HLLC
 inline int pde_kind(const dolinc_params& p) {
   if (p.pde == DOLINC_ADVECTION) return 0;
@@ -44,13 +60,27 @@ inline int pde_kind(const dolinc_params& p) {
 }
 
 template <class T, int D, int PK, int SCH, bool BL>
-hipError_t go_flux(const KArgs<T>& a, size_t lds, hipStream_t s, bool exporting) {
+hipError_t go_flux(const KArgs<T>& a0, size_t lds, hipStream_t s, bool exporting) {
   if (exporting) {
-    const unsigned nb = (unsigned)((a.nf + KTPB - 1) / KTPB);
-    hipLaunchKernelGGL((k_face_export<T, D, PK, SCH, BL>), dim3(nb), dim3(KTPB), 0, s, a);
-  } else {
-    hipLaunchKernelGGL((k_flux<T, D, PK, SCH, BL>), dim3(8 * a.per_xcd), dim3(KTPB), lds, s, a);
+    const unsigned nb = (unsigned)((a0.nf + KTPB - 1) / KTPB);
+    hipLaunchKernelGGL((k_face_export<T, D, PK, SCH, BL>), dim3(nb), dim3(KTPB), 0, s, a0);
+    return hipGetLastError();
   }
+  using FS = FluxStage<T, D, PK, SCH, BL>;
+  KArgs<T> a = a0;
+  const size_t limit = flux_lds_limit();
+  // Rows are gathered straight from HBM/L2 by default: staging the
+  // partition's own rows in LDS (mask bits 1 G1, 2 G2, 4 U and theta) cost
+  // more in occupancy and the extra barrier than it saved on this workload.
+  int mask = 0;
+  if (const char* env = std::getenv("DOLINC_STAGE_MASK")) {  // tuning override (still bounded by the limit)
+    mask = std::atoi(env) & 7;
+  }
+  if (lds + FS::bytes(a.B, mask) > limit) mask = 0;
+  a.stage_mask = mask;
+  const size_t total = lds + FS::bytes(a.B, mask);
+  if (total > limit) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((k_flux<T, D, PK, SCH, BL>), dim3(8 * a.per_xcd), dim3(KTPB), total, s, a);
   return hipGetLastError();
 }
 

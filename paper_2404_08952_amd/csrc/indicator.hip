@@ -42,6 +42,23 @@ hipError_t indicator_launch(dolinc_ctx_s* c, const void* U, float* theta, hipStr
   return hipGetLastError();
 }
 
+hipError_t grad_indicator_launch(dolinc_ctx_s* c, const void* U, void* G1, float* theta, hipStream_t s) {
+  const int dcs = dc_stride(c->params.scheme);
+  const MlpDev m = mlp_dev(c);
+  if (c->w.precision == DOLINC_FP64) {
+    KArgs<double> a = base_args<double>(c);
+    a.U = (const double*)U;
+    hipLaunchKernelGGL((k_grad_indicator<double, 3>), dim3(8 * a.cell_per_xcd), dim3(KTPB), 0, s, a, dcs, m,
+                       (double*)G1, theta);
+  } else {
+    KArgs<float> a = base_args<float>(c);
+    a.U = (const float*)U;
+    hipLaunchKernelGGL((k_grad_indicator<float, 3>), dim3(8 * a.cell_per_xcd), dim3(KTPB), 0, s, a, dcs, m,
+                       (float*)G1, theta);
+  }
+  return hipGetLastError();
+}
+
 hipError_t mlp_pack_launch(dolinc_ctx_s* c, hipStream_t s) {
   hipLaunchKernelGGL(k_mlp_pack, dim3((MLP_H * MLP_H + 255) / 256), dim3(256), 0, s, c->mlp.p, c->mlp.w1b,
                      c->mlp.w2b);

@@ -29,11 +29,8 @@ constexpr int OFF_W1 = 0, OFF_B1 = MLP_H * MLP_IN, OFF_W2 = OFF_B1 + MLP_H, OFF_
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ unsigned short f2bf(float x) {
-  unsigned u = __float_as_uint(x);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
+// FP32 -> bf16, round to nearest even (v_cvt_pk_bf16_f32 on gfx950)
+__device__ __forceinline__ unsigned short f2bf(float x) { return __builtin_bit_cast(unsigned short, (__bf16)x); }
 __device__ __forceinline__ float bf2f(unsigned short b) { return __uint_as_float(((unsigned)b) << 16); }
 
 __device__ __forceinline__ v4f mfma16(v4s a, v4s b, v4f c) {
@@ -47,17 +44,25 @@ struct MlpDev {
 };
 
 // ---------------------------------------------------------------- features
+
+// tanh through one exponential: tanh x = 1 - 2 / (exp(2x) + 1), |x| clamped
+__device__ __forceinline__ float fast_tanh(float x) {
+  const float y = fminf(fmaxf(x, -15.f), 15.f);
+  const float e = __expf(2.f * y);
+  return 1.f - 2.f * __builtin_amdgcn_rcpf(e + 1.f);
+}
+
 template <class T, int D>
 __device__ __forceinline__ void cell_channels(const T* U, const T* G, T gamma, T* q, T (*gq)[D]) {
   const T rho = U[0];
   T u[D], ke = T(0), mag2 = T(0);
   for (int a = 0; a < D; ++a) {
-    u[a] = U[1 + a] / rho;
+    u[a] = fdiv(U[1 + a], rho);
     ke += U[1 + a] * u[a];
     mag2 += U[1 + a] * U[1 + a];
   }
   const T E = U[D + 1];
-  const T mag = sqrt(mag2);
+  const T mag = fsqrt(mag2);
   q[0] = rho;
   q[1] = (gamma - T(1)) * (E - T(0.5) * ke);
   q[2] = E;
@@ -74,73 +79,102 @@ __device__ __forceinline__ void cell_channels(const T* U, const T* G, T gamma, T
     gq[0][x] = gr;
     gq[1][x] = (gamma - T(1)) * (gE - ugm + T(0.5) * uu * gr);
     gq[2][x] = gE;
-    gq[3][x] = mag > T(1e-30) ? mgm / mag : T(0);
+    gq[3][x] = mag > T(1e-30) ? fdiv(mgm, mag) : T(0);
   }
 }
 
+// Gc: the cell's gradient [NV][D] (from memory or registers)
 template <class T, int D>
-__device__ void cell_features(const KArgs<T>& a, int dcs, int64_t c, float* feat) {
+__device__ void cell_features_from(const KArgs<T>& a, int dcs, int64_t c, const T* Gc, float* feat,
+                                   const T* Ulds = nullptr, int64_t c0 = 0, int n = 0) {
   constexpr int NV = D + 2;
   const int e0 = a.part_ptr[c / a.B];
   const int s0 = a.slot_ptr[c], s1 = a.slot_ptr[c + 1];
   T qc[4], gqc[4][D];
-  cell_channels<T, D>(a.U + c * NV, a.G1 + c * NV * D, a.gamma, qc, gqc);
+  T Uc[NV];
+  load_row<T, NV>(Uc, Ulds, a.U, c0, n, c);
+  cell_channels<T, D>(Uc, Gc, a.gamma, qc, gqc);
   T mx_g0[4], mx_dl[4], mx_b[4], sm_b[4], mn_r[4], mx_sd[4], sm_dl[4];
   for (int k = 0; k < 4; ++k) {
     mx_g0[k] = mx_dl[k] = mx_b[k] = sm_b[k] = mx_sd[k] = sm_dl[k] = T(0);
     mn_r[k] = T(2);
   }
-  for (int s = s0; s < s1; ++s) {
-    const uint16_t sl = a.slots[s];
-    const int64_t e = e0 + (sl & 0x7fff);
-    const bool nb = (sl >> 15) != 0;
-    const int2 pn = a.ent_pn[e];
-    const int64_t o = nb ? pn.x : pn.y;
-    const T* dcp = a.dc + (int64_t)dcs * e;
-    const T sg = nb ? T(-1) : T(1);
-    // neighbour channel values
-    const T* Uo = a.U + o * NV;
-    T qo[4];
-    {
-      const T rho = Uo[0];
-      T ke = T(0), m2 = T(0);
-      for (int x = 0; x < D; ++x) {
-        ke += Uo[1 + x] * Uo[1 + x] / rho;
-        m2 += Uo[1 + x] * Uo[1 + x];
-      }
-      qo[0] = rho;
-      qo[1] = (a.gamma - T(1)) * (Uo[D + 1] - T(0.5) * ke);
-      qo[2] = Uo[D + 1];
-      qo[3] = sqrt(m2);
+  // faces in batches of 4: slot records first, then face vectors and
+  // neighbour rows (a slot past the last is skipped)
+  constexpr int GB = 4;
+  for (int s = s0; s < s1; s += GB) {
+    int64_t o[GB], e[GB];
+    T sg[GB];
+#pragma unroll
+    for (int j = 0; j < GB; ++j) {
+      const int sj = s + j < s1 ? s + j : s0;
+      o[j] = a.slot_o[sj];
+      const uint16_t sl = a.slots[sj];
+      e[j] = e0 + (sl & 0x7fff);
+      sg[j] = (sl >> 15) ? T(-1) : T(1);
     }
-    for (int k = 0; k < 4; ++k) {
-      T g0 = T(0);
-      for (int x = 0; x < D; ++x) g0 += dcp[x] * gqc[k][x];
-      g0 *= T(2) * sg;
-      const T delta = qo[k] - qc[k];
-      const T sd = g0 - delta;
-      const T eps = T(1e-8) * (fabs(qc[k]) + fabs(qo[k])) + T(1e-30);
-      const T beta = fabs(sd - delta) / (fabs(sd) + fabs(delta) + eps);
-      T r = sd * delta / (delta * delta + eps * eps);
-      r = r < T(-2) ? T(-2) : (r > T(2) ? T(2) : r);
-      mx_g0[k] = fmax(mx_g0[k], fabs(g0));
-      mx_dl[k] = fmax(mx_dl[k], fabs(delta));
-      mx_b[k] = fmax(mx_b[k], beta);
-      sm_b[k] += beta;
-      mn_r[k] = fmin(mn_r[k], r);
-      mx_sd[k] = fmax(mx_sd[k], fabs(sd - delta));
-      sm_dl[k] += fabs(delta);
+    T dv[GB][D], Uo[GB][NV];
+#pragma unroll
+    for (int j = 0; j < GB; ++j) {
+      GlbPtr<T> dcp = as_glb(a.dc + (int64_t)dcs * e[j]);
+#pragma unroll
+      for (int x = 0; x < D; ++x) dv[j][x] = dcp[x];
+      load_row<T, NV>(Uo[j], Ulds, a.U, c0, n, o[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < GB; ++j) {
+      if (s + j >= s1) break;
+      // neighbour channel values
+      T qo[4];
+      {
+        const T rho = Uo[j][0];
+        T ke = T(0), m2 = T(0);
+        for (int x = 0; x < D; ++x) {
+          ke += fdiv(Uo[j][1 + x] * Uo[j][1 + x], rho);
+          m2 += Uo[j][1 + x] * Uo[j][1 + x];
+        }
+        qo[0] = rho;
+        qo[1] = (a.gamma - T(1)) * (Uo[j][D + 1] - T(0.5) * ke);
+        qo[2] = Uo[j][D + 1];
+        qo[3] = fsqrt(m2);
+      }
+      for (int k = 0; k < 4; ++k) {
+        T g0 = T(0);
+        for (int x = 0; x < D; ++x) g0 += dv[j][x] * gqc[k][x];
+        g0 *= T(2) * sg[j];
+        const T delta = qo[k] - qc[k];
+        const T sd = g0 - delta;
+        const T eps = T(1e-8) * (fabs(qc[k]) + fabs(qo[k])) + T(1e-30);
+        const T beta = fdiv(fabs(sd - delta), fabs(sd) + fabs(delta) + eps);
+        // eps^2 underflows in FP32 when both channel values are 0; the
+        // ratio is then 0 (as in exact arithmetic, where Delta = 0 gives 0)
+        const T den = delta * delta + eps * eps;
+        T r = den > T(0) ? fdiv(sd * delta, den) : T(0);
+        r = r < T(-2) ? T(-2) : (r > T(2) ? T(2) : r);
+        mx_g0[k] = fmax(mx_g0[k], fabs(g0));
+        mx_dl[k] = fmax(mx_dl[k], fabs(delta));
+        mx_b[k] = fmax(mx_b[k], beta);
+        sm_b[k] += beta;
+        mn_r[k] = fmin(mn_r[k], r);
+        mx_sd[k] = fmax(mx_sd[k], fabs(sd - delta));
+        sm_dl[k] += fabs(delta);
+      }
     }
   }
   const T inv = T(1) / (T)(s1 - s0);
   for (int k = 0; k < 4; ++k) {
-    const T scale = fabs(qc[k]) + sm_dl[k] * inv + T(1e-8);
-    T f[6] = {mx_g0[k] / scale, mx_dl[k] / scale, mx_b[k], sm_b[k] * inv, mn_r[k], mx_sd[k] / scale};
+    const T rs = fdiv(T(1), fabs(qc[k]) + sm_dl[k] * inv + T(1e-8));
+    T f[6] = {mx_g0[k] * rs, mx_dl[k] * rs, mx_b[k], sm_b[k] * inv, mn_r[k], mx_sd[k] * rs};
     for (int j = 0; j < 6; ++j) {
       T v = f[j] < T(-8) ? T(-8) : (f[j] > T(8) ? T(8) : f[j]);
       feat[6 * k + j] = (float)v;
     }
   }
+}
+
+template <class T, int D>
+__device__ __forceinline__ void cell_features(const KArgs<T>& a, int dcs, int64_t c, float* feat) {
+  cell_features_from<T, D>(a, dcs, c, a.G1 + c * (D + 2) * D, feat);
 }
 
 template <class T, int D>
@@ -190,13 +224,13 @@ __device__ __forceinline__ void load_weights(const MlpDev& m, MlpRegs& R) {
 // beyond nrow read as zero).  Outputs in D layout (lane: units 16t+4g+i of
 // cell l%16): H1 (fp32), H2 (fp32); returns theta of cell l % 16.
 __device__ __forceinline__ float mlp_tile_fwd(const MlpDev& m, const MlpRegs& R, const unsigned short* X, int nrow,
-                                              v4f* H1, v4f* H2, float* z3out) {
+                                              v4f* H1, v4f* H2, float* z3out, int xstride = MLP_INP) {
   const int l = threadIdx.x & 63;
   const int r = l & 15, g = l >> 4;
   v4s xb[2];
   for (int kk = 0; kk < 2; ++kk) {
     if (r < nrow)
-      xb[kk] = load4(X + r * MLP_INP + 16 * kk + 4 * g);
+      xb[kk] = load4(X + r * xstride + 16 * kk + 4 * g);
     else
       xb[kk] = v4s{0, 0, 0, 0};
   }
@@ -206,7 +240,7 @@ __device__ __forceinline__ float mlp_tile_fwd(const MlpDev& m, const MlpRegs& R,
     for (int i = 0; i < 4; ++i) acc[i] = m.p[OFF_B1 + 16 * t + 4 * g + i];
     for (int kk = 0; kk < 2; ++kk) acc = mfma16(R.w1[t][kk], xb[kk], acc);
     v4f h;
-    for (int i = 0; i < 4; ++i) h[i] = tanhf(acc[i]);
+    for (int i = 0; i < 4; ++i) h[i] = fast_tanh(acc[i]);
     H1[t] = h;
     h1b[t] = v4s{(short)f2bf(h[0]), (short)f2bf(h[1]), (short)f2bf(h[2]), (short)f2bf(h[3])};
   }
@@ -217,7 +251,7 @@ __device__ __forceinline__ float mlp_tile_fwd(const MlpDev& m, const MlpRegs& R,
     for (int kk = 0; kk < 4; ++kk) acc = mfma16(R.w2[t][kk], h1b[kk], acc);
     v4f h;
     for (int i = 0; i < 4; ++i) {
-      h[i] = tanhf(acc[i]);
+      h[i] = fast_tanh(acc[i]);
       part += m.p[OFF_W3 + 16 * t + 4 * g + i] * h[i];
     }
     H2[t] = h;
@@ -226,7 +260,7 @@ __device__ __forceinline__ float mlp_tile_fwd(const MlpDev& m, const MlpRegs& R,
   part += __shfl_xor(part, 32, 64);
   const float z3 = part + m.p[OFF_B3];
   *z3out = z3;
-  return 1.f / (1.f + expf(-z3));
+  return __builtin_amdgcn_rcpf(1.f + __expf(-z3));
 }
 
 __global__ __launch_bounds__(256) void k_mlp_fwd(MlpDev m, const unsigned short* __restrict__ X, int64_t n,
@@ -463,6 +497,57 @@ __global__ __launch_bounds__(KTPB) void k_indicator(KArgs<T> a, int dcs, MlpDev 
     v4f H1[4], H2[4];
     float z3;
     const float th = mlp_tile_fwd(m, R, xs + (64 * w + 16 * t) * MLP_INP, nrow, H1, H2, &z3);
+    if (l < nrow) theta[row0 + l] = th;
+  }
+}
+
+// First gradient fused with the learned indicator: the cell's Gauss-linear
+// gradient is stored and, still in registers, feeds the features; the
+// network then runs on the block's cells from LDS.  Same arithmetic as
+// k_grad + k_features + k_mlp_fwd, so theta is identical.
+template <class T, int D>
+__global__ __launch_bounds__(KTPB) void k_grad_indicator(KArgs<T> a, int dcs, MlpDev m, T* __restrict__ G1out,
+                                                          float* __restrict__ theta) {
+  constexpr int NV = D + 2;
+  constexpr int XS = MLP_INP + 2;  // padded row stride (shorts) against LDS bank conflicts
+  __shared__ unsigned short xs[KTPB * XS];
+  __shared__ T ul[KTPB * NV];
+  const int b = xcd_remap(blockIdx.x, a.cell_per_xcd, a.n_cell_blocks);
+  if (b < 0) return;
+  const int64_t c0 = (int64_t)b * KTPB;
+  const int ncl = (int)(a.nc - c0 < KTPB ? a.nc - c0 : KTPB);
+  stage_rows(ul, a.U, c0, ncl, NV);
+  __syncthreads();
+  const int64_t c = c0 + threadIdx.x;
+  unsigned short* row = xs + threadIdx.x * XS;
+  if (c < a.nc) {
+    T acc[NV][D];
+    grad_sums<T, D, NV>(a, a.U, c, acc, ul, c0, ncl);
+    const T rv = a.rV[c];
+    T g[NV * D];
+    for (int k = 0; k < NV; ++k)
+      for (int x = 0; x < D; ++x) {
+        g[k * D + x] = acc[k][x] * rv;
+        G1out[(c * NV + k) * D + x] = g[k * D + x];
+      }
+    float f[MLP_IN];
+    cell_features_from<T, D>(a, dcs, c, g, f, ul, c0, ncl);
+    for (int j = 0; j < MLP_IN; ++j) row[j] = f2bf(f[j]);
+  } else {
+    for (int j = 0; j < MLP_IN; ++j) row[j] = 0;
+  }
+  for (int j = MLP_IN; j < MLP_INP; ++j) row[j] = 0;
+  __syncthreads();
+  MlpRegs R;
+  load_weights(m, R);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  for (int t = 0; t < 4; ++t) {
+    const int64_t row0 = c0 + 64 * w + 16 * t;
+    if (row0 >= a.nc) break;
+    const int nrow = (int)((a.nc - row0) < 16 ? (a.nc - row0) : 16);
+    v4f H1[4], H2[4];
+    float z3;
+    const float th = mlp_tile_fwd(m, R, xs + (64 * w + 16 * t) * XS, nrow, H1, H2, &z3, XS);
     if (l < nrow) theta[row0 + l] = th;
   }
 }

@@ -15,6 +15,12 @@ namespace dolinc {
 //   sw[e][4]  : S_x, S_y, S_z (0 in 2-D), omega (owner weight)
 //   dc[e][DC] : d_x, d_y, d_z, then the coefficients of the DOLINC
 //               representation of each side (see kernels for the meaning).
+// Per-slot record (one per cell-face incidence, contiguous per cell):
+//   ssw[s][4] : w_o S_x, w_o S_y, w_o S_z, sign; S is the face area vector
+//               oriented owner -> neighbour, sign = +1 on the owner side and
+//               -1 on the neighbour side, and w_o = sign * (weight of the
+//               other cell in the face interpolation), so the Gauss-linear
+//               sum of a cell is sum_s (phi_o - phi_c) ssw[s][0..D).
 inline int coef_left(int scheme) { return scheme <= 2 ? 1 : scheme == 3 ? 2 : scheme == 4 ? 3 : 4; }
 inline int coef_right(int scheme) { return scheme <= 2 ? 1 : scheme == 3 ? 2 : scheme == 4 ? 0 : 4; }
 inline int dc_stride(int scheme) {
@@ -30,6 +36,7 @@ struct DevMesh {
   int2* ent_pn = nullptr;
   int32_t* slot_ptr = nullptr;
   uint16_t* slots = nullptr;
+  int32_t* slot_o = nullptr;     // per slot: the cell on the other side of the face
   int32_t* face_ent = nullptr;   // one entry per caller face
   int32_t* face_own = nullptr;   // internal owner per caller face
   int32_t* face_nei = nullptr;
@@ -63,6 +70,7 @@ struct Mlp {
 
 struct Work {
   void* sw = nullptr;
+  void* ssw = nullptr;
   void* dc = nullptr;
   void* rV = nullptr;
   void* G1 = nullptr;
@@ -114,6 +122,7 @@ hipError_t launch_diagnostics(dolinc_ctx_s* c, const void* U, double* out_host, 
 bool flux_supported(const dolinc_params& p, int dim);
 hipError_t features_launch(dolinc_ctx_s* c, const void* U, float* X32, unsigned short* Xb, hipStream_t s);
 hipError_t indicator_launch(dolinc_ctx_s* c, const void* U, float* theta, hipStream_t s);
+hipError_t grad_indicator_launch(dolinc_ctx_s* c, const void* U, void* G1, float* theta, hipStream_t s);
 hipError_t mlp_pack_launch(dolinc_ctx_s* c, hipStream_t s);
 hipError_t mlp_forward_launch(dolinc_ctx_s* c, const unsigned short* X, int64_t n, float* theta, hipStream_t s);
 hipError_t mlp_grad_launch(dolinc_ctx_s* c, const unsigned short* X, const float* y, int64_t n, int nblocks,

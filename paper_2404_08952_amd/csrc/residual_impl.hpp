@@ -35,7 +35,9 @@ struct KArgs {
   const int2* ent_pn;
   const int32_t* slot_ptr;
   const uint16_t* slots;
+  const int32_t* slot_o;
   const T* sw;
+  const T* ssw;
   const T* dc;
   const T* rV;
   const T* U;
@@ -51,6 +53,7 @@ struct KArgs {
   T bdir[3];
   int use_ref;
   T uref[5];
+  int stage_mask;  // k_flux rows staged in LDS: 1 G1, 2 G2, 4 U and theta
   const int32_t* face_ent;
   int64_t nf;
   T* eUL;
@@ -79,10 +82,105 @@ struct SchemeInfo {
   static constexpr int DCS = (3 + NL + NR + 3) & ~3;
 };
 
+// A partition's cells are a contiguous index range, so their rows of a
+// per-cell array are staged into LDS with coalesced loads; a gathered row is
+// then read from LDS when the cell is local and from global memory when it
+// belongs to another partition (generic pointers pick the address space).
+template <class T>
+__device__ __forceinline__ void stage_rows(T* __restrict__ lds, const T* __restrict__ g, int64_t c0, int n, int w) {
+  const int64_t base = c0 * w;
+  for (int i = threadIdx.x; i < n * w; i += blockDim.x) lds[i] = g[base + i];
+}
+
+// Pointers with an explicit address space: the compiler may otherwise merge
+// an LDS branch and an HBM branch into one generic (flat) load.
+template <class T>
+using LdsPtr = const T __attribute__((address_space(3)))*;
+template <class T>
+using GlbPtr = const T __attribute__((address_space(1)))*;
+
+template <class T>
+__device__ __forceinline__ LdsPtr<T> as_lds(const T* p) {
+  return (LdsPtr<T>)p;
+}
+template <class T>
+__device__ __forceinline__ GlbPtr<T> as_glb(const T* p) {
+  return (GlbPtr<T>)p;
+}
+
+// Copy row `row` (W values) into registers, from LDS when the row is one of
+// the n staged rows starting at c0, else from HBM.
+template <class T, int W>
+__device__ __forceinline__ void load_row(T* dst, const T* lds, const T* __restrict__ g, int64_t c0, int n,
+                                         int64_t row) {
+  const int64_t r = row - c0;
+  if (r >= 0 && r < n) {
+    LdsPtr<T> src = as_lds(lds + r * W);
+#pragma unroll
+    for (int k = 0; k < W; ++k) dst[k] = src[k];
+  } else {
+    GlbPtr<T> src = as_glb(g + row * W);
+#pragma unroll
+    for (int k = 0; k < W; ++k) dst[k] = src[k];
+  }
+}
+
+// out[v] = sum_x d_x row[v*D + x] for a row of NV*D values
+template <class T, int NV, int D, class P>
+__device__ __forceinline__ void contract1(P src, const T* d, T* out) {
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    T acc = T(0);
+#pragma unroll
+    for (int x = 0; x < D; ++x) acc += d[x] * src[v * D + x];
+    out[v] = acc;
+  }
+}
+
+// out[v] = d . sym(G2_v) . d for a row of NV * D(D+1)/2 values
+template <class T, int NV, int D, class P>
+__device__ __forceinline__ void contract2(P src, const T* d, T* out) {
+  constexpr int NS2 = D * (D + 1) / 2;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    P h = src + v * NS2;
+    T acc = T(0);
+#pragma unroll
+    for (int x = 0; x < D; ++x) acc += h[x] * d[x] * d[x];
+    if constexpr (D == 3) {
+      acc += h[3] * (T(2) * d[0] * d[1]) + h[4] * (T(2) * d[0] * d[2]) + h[5] * (T(2) * d[1] * d[2]);
+    } else {
+      acc += h[2] * (T(2) * d[0] * d[1]);
+    }
+    out[v] = acc;
+  }
+}
+
+template <class T, int NV, int D, int ORD>
+__device__ __forceinline__ void contract_cell(const T* lds, const T* __restrict__ g, int64_t c0, int n, int64_t row,
+                                              const T* d, T* out) {
+  constexpr int W = ORD == 1 ? NV * D : NV * D * (D + 1) / 2;
+  const int64_t r = row - c0;
+  if (r >= 0 && r < n) {
+    if constexpr (ORD == 1) contract1<T, NV, D>(as_lds(lds + r * W), d, out);
+    else contract2<T, NV, D>(as_lds(lds + r * W), d, out);
+  } else {
+    if constexpr (ORD == 1) contract1<T, NV, D>(as_glb(g + row * W), d, out);
+    else contract2<T, NV, D>(as_glb(g + row * W), d, out);
+  }
+}
+
+// FP32 quotient and square root on the hardware reciprocal / square-root
+// units (about 1 ulp, no correction sequence); FP64 stays correctly rounded.
+__device__ __forceinline__ float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double fdiv(double a, double b) { return a / b; }
+__device__ __forceinline__ float fsqrt(float a) { return __builtin_amdgcn_sqrtf(a); }
+__device__ __forceinline__ double fsqrt(double a) { return sqrt(a); }
+
 template <class T>
 __device__ __forceinline__ T vanleer_inc(T s, T delta) {
   const T prod = s * delta;
-  return prod > T(0) ? T(2) * prod / (s + delta) : T(0);
+  return prod > T(0) ? fdiv(T(2) * prod, s + delta) : T(0);
 }
 
 // ---------------------------------------------------------------- Euler fluxes
@@ -91,7 +189,7 @@ __device__ __forceinline__ void euler_prim(const T* U, T gamma, T& r, T* v, T& E
   r = U[0];
   T ke = T(0);
   for (int a = 0; a < D; ++a) {
-    v[a] = U[1 + a] / r;
+    v[a] = fdiv(U[1 + a], r);
     ke += v[a] * U[1 + a];
   }
   E = U[D + 1];
@@ -111,7 +209,7 @@ template <class T, int D>
 __device__ __forceinline__ void flux_rusanov(const T* UL, const T* UR, const T* S, T gamma, T* F) {
   T area2 = T(0);
   for (int a = 0; a < D; ++a) area2 += S[a] * S[a];
-  const T area = sqrt(area2);
+  const T area = fsqrt(area2);
   T rL, vL[D], EL, pL, rR, vR[D], ER, pR;
   euler_prim<T, D>(UL, gamma, rL, vL, EL, pL);
   euler_prim<T, D>(UR, gamma, rR, vR, ER, pR);
@@ -120,9 +218,9 @@ __device__ __forceinline__ void flux_rusanov(const T* UL, const T* UR, const T* 
     qL += vL[a] * S[a];
     qR += vR[a] * S[a];
   }
-  qL /= area;
-  qR /= area;
-  const T cL = sqrt(gamma * pL / rL), cR = sqrt(gamma * pR / rR);
+  qL = fdiv(qL, area);
+  qR = fdiv(qR, area);
+  const T cL = fsqrt(fdiv(gamma * pL, rL)), cR = fsqrt(fdiv(gamma * pR, rR));
   const T lam = fmax(fabs(qL) + cL, fabs(qR) + cR);
   T FL[D + 2], FR[D + 2];
   euler_phys<T, D>(UL, rL, vL, EL, pL, S, FL);
@@ -135,9 +233,9 @@ template <class T, int D>
 __device__ __forceinline__ void flux_hllc(const T* UL, const T* UR, const T* S, T gamma, T* F) {
   T area2 = T(0);
   for (int a = 0; a < D; ++a) area2 += S[a] * S[a];
-  const T area = sqrt(area2);
+  const T area = fsqrt(area2);
   T n[D];
-  for (int a = 0; a < D; ++a) n[a] = S[a] / area;
+  for (int a = 0; a < D; ++a) n[a] = fdiv(S[a], area);
   T rL, vL[D], EL, pL, rR, vR[D], ER, pR;
   euler_prim<T, D>(UL, gamma, rL, vL, EL, pL);
   euler_prim<T, D>(UR, gamma, rR, vR, ER, pR);
@@ -146,10 +244,10 @@ __device__ __forceinline__ void flux_hllc(const T* UL, const T* UR, const T* S, 
     qL += vL[a] * n[a];
     qR += vR[a] * n[a];
   }
-  const T cL = sqrt(gamma * pL / rL), cR = sqrt(gamma * pR / rR);
+  const T cL = fsqrt(fdiv(gamma * pL, rL)), cR = fsqrt(fdiv(gamma * pR, rR));
   const T SL = fmin(qL - cL, qR - cR);
   const T SR = fmax(qL + cL, qR + cR);
-  const T Ss = (pR - pL + rL * qL * (SL - qL) - rR * qR * (SR - qR)) / (rL * (SL - qL) - rR * (SR - qR));
+  const T Ss = fdiv(pR - pL + rL * qL * (SL - qL) - rR * qR * (SR - qR), rL * (SL - qL) - rR * (SR - qR));
   // choose the side: the flux is F_K (+ S_K (U*_K - U_K) inside the fan)
   const bool left = SL >= T(0) || Ss >= T(0);
   const T* UK = left ? UL : UR;
@@ -161,11 +259,11 @@ __device__ __forceinline__ void flux_hllc(const T* UL, const T* UR, const T* S, 
   euler_phys<T, D>(UK, rK, vK, EK, pK, n, FK);
   const bool star = left ? (SL < T(0)) : (SR > T(0));
   if (star) {
-    const T fac = rK * (SK - qK) / (SK - Ss);
+    const T fac = fdiv(rK * (SK - qK), SK - Ss);
     T Us[D + 2];
     Us[0] = fac;
     for (int a = 0; a < D; ++a) Us[1 + a] = fac * (vK[a] + (Ss - qK) * n[a]);
-    Us[D + 1] = fac * (EK / rK + (Ss - qK) * (Ss + pK / (rK * (SK - qK))));
+    Us[D + 1] = fac * (fdiv(EK, rK) + (Ss - qK) * (Ss + fdiv(pK, rK * (SK - qK))));
     for (int k = 0; k < D + 2; ++k) FK[k] += SK * (Us[k] - UK[k]);
   }
   for (int k = 0; k < D + 2; ++k) F[k] = FK[k] * area;
@@ -194,7 +292,7 @@ __device__ __forceinline__ void ref_state(const T* uref, T gamma, RefState<T, D>
   T k = T(0);
   for (int a = 0; a < D; ++a) {
     R.m[a] = uref[1 + a];
-    R.u[a] = uref[1 + a] / uref[0];
+    R.u[a] = fdiv(uref[1 + a], uref[0]);
     k += R.m[a] * R.u[a];
   }
   R.E = uref[D + 1];
@@ -211,7 +309,7 @@ __device__ __forceinline__ void pert_state(const T* dU, const RefState<T, D>& R,
   P.r = R.r + dU[0];
   T dk = T(0);
   for (int a = 0; a < D; ++a) {
-    P.du[a] = (dU[1 + a] - R.u[a] * dU[0]) / P.r;
+    P.du[a] = fdiv(dU[1 + a] - R.u[a] * dU[0], P.r);
     P.u[a] = R.u[a] + P.du[a];
     dk += dU[1 + a] * P.u[a] + R.m[a] * P.du[a];
   }
@@ -248,10 +346,10 @@ __device__ __forceinline__ void flux_rusanov_pert(const T* dL, const T* dR, cons
     qL += PL.u[a] * S[a];
     qR += PR.u[a] * S[a];
   }
-  const T area = sqrt(area2);
-  qL /= area;
-  qR /= area;
-  const T cL = sqrt(gamma * PL.p / PL.r), cR = sqrt(gamma * PR.p / PR.r);
+  const T area = fsqrt(area2);
+  qL = fdiv(qL, area);
+  qR = fdiv(qR, area);
+  const T cL = fsqrt(fdiv(gamma * PL.p, PL.r)), cR = fsqrt(fdiv(gamma * PR.p, PR.r));
   const T lam = fmax(fabs(qL) + cL, fabs(qR) + cR);
   T FL[D + 2], FR[D + 2];
   pert_flux<T, D>(dL, PL, R, S, FL);
@@ -273,22 +371,22 @@ __device__ __forceinline__ void flux_hllc_pert(const T* dL, const T* dR, const T
   pert_state<T, D>(dR, R, gamma, PR);
   T area2 = T(0);
   for (int a = 0; a < D; ++a) area2 += S[a] * S[a];
-  const T area = sqrt(area2);
+  const T area = fsqrt(area2);
   T n[D];
-  for (int a = 0; a < D; ++a) n[a] = S[a] / area;
+  for (int a = 0; a < D; ++a) n[a] = fdiv(S[a], area);
   T qL = T(0), qR = T(0), dqLR = T(0);
   for (int a = 0; a < D; ++a) {
     qL += PL.u[a] * n[a];
     qR += PR.u[a] * n[a];
     dqLR += (PR.du[a] - PL.du[a]) * n[a];
   }
-  const T cL = sqrt(gamma * PL.p / PL.r), cR = sqrt(gamma * PR.p / PR.r);
+  const T cL = fsqrt(fdiv(gamma * PL.p, PL.r)), cR = fsqrt(fdiv(gamma * PR.p, PR.r));
   const T SL = fmin(qL - cL, qR - cR);
   const T SR = fmax(qL + cL, qR + cR);
   const T aL = PL.r * (SL - qL), aR = PR.r * (SR - qR);
   const T dpLR = PR.dp - PL.dp;
-  const T sL = (dpLR - aR * dqLR) / (aL - aR);  // S* - q_L
-  const T sR = (dpLR - aL * dqLR) / (aL - aR);  // S* - q_R
+  const T sL = fdiv(dpLR - aR * dqLR, aL - aR);  // S* - q_L
+  const T sR = fdiv(dpLR - aL * dqLR, aL - aR);  // S* - q_R
   const T Ss = qL + sL;
   const bool left = SL >= T(0) || Ss >= T(0);
   const T* dK = left ? dL : dR;
@@ -301,11 +399,11 @@ __device__ __forceinline__ void flux_hllc_pert(const T* dL, const T* dR, const T
     const T sK = left ? sL : sR;
     const T qK = left ? qL : qR;
     const T EK = R.E + dK[D + 1];
-    const T fr = PK.r * sK / (SK - Ss);  // fac - rho_K
+    const T fr = fdiv(PK.r * sK, SK - Ss);  // fac - rho_K
     const T fac = PK.r + fr;
     FK[0] += SK * fr;
     for (int a = 0; a < D; ++a) FK[1 + a] += SK * (fr * PK.u[a] + fac * sK * n[a]);
-    FK[D + 1] += SK * (fr * EK / PK.r + fac * sK * (Ss + PK.p / (PK.r * (SK - qK))));
+    FK[D + 1] += SK * (fdiv(fr * EK, PK.r) + fac * sK * (Ss + fdiv(PK.p, PK.r * (SK - qK))));
   }
   for (int k = 0; k < D + 2; ++k) F[k] = FK[k] * area;
 }
@@ -313,8 +411,23 @@ __device__ __forceinline__ void flux_hllc_pert(const T* dL, const T* dR, const T
 // ---------------------------------------------------------------- face evaluation
 // Loads one face entry, reconstructs (U_L, U_R) and returns the
 // face-integrated flux F.S (owner -> neighbour).
+// Optional LDS copies of the current partition's cell rows (k_flux).
+template <class T>
+struct Stage {
+  // Rows c0 .. c0+n* of each array held in LDS (n* = 0: read it from HBM).
+  // The pointers always point into LDS (never null) so that loads through
+  // them stay LDS loads.
+  const T* U = nullptr;
+  const T* G1 = nullptr;
+  const T* G2 = nullptr;
+  const float* th = nullptr;
+  int64_t c0 = 0;
+  int nU = 0, nG1 = 0, nG2 = 0, nth = 0;
+};
+
 template <class T, int D, int PK, int SCH, bool BLEND>
-__device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T* UR, T* F) {
+__device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T* UR, T* F,
+                                          const Stage<T>& st = Stage<T>()) {
   constexpr int NV = NVars<PK, D>::value;
   constexpr int ORD = SchemeInfo<SCH>::ORD;
   constexpr int DCS = SchemeInfo<SCH>::DCS;
@@ -331,50 +444,25 @@ __device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T
   T uP[NV], uN[NV];
   // Euler with a reference state: reconstruct perturbations U - U_ref
   const bool pert = PK >= 2 && a.use_ref;
+  load_row<T, NV>(uP, st.U, a.U, st.c0, st.nU, P);
+  load_row<T, NV>(uN, st.U, a.U, st.c0, st.nU, N);
+  if (pert) {
 #pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    const T r = pert ? a.uref[v] : T(0);
-    uP[v] = a.U[P * NV + v] - r;
-    uN[v] = a.U[N * NV + v] - r;
+    for (int v = 0; v < NV; ++v) {
+      uP[v] -= a.uref[v];
+      uN[v] -= a.uref[v];
+    }
   }
   T gP[NV], gN[NV], hP[NV], hN[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) gP[v] = gN[v] = hP[v] = hN[v] = T(0);
   if constexpr (ORD >= 1 || BLEND) {
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const T* gp = a.G1 + (P * NV + v) * D;
-      const T* gn = a.G1 + (N * NV + v) * D;
-#pragma unroll
-      for (int x = 0; x < D; ++x) {
-        gP[v] += dc[x] * gp[x];
-        gN[v] += dc[x] * gn[x];
-      }
-    }
+    contract_cell<T, NV, D, 1>(st.G1, a.G1, st.c0, st.nG1, P, dc, gP);
+    contract_cell<T, NV, D, 1>(st.G1, a.G1, st.c0, st.nG1, N, dc, gN);
   }
   if constexpr (ORD >= 2) {
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const T* hp = a.G2 + (P * NV + v) * NS2;
-      const T* hn = a.G2 + (N * NV + v) * NS2;
-      T sp = T(0), sn = T(0);
-#pragma unroll
-      for (int x = 0; x < D; ++x) {
-        sp += hp[x] * dc[x] * dc[x];
-        sn += hn[x] * dc[x] * dc[x];
-      }
-      if constexpr (D == 3) {
-        const T dxy = T(2) * dc[0] * dc[1], dxz = T(2) * dc[0] * dc[2], dyz = T(2) * dc[1] * dc[2];
-        sp += hp[3] * dxy + hp[4] * dxz + hp[5] * dyz;
-        sn += hn[3] * dxy + hn[4] * dxz + hn[5] * dyz;
-      } else {
-        const T dxy = T(2) * dc[0] * dc[1];
-        sp += hp[2] * dxy;
-        sn += hn[2] * dxy;
-      }
-      hP[v] = sp;
-      hN[v] = sn;
-    }
+    contract_cell<T, NV, D, 2>(st.G2, a.G2, st.c0, st.nG2, P, dc, hP);
+    contract_cell<T, NV, D, 2>(st.G2, a.G2, st.c0, st.nG2, N, dc, hN);
   }
   // reconstruction in the DOLINC representation (coefficients from precompute)
 #pragma unroll
@@ -394,7 +482,10 @@ __device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T
     }
   }
   if constexpr (BLEND) {
-    const T tf = (T)fminf(a.theta[P], a.theta[N]);
+    float thP, thN;
+    load_row<float, 1>(&thP, st.th, a.theta, st.c0, st.nth, P);
+    load_row<float, 1>(&thN, st.th, a.theta, st.c0, st.nth, N);
+    const T tf = (T)fminf(thP, thN);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       const T dL = uN[v] - uP[v];
@@ -465,23 +556,79 @@ __device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T
 }
 
 // ---------------------------------------------------------------- kernels
+// Rows of one cell staged by k_flux: U, G1 (if used), G2 (FP32 only), theta.
+template <class T, int D, int PK, int SCH, bool BLEND>
+struct FluxStage {
+  static constexpr int NV = NVars<PK, D>::value;
+  static constexpr bool G1 = SchemeInfo<SCH>::ORD >= 1 || BLEND;
+  static constexpr bool G2 = SchemeInfo<SCH>::ORD >= 2;
+  // bytes of LDS for the staged rows of B cells (theta as T-sized slots)
+  static constexpr size_t bytes(int B, int mask) {
+    return (size_t)B *
+           ((mask & 4 ? NV + (BLEND ? 1 : 0) : 0) + ((mask & 1) && G1 ? NV * D : 0) +
+            ((mask & 2) && G2 ? NV * D * (D + 1) / 2 : 0)) *
+           sizeof(T);
+  }
+};
+
 template <class T, int D, int PK, int SCH, bool BLEND>
 __global__ __launch_bounds__(KTPB) void k_flux(KArgs<T> a) {
   constexpr int NV = NVars<PK, D>::value;
+  using FS = FluxStage<T, D, PK, SCH, BLEND>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* Fs = reinterpret_cast<T*>(smem_raw);
   const int p = xcd_remap(blockIdx.x, a.per_xcd, a.np);
   if (p < 0) return;
+  const int64_t c0 = (int64_t)p * a.B;
+  const int ncl = (int)(a.nc - c0 < a.B ? a.nc - c0 : a.B);
+  // LDS: staged cell rows, then the face fluxes
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  Stage<T> st;
+  st.c0 = c0;
+  st.U = st.G1 = st.G2 = lds;
+  st.th = reinterpret_cast<const float*>(lds);
+  size_t off = 0;
+  if (a.stage_mask & 4) {
+    stage_rows(lds + off, a.U, c0, ncl, NV);
+    st.nU = ncl;
+    off += (size_t)a.B * NV;
+  }
+  if constexpr (FS::G1) {
+    if (a.stage_mask & 1) {
+      stage_rows(lds + off, a.G1, c0, ncl, NV * D);
+      st.G1 = lds + off;
+      st.nG1 = ncl;
+      off += (size_t)a.B * NV * D;
+    }
+  }
+  if constexpr (FS::G2) {
+    if (a.stage_mask & 2) {
+      constexpr int NS2 = D * (D + 1) / 2;
+      stage_rows(lds + off, a.G2, c0, ncl, NV * NS2);
+      st.G2 = lds + off;
+      st.nG2 = ncl;
+      off += (size_t)a.B * NV * NS2;
+    }
+  }
+  if constexpr (BLEND) {
+    if (a.stage_mask & 4) {
+      float* thl = reinterpret_cast<float*>(lds + off);
+      stage_rows(thl, a.theta, c0, ncl, 1);
+      st.th = thl;
+      st.nth = ncl;
+      off += (size_t)a.B;
+    }
+  }
+  T* Fs = lds + off;
+  __syncthreads();
   const int e0 = a.part_ptr[p], e1 = a.part_ptr[p + 1];
   for (int e = e0 + (int)threadIdx.x; e < e1; e += KTPB) {
     T UL[NV], UR[NV], F[NV];
-    eval_face<T, D, PK, SCH, BLEND>(a, e, UL, UR, F);
+    eval_face<T, D, PK, SCH, BLEND>(a, e, UL, UR, F, st);
 #pragma unroll
     for (int v = 0; v < NV; ++v) Fs[(e - e0) * NV + v] = F[v];
   }
   __syncthreads();
-  const int64_t c0 = (int64_t)p * a.B;
-  const int64_t c1 = c0 + a.B < a.nc ? c0 + a.B : a.nc;
+  const int64_t c1 = c0 + ncl;
   for (int64_t c = c0 + threadIdx.x; c < c1; c += KTPB) {
     const int s0 = a.slot_ptr[c], s1 = a.slot_ptr[c + 1];
     T sum[NV], comp[NV];
@@ -535,41 +682,63 @@ __global__ __launch_bounds__(KTPB) void k_face_export(KArgs<T> a) {
 // Cell-centric Gauss-linear gradient of phi [nc][NQ] -> out [nc][NQ][D].
 // SYM: NQ = NV*D input components (a gradient) and the output is the
 // symmetrised second derivative [nc][NV][D(D+1)/2].
-template <class T, int D, int NQ, bool SYM>
-__global__ __launch_bounds__(KTPB) void k_grad(KArgs<T> a, const T* __restrict__ phi, T* __restrict__ out) {
-  const int b = xcd_remap(blockIdx.x, a.cell_per_xcd, a.n_cell_blocks);
-  if (b < 0) return;
-  const int64_t c = (int64_t)b * KTPB + threadIdx.x;
-  if (c >= a.nc) return;
-  const int e0 = a.part_ptr[c / a.B];
+// Gauss-linear sums of cell c: acc[k][x] = sum_f sigma S_f,x w (phi_o - phi_c)_k
+// The faces of a cell are taken GB at a time: the per-slot records of a
+// batch are loaded together, then the batch's neighbour rows, so that one
+// cell waits on two memory latencies per batch rather than three per face.
+// A slot past the cell's last one reads the cell's own row with a zero
+// weight (phi_c - phi_c = 0 exactly), which leaves the sums unchanged.
+template <class T, int D, int NQ>
+__device__ __forceinline__ void grad_sums(const KArgs<T>& a, const T* __restrict__ phi, int64_t c, T (*acc)[D],
+                                          const T* lds = nullptr, int64_t c0 = 0, int n = 0) {
+  constexpr int GB = NQ <= 5 ? 4 : 2;
   const int s0 = a.slot_ptr[c], s1 = a.slot_ptr[c + 1];
   T q[NQ];
-#pragma unroll
-  for (int k = 0; k < NQ; ++k) q[k] = phi[c * NQ + k];
-  T acc[NQ][D];
+  load_row<T, NQ>(q, lds, phi, c0, n, c);
 #pragma unroll
   for (int k = 0; k < NQ; ++k)
 #pragma unroll
     for (int x = 0; x < D; ++x) acc[k][x] = T(0);
-  for (int s = s0; s < s1; ++s) {
-    const uint16_t sl = a.slots[s];
-    const int64_t e = e0 + (sl & 0x7fff);
-    const bool nb = (sl >> 15) != 0;
-    const int2 pn = a.ent_pn[e];
-    const int64_t o = nb ? pn.x : pn.y;
-    const T* swp = a.sw + 4 * e;
-    const T om = swp[3];
-    const T wgt = nb ? -om : T(1) - om;
-    T Sw[D];
+  for (int s = s0; s < s1; s += GB) {
+    int64_t o[GB];
+    T Sw[GB][D];
 #pragma unroll
-    for (int x = 0; x < D; ++x) Sw[x] = wgt * swp[x];
+    for (int j = 0; j < GB; ++j) {
+      const bool ok = s + j < s1;
+      const int sj = ok ? s + j : s0;
+      const int32_t oj = a.slot_o[sj];
+      GlbPtr<T> r = as_glb(a.ssw + 4 * (int64_t)sj);
+      o[j] = ok ? (int64_t)oj : c;
 #pragma unroll
-    for (int k = 0; k < NQ; ++k) {
-      const T dq = phi[o * NQ + k] - q[k];
-#pragma unroll
-      for (int x = 0; x < D; ++x) acc[k][x] += dq * Sw[x];
+      for (int x = 0; x < D; ++x) Sw[j][x] = ok ? r[x] : T(0);
     }
+    T qo[GB][NQ];
+#pragma unroll
+    for (int j = 0; j < GB; ++j) load_row<T, NQ>(qo[j], lds, phi, c0, n, o[j]);
+#pragma unroll
+    for (int j = 0; j < GB; ++j)
+#pragma unroll
+      for (int k = 0; k < NQ; ++k) {
+        const T dq = qo[j][k] - q[k];
+#pragma unroll
+        for (int x = 0; x < D; ++x) acc[k][x] += dq * Sw[j][x];
+      }
   }
+}
+
+template <class T, int D, int NQ, bool SYM>
+__global__ __launch_bounds__(KTPB) void k_grad(KArgs<T> a, const T* __restrict__ phi, T* __restrict__ out) {
+  __shared__ T lds[KTPB * NQ];
+  const int b = xcd_remap(blockIdx.x, a.cell_per_xcd, a.n_cell_blocks);
+  if (b < 0) return;
+  const int64_t c0 = (int64_t)b * KTPB;
+  const int n = (int)(a.nc - c0 < KTPB ? a.nc - c0 : KTPB);
+  stage_rows(lds, phi, c0, n, NQ);
+  __syncthreads();
+  const int64_t c = c0 + threadIdx.x;
+  if (c >= a.nc) return;
+  T acc[NQ][D];
+  grad_sums<T, D, NQ>(a, phi, c, acc, lds, c0, n);
   const T rv = a.rV[c];
   if constexpr (!SYM) {
 #pragma unroll
@@ -625,7 +794,7 @@ __global__ __launch_bounds__(KTPB) void k_theta(KArgs<T> a, int dcs, float* __re
       const T delta = phi1 - phi0;
       const T sdiff = T(2) * sg * dot - delta;
       const T eps = T(1e-8) * (fabs(phi0) + fabs(phi1)) + T(1e-30);
-      const T bf = fabs(sdiff - delta) / (fabs(sdiff) + fabs(delta) + eps);
+      const T bf = fdiv(fabs(sdiff - delta), fabs(sdiff) + fabs(delta) + eps);
       beta = fmax(beta, bf);
     }
   }
