@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -79,7 +80,7 @@ void dfree_t(X*& p) {
 
 void free_work(dolinc_ctx c) {
   Work& w = c->w;
-  dfree(w.sw); dfree(w.ssw); dfree(w.dc); dfree(w.rV); dfree(w.G1); dfree(w.G2); dfree(w.W1); dfree(w.W2);
+  dfree(w.sw); dfree(w.ell_sw); dfree(w.ell_d); dfree(w.dc); dfree(w.rV); dfree(w.G1); dfree(w.G2); dfree(w.W1); dfree(w.W2);
   dfree_t(w.theta);
   w.scheme = w.precision = -1;
   w.nv = 0;
@@ -92,7 +93,7 @@ void free_all(dolinc_ctx c) {
   free_mlp(c);
   DevMesh& m = c->m;
   dfree_t(m.part_ptr); dfree_t(m.ent_face); dfree_t(m.ent_pn); dfree_t(m.slot_ptr); dfree_t(m.slots);
-  dfree_t(m.slot_o);
+  dfree_t(m.ell_ptr);
   dfree_t(m.face_ent); dfree_t(m.face_own); dfree_t(m.face_nei);
   dfree_t(m.nodes); dfree_t(m.fptr); dfree_t(m.fnodes); dfree_t(m.shift);
   dfree_t(m.V); dfree_t(m.xc); dfree_t(m.S); dfree_t(m.xf); dfree_t(m.fanc); dfree_t(m.omega); dfree_t(m.g);
@@ -319,12 +320,28 @@ dolinc_status dolinc_create(const dolinc_mesh_desc* mesh, dolinc_ctx* out) {
     UP(m.fptr, mesh->face_node_ptr, nf + 1);
     UP(m.fnodes, mesh->face_nodes, mesh->face_node_ptr[nf]);
     UP(m.shift, mesh->neigh_shift, nf * dim);
+    {
+      // sliced-ELL offsets: ELL_BLOCK cells per block, as many records per
+      // cell as the block's widest cell has faces
+      const int64_t nb = (P.n_cells + ELL_BLOCK - 1) / ELL_BLOCK;
+      std::vector<int32_t> ep(nb + 1, 0);
+      int64_t tot = 0;
+      for (int64_t b = 0; b < nb; ++b) {
+        int mf = 0;
+        const int64_t c1 = std::min<int64_t>(P.n_cells, (b + 1) * ELL_BLOCK);
+        for (int64_t cc = b * ELL_BLOCK; cc < c1; ++cc) mf = std::max(mf, P.slot_ptr[cc + 1] - P.slot_ptr[cc]);
+        tot += (int64_t)mf * ELL_BLOCK;
+        ep[b + 1] = (int32_t)std::min<int64_t>(tot, INT32_MAX);
+      }
+      if (tot > INT32_MAX && e == hipSuccess) e = hipErrorInvalidValue;  // reported below
+      c->n_ell = tot;
+      UP(m.ell_ptr, ep.data(), ep.size());
+    }
 #undef UP
     const size_t nc = (size_t)P.n_cells;
     auto dm = [&](double** p, size_t n) {
       if (e == hipSuccess) e = hipMalloc((void**)p, n * sizeof(double));
     };
-    if (e == hipSuccess) e = hipMalloc((void**)&m.slot_o, std::max<size_t>(P.slots.size(), 1) * sizeof(int32_t));
     dm(&m.V, nc);
     dm(&m.xc, 3 * nc);
     dm(&m.S, 3 * (size_t)nf);
@@ -409,7 +426,8 @@ dolinc_status dolinc_precompute(dolinc_ctx c, const dolinc_params* p, dolinc_str
       if (e == hipSuccess) e = hipMalloc(q, bytes ? bytes : 16);
     };
     al(&c->w.sw, ne * 4 * el);
-    al(&c->w.ssw, (size_t)(2 * c->n_faces) * 4 * el);
+    al(&c->w.ell_sw, (size_t)c->n_ell * 4 * el);
+    al(&c->w.ell_d, (size_t)c->n_ell * 4 * el);
     al(&c->w.dc, ne * (size_t)dc_stride(p->scheme) * el);
     al(&c->w.rV, nc * el);
     if (ord >= 1 || bl) al(&c->w.G1, nc * nv * c->dim * el);

@@ -20,9 +20,10 @@ KArgs<T> base_args(dolinc_ctx_s* c) {
   a.ent_pn = c->m.ent_pn;
   a.slot_ptr = c->m.slot_ptr;
   a.slots = c->m.slots;
-  a.slot_o = c->m.slot_o;
+  a.ell_ptr = c->m.ell_ptr;
   a.sw = (const T*)c->w.sw;
-  a.ssw = (const T*)c->w.ssw;
+  a.ell_sw = (const T*)c->w.ell_sw;
+  a.ell_d = (const T*)c->w.ell_d;
   a.dc = (const T*)c->w.dc;
   a.rV = (const T*)c->w.rV;
   a.G1 = (const T*)c->w.G1;

@@ -88,8 +88,9 @@ template <class T, int D>
 __device__ void cell_features_from(const KArgs<T>& a, int dcs, int64_t c, const T* Gc, float* feat,
                                    const T* Ulds = nullptr, int64_t c0 = 0, int n = 0) {
   constexpr int NV = D + 2;
-  const int e0 = a.part_ptr[c / a.B];
-  const int s0 = a.slot_ptr[c], s1 = a.slot_ptr[c + 1];
+  const int64_t b = c / KTPB;
+  const int lane = (int)(c - b * KTPB);
+  const int r0 = a.ell_ptr[b], m = (a.ell_ptr[b + 1] - r0) / KTPB;
   T qc[4], gqc[4][D];
   T Uc[NV];
   load_row<T, NV>(Uc, Ulds, a.U, c0, n, c);
@@ -99,49 +100,48 @@ __device__ void cell_features_from(const KArgs<T>& a, int dcs, int64_t c, const 
     mx_g0[k] = mx_dl[k] = mx_b[k] = sm_b[k] = mx_sd[k] = sm_dl[k] = T(0);
     mn_r[k] = T(2);
   }
-  // faces in batches of 4: slot records first, then face vectors and
-  // neighbour rows (a slot past the last is skipped)
+  // face records (sliced ELL) in batches of 4, then the batch's neighbour
+  // rows; padding records (sigma = 0) are skipped
   constexpr int GB = 4;
-  for (int s = s0; s < s1; s += GB) {
-    int64_t o[GB], e[GB];
-    T sg[GB];
+  int nface = 0;
+  for (int j = 0; j < m; j += GB) {
+    int64_t o[GB];
+    T dv[GB][D], sg[GB];
 #pragma unroll
-    for (int j = 0; j < GB; ++j) {
-      const int sj = s + j < s1 ? s + j : s0;
-      o[j] = a.slot_o[sj];
-      const uint16_t sl = a.slots[sj];
-      e[j] = e0 + (sl & 0x7fff);
-      sg[j] = (sl >> 15) ? T(-1) : T(1);
+    for (int jj = 0; jj < GB; ++jj) {
+      const bool ok = j + jj < m;
+      const int64_t r = (int64_t)r0 + (int64_t)(ok ? j + jj : j) * KTPB + lane;
+      GlbPtr<T> rd = as_glb(a.ell_d + 4 * r);
+#pragma unroll
+      for (int x = 0; x < D; ++x) dv[jj][x] = rd[x];
+      sg[jj] = ok ? rd[3] : T(0);
+      o[jj] = ok ? rec_cell(a.ell_sw[4 * r + 3]) : c;
     }
-    T dv[GB][D], Uo[GB][NV];
+    T Uo[GB][NV];
 #pragma unroll
-    for (int j = 0; j < GB; ++j) {
-      GlbPtr<T> dcp = as_glb(a.dc + (int64_t)dcs * e[j]);
+    for (int jj = 0; jj < GB; ++jj) load_row<T, NV>(Uo[jj], Ulds, a.U, c0, n, o[jj]);
 #pragma unroll
-      for (int x = 0; x < D; ++x) dv[j][x] = dcp[x];
-      load_row<T, NV>(Uo[j], Ulds, a.U, c0, n, o[j]);
-    }
-#pragma unroll
-    for (int j = 0; j < GB; ++j) {
-      if (s + j >= s1) break;
+    for (int jj = 0; jj < GB; ++jj) {
+      if (sg[jj] == T(0)) continue;
+      ++nface;
       // neighbour channel values
       T qo[4];
       {
-        const T rho = Uo[j][0];
+        const T rho = Uo[jj][0];
         T ke = T(0), m2 = T(0);
         for (int x = 0; x < D; ++x) {
-          ke += fdiv(Uo[j][1 + x] * Uo[j][1 + x], rho);
-          m2 += Uo[j][1 + x] * Uo[j][1 + x];
+          ke += fdiv(Uo[jj][1 + x] * Uo[jj][1 + x], rho);
+          m2 += Uo[jj][1 + x] * Uo[jj][1 + x];
         }
         qo[0] = rho;
-        qo[1] = (a.gamma - T(1)) * (Uo[j][D + 1] - T(0.5) * ke);
-        qo[2] = Uo[j][D + 1];
+        qo[1] = (a.gamma - T(1)) * (Uo[jj][D + 1] - T(0.5) * ke);
+        qo[2] = Uo[jj][D + 1];
         qo[3] = fsqrt(m2);
       }
       for (int k = 0; k < 4; ++k) {
         T g0 = T(0);
-        for (int x = 0; x < D; ++x) g0 += dv[j][x] * gqc[k][x];
-        g0 *= T(2) * sg[j];
+        for (int x = 0; x < D; ++x) g0 += dv[jj][x] * gqc[k][x];
+        g0 *= T(2);
         const T delta = qo[k] - qc[k];
         const T sd = g0 - delta;
         const T eps = T(1e-8) * (fabs(qc[k]) + fabs(qo[k])) + T(1e-30);
@@ -161,7 +161,7 @@ __device__ void cell_features_from(const KArgs<T>& a, int dcs, int64_t c, const 
       }
     }
   }
-  const T inv = T(1) / (T)(s1 - s0);
+  const T inv = T(1) / (T)nface;
   for (int k = 0; k < 4; ++k) {
     const T rs = fdiv(T(1), fabs(qc[k]) + sm_dl[k] * inv + T(1e-8));
     T f[6] = {mx_g0[k] * rs, mx_dl[k] * rs, mx_b[k], sm_b[k] * inv, mn_r[k], mx_sd[k] * rs};
@@ -512,6 +512,7 @@ __global__ __launch_bounds__(KTPB) void k_grad_indicator(KArgs<T> a, int dcs, Ml
   constexpr int XS = MLP_INP + 2;  // padded row stride (shorts) against LDS bank conflicts
   __shared__ unsigned short xs[KTPB * XS];
   __shared__ T ul[KTPB * NV];
+  __shared__ T g1buf[KTPB * NV * D];
   const int b = xcd_remap(blockIdx.x, a.cell_per_xcd, a.n_cell_blocks);
   if (b < 0) return;
   const int64_t c0 = (int64_t)b * KTPB;
@@ -520,16 +521,13 @@ __global__ __launch_bounds__(KTPB) void k_grad_indicator(KArgs<T> a, int dcs, Ml
   __syncthreads();
   const int64_t c = c0 + threadIdx.x;
   unsigned short* row = xs + threadIdx.x * XS;
+  T g[NV * D];
   if (c < a.nc) {
     T acc[NV][D];
     grad_sums<T, D, NV>(a, a.U, c, acc, ul, c0, ncl);
     const T rv = a.rV[c];
-    T g[NV * D];
     for (int k = 0; k < NV; ++k)
-      for (int x = 0; x < D; ++x) {
-        g[k * D + x] = acc[k][x] * rv;
-        G1out[(c * NV + k) * D + x] = g[k * D + x];
-      }
+      for (int x = 0; x < D; ++x) g[k * D + x] = acc[k][x] * rv;
     float f[MLP_IN];
     cell_features_from<T, D>(a, dcs, c, g, f, ul, c0, ncl);
     for (int j = 0; j < MLP_IN; ++j) row[j] = f2bf(f[j]);
@@ -537,7 +535,7 @@ __global__ __launch_bounds__(KTPB) void k_grad_indicator(KArgs<T> a, int dcs, Ml
     for (int j = 0; j < MLP_IN; ++j) row[j] = 0;
   }
   for (int j = MLP_IN; j < MLP_INP; ++j) row[j] = 0;
-  __syncthreads();
+  store_rows_coalesced<T, NV * D>(G1out, c0, ncl, g, g1buf);  // also orders the xs writes
   MlpRegs R;
   load_weights(m, R);
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;

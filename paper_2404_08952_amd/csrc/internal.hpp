@@ -15,12 +15,19 @@ namespace dolinc {
 //   sw[e][4]  : S_x, S_y, S_z (0 in 2-D), omega (owner weight)
 //   dc[e][DC] : d_x, d_y, d_z, then the coefficients of the DOLINC
 //               representation of each side (see kernels for the meaning).
-// Per-slot record (one per cell-face incidence, contiguous per cell):
-//   ssw[s][4] : w_o S_x, w_o S_y, w_o S_z, sign; S is the face area vector
-//               oriented owner -> neighbour, sign = +1 on the owner side and
-//               -1 on the neighbour side, and w_o = sign * (weight of the
-//               other cell in the face interpolation), so the Gauss-linear
-//               sum of a cell is sum_s (phi_o - phi_c) ssw[s][0..D).
+// Per-cell face records in sliced ELL order: cells are taken in blocks of
+// ELL_BLOCK; block b holds m_b = (max faces of a cell in b) records per
+// cell, record j of cell lane l at ell_ptr[b] + j * ELL_BLOCK + l, so that
+// the lanes of a wave read consecutive records.  A cell with fewer faces is
+// padded with records of zero weight that name the cell itself.
+//   ell_sw[r][4] : w_o S_x, w_o S_y, w_o S_z, other cell (index bits); S is
+//                  the face area vector oriented owner -> neighbour and
+//                  w_o = sigma * (weight of the other cell in the face
+//                  interpolation), sigma = +1 on the owner side, -1 on the
+//                  neighbour side, so the Gauss-linear sum of a cell is
+//                  sum_r (phi_o - phi_c) ell_sw[r][0..D).
+//   ell_d[r][4]  : sigma d_x, sigma d_y, sigma d_z, sigma (0 for padding).
+constexpr int ELL_BLOCK = 256;
 inline int coef_left(int scheme) { return scheme <= 2 ? 1 : scheme == 3 ? 2 : scheme == 4 ? 3 : 4; }
 inline int coef_right(int scheme) { return scheme <= 2 ? 1 : scheme == 3 ? 2 : scheme == 4 ? 0 : 4; }
 inline int dc_stride(int scheme) {
@@ -36,7 +43,7 @@ struct DevMesh {
   int2* ent_pn = nullptr;
   int32_t* slot_ptr = nullptr;
   uint16_t* slots = nullptr;
-  int32_t* slot_o = nullptr;     // per slot: the cell on the other side of the face
+  int32_t* ell_ptr = nullptr;    // [n_cells / ELL_BLOCK + 1] record offsets
   int32_t* face_ent = nullptr;   // one entry per caller face
   int32_t* face_own = nullptr;   // internal owner per caller face
   int32_t* face_nei = nullptr;
@@ -70,7 +77,8 @@ struct Mlp {
 
 struct Work {
   void* sw = nullptr;
-  void* ssw = nullptr;
+  void* ell_sw = nullptr;
+  void* ell_d = nullptr;
   void* dc = nullptr;
   void* rV = nullptr;
   void* G1 = nullptr;
@@ -90,7 +98,7 @@ struct dolinc_ctx_s {
   int dim = 0;
   int64_t n_cells = 0, n_faces = 0, n_nodes = 0, n_entries = 0, n_parts = 0;
   int part_cells = 256;
-  int64_t max_entries = 0, max_cell_faces = 0;
+  int64_t max_entries = 0, max_cell_faces = 0, n_ell = 0;
   std::vector<int32_t> new_of_old;
   dolinc::DevMesh m;
   dolinc::Work w;

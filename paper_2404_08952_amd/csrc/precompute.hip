@@ -269,38 +269,51 @@ __global__ void k_entry_fill(int64_t ne, int dim, int scheme, int dcs, const int
   }
 }
 
-// Per-slot other cell and interpolation-weighted area vector (layout of
-// ssw: see the record description in internal.hpp).
-__global__ void k_slot_other(int64_t nc, int B, const int32_t* __restrict__ part_ptr,
-                             const int32_t* __restrict__ slot_ptr, const uint16_t* __restrict__ slots,
-                             const int2* __restrict__ ent_pn, int32_t* __restrict__ slot_o) {
-  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= nc) return;
-  const int e0 = part_ptr[c / B];
-  for (int s = slot_ptr[c]; s < slot_ptr[c + 1]; ++s) {
-    const uint16_t sl = slots[s];
-    const int2 pn = ent_pn[e0 + (sl & 0x7fff)];
-    slot_o[s] = (sl >> 15) ? pn.x : pn.y;
-  }
-}
-
+// Sliced-ELL face records of every cell (layout: see internal.hpp), from
+// the per-entry records sw and dc already in the working type.
 template <class T>
-__global__ void k_slot_fill(int64_t nc, int B, const int32_t* __restrict__ part_ptr,
-                            const int32_t* __restrict__ slot_ptr, const uint16_t* __restrict__ slots,
-                            const T* __restrict__ sw, T* __restrict__ ssw) {
-  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_ell_fill(int64_t nc, int B, const int32_t* __restrict__ part_ptr,
+                           const int32_t* __restrict__ slot_ptr, const uint16_t* __restrict__ slots,
+                           const int2* __restrict__ ent_pn, const int32_t* __restrict__ ell_ptr, int dcs,
+                           const T* __restrict__ sw, const T* __restrict__ dc, T* __restrict__ ell_sw,
+                           T* __restrict__ ell_d) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= nc) return;
+  const int64_t b = c / ELL_BLOCK;
+  const int lane = (int)(c - b * ELL_BLOCK);
+  const int r0 = ell_ptr[b], m = (ell_ptr[b + 1] - r0) / ELL_BLOCK;
   const int e0 = part_ptr[c / B];
-  for (int s = slot_ptr[c]; s < slot_ptr[c + 1]; ++s) {
-    const uint16_t sl = slots[s];
-    const bool nb = (sl >> 15) != 0;
-    const T* r = sw + 4 * (int64_t)(e0 + (sl & 0x7fff));
-    const T om = r[3];
-    const T wgt = nb ? -om : T(1) - om;
-    ssw[4 * (int64_t)s + 0] = wgt * r[0];
-    ssw[4 * (int64_t)s + 1] = wgt * r[1];
-    ssw[4 * (int64_t)s + 2] = wgt * r[2];
-    ssw[4 * (int64_t)s + 3] = nb ? T(-1) : T(1);
+  const int s0 = slot_ptr[c], nf = slot_ptr[c + 1] - s0;
+  for (int j = 0; j < m; ++j) {
+    const int64_t r = (int64_t)r0 + (int64_t)j * ELL_BLOCK + lane;
+    T* q = ell_sw + 4 * r;
+    T* dd = ell_d + 4 * r;
+    int64_t o = c;
+    if (j < nf) {
+      const uint16_t sl = slots[s0 + j];
+      const bool nb = (sl >> 15) != 0;
+      const int64_t e = e0 + (sl & 0x7fff);
+      const int2 pn = ent_pn[e];
+      o = nb ? pn.x : pn.y;
+      const T om = sw[4 * e + 3];
+      const T wgt = nb ? -om : T(1) - om;
+      const T sg = nb ? T(-1) : T(1);
+      for (int x = 0; x < 3; ++x) {
+        q[x] = wgt * sw[4 * e + x];
+        dd[x] = sg * dc[(int64_t)dcs * e + x];
+      }
+      dd[3] = sg;
+    } else {
+      for (int x = 0; x < 4; ++x) {
+        q[x] = T(0);
+        dd[x] = T(0);
+      }
+    }
+    if constexpr (sizeof(T) == 4) {
+      q[3] = __int_as_float((int)o);
+    } else {
+      q[3] = __longlong_as_double((long long)o);
+    }
   }
 }
 
@@ -323,8 +336,6 @@ hipError_t launch_geometry(dolinc_ctx_s* c, hipStream_t s) {
                      m.fanc, m.V, m.xc, c->w.flag);
   hipLaunchKernelGGL(k_face_scalars, dim3(nblk(c->n_faces)), dim3(TPB), 0, s, c->n_faces, c->dim, m.face_own,
                      m.face_nei, m.xc, m.shift, m.xf, m.dvec, m.omega, m.g, c->w.flag);
-  hipLaunchKernelGGL(k_slot_other, dim3(nblk(c->n_cells)), dim3(TPB), 0, s, c->n_cells, c->part_cells, m.part_ptr,
-                     m.slot_ptr, m.slots, m.ent_pn, m.slot_o);
   return hipGetLastError();
 }
 
@@ -335,15 +346,17 @@ hipError_t launch_entry_fill(dolinc_ctx_s* c, hipStream_t s) {
   if (c->w.precision == DOLINC_FP64) {
     hipLaunchKernelGGL(k_entry_fill<double>, dim3(nblk(c->n_entries)), dim3(TPB), 0, s, c->n_entries, c->dim, sch,
                        dcs, m.ent_face, m.S, m.omega, m.g, m.dvec, (double*)c->w.sw, (double*)c->w.dc);
-    hipLaunchKernelGGL(k_slot_fill<double>, dim3(nblk(c->n_cells)), dim3(TPB), 0, s, c->n_cells, c->part_cells,
-                       m.part_ptr, m.slot_ptr, m.slots, (const double*)c->w.sw, (double*)c->w.ssw);
+    hipLaunchKernelGGL(k_ell_fill<double>, dim3(nblk(c->n_cells)), dim3(TPB), 0, s, c->n_cells, c->part_cells,
+                       m.part_ptr, m.slot_ptr, m.slots, m.ent_pn, m.ell_ptr, dcs, (const double*)c->w.sw,
+                       (const double*)c->w.dc, (double*)c->w.ell_sw, (double*)c->w.ell_d);
     hipLaunchKernelGGL(k_recip<double>, dim3(nblk(c->n_cells)), dim3(TPB), 0, s, c->n_cells, m.V,
                        (double*)c->w.rV);
   } else {
     hipLaunchKernelGGL(k_entry_fill<float>, dim3(nblk(c->n_entries)), dim3(TPB), 0, s, c->n_entries, c->dim, sch,
                        dcs, m.ent_face, m.S, m.omega, m.g, m.dvec, (float*)c->w.sw, (float*)c->w.dc);
-    hipLaunchKernelGGL(k_slot_fill<float>, dim3(nblk(c->n_cells)), dim3(TPB), 0, s, c->n_cells, c->part_cells,
-                       m.part_ptr, m.slot_ptr, m.slots, (const float*)c->w.sw, (float*)c->w.ssw);
+    hipLaunchKernelGGL(k_ell_fill<float>, dim3(nblk(c->n_cells)), dim3(TPB), 0, s, c->n_cells, c->part_cells,
+                       m.part_ptr, m.slot_ptr, m.slots, m.ent_pn, m.ell_ptr, dcs, (const float*)c->w.sw,
+                       (const float*)c->w.dc, (float*)c->w.ell_sw, (float*)c->w.ell_d);
     hipLaunchKernelGGL(k_recip<float>, dim3(nblk(c->n_cells)), dim3(TPB), 0, s, c->n_cells, m.V,
                        (float*)c->w.rV);
   }

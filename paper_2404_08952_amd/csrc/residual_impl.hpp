@@ -35,9 +35,10 @@ struct KArgs {
   const int2* ent_pn;
   const int32_t* slot_ptr;
   const uint16_t* slots;
-  const int32_t* slot_o;
+  const int32_t* ell_ptr;
   const T* sw;
-  const T* ssw;
+  const T* ell_sw;
+  const T* ell_d;
   const T* dc;
   const T* rV;
   const T* U;
@@ -679,56 +680,90 @@ __global__ __launch_bounds__(KTPB) void k_face_export(KArgs<T> a) {
   }
 }
 
+// Other cell named by a face record (index bits stored in the 4th slot).
+__device__ __forceinline__ int64_t rec_cell(float v) { return (int64_t)__float_as_int(v); }
+__device__ __forceinline__ int64_t rec_cell(double v) { return (int64_t)__double_as_longlong(v); }
+
 // Cell-centric Gauss-linear gradient of phi [nc][NQ] -> out [nc][NQ][D].
 // SYM: NQ = NV*D input components (a gradient) and the output is the
 // symmetrised second derivative [nc][NV][D(D+1)/2].
 // Gauss-linear sums of cell c: acc[k][x] = sum_f sigma S_f,x w (phi_o - phi_c)_k
-// The faces of a cell are taken GB at a time: the per-slot records of a
-// batch are loaded together, then the batch's neighbour rows, so that one
-// cell waits on two memory latencies per batch rather than three per face.
-// A slot past the cell's last one reads the cell's own row with a zero
-// weight (phi_c - phi_c = 0 exactly), which leaves the sums unchanged.
+// The cell's face records (sliced ELL: the lanes of a wave read consecutive
+// records) are taken GB at a time, then the batch's neighbour rows, so a
+// cell waits on two memory latencies per batch.  Padding records name the
+// cell itself with zero weight (phi_c - phi_c = 0), leaving the sums as
+// they are.  c must be cell lane of the ELL block c / KTPB.
 template <class T, int D, int NQ>
 __device__ __forceinline__ void grad_sums(const KArgs<T>& a, const T* __restrict__ phi, int64_t c, T (*acc)[D],
                                           const T* lds = nullptr, int64_t c0 = 0, int n = 0) {
   constexpr int GB = NQ <= 5 ? 4 : 2;
-  const int s0 = a.slot_ptr[c], s1 = a.slot_ptr[c + 1];
+  const int64_t b = c / KTPB;
+  const int lane = (int)(c - b * KTPB);
+  const int r0 = a.ell_ptr[b], m = (a.ell_ptr[b + 1] - r0) / KTPB;
   T q[NQ];
   load_row<T, NQ>(q, lds, phi, c0, n, c);
 #pragma unroll
   for (int k = 0; k < NQ; ++k)
 #pragma unroll
     for (int x = 0; x < D; ++x) acc[k][x] = T(0);
-  for (int s = s0; s < s1; s += GB) {
+  for (int j = 0; j < m; j += GB) {
     int64_t o[GB];
     T Sw[GB][D];
 #pragma unroll
-    for (int j = 0; j < GB; ++j) {
-      const bool ok = s + j < s1;
-      const int sj = ok ? s + j : s0;
-      const int32_t oj = a.slot_o[sj];
-      GlbPtr<T> r = as_glb(a.ssw + 4 * (int64_t)sj);
-      o[j] = ok ? (int64_t)oj : c;
+    for (int jj = 0; jj < GB; ++jj) {
+      const bool ok = j + jj < m;
+      const int64_t r = (int64_t)r0 + (int64_t)(ok ? j + jj : j) * KTPB + lane;
+      GlbPtr<T> rec = as_glb(a.ell_sw + 4 * r);
+      T v[4];
 #pragma unroll
-      for (int x = 0; x < D; ++x) Sw[j][x] = ok ? r[x] : T(0);
+      for (int x = 0; x < 4; ++x) v[x] = rec[x];
+      o[jj] = ok ? rec_cell(v[3]) : c;
+#pragma unroll
+      for (int x = 0; x < D; ++x) Sw[jj][x] = ok ? v[x] : T(0);
     }
     T qo[GB][NQ];
 #pragma unroll
-    for (int j = 0; j < GB; ++j) load_row<T, NQ>(qo[j], lds, phi, c0, n, o[j]);
+    for (int jj = 0; jj < GB; ++jj) load_row<T, NQ>(qo[jj], lds, phi, c0, n, o[jj]);
 #pragma unroll
-    for (int j = 0; j < GB; ++j)
+    for (int jj = 0; jj < GB; ++jj)
 #pragma unroll
       for (int k = 0; k < NQ; ++k) {
-        const T dq = qo[j][k] - q[k];
+        const T dq = qo[jj][k] - q[k];
 #pragma unroll
-        for (int x = 0; x < D; ++x) acc[k][x] += dq * Sw[j][x];
+        for (int x = 0; x < D; ++x) acc[k][x] += dq * Sw[jj][x];
       }
   }
 }
 
+// Rows of W values for the block's cells c0 .. c0+n-1, written by their
+// threads into LDS (row-major), then copied to HBM with consecutive lanes
+// on consecutive addresses.  Every thread of the block must call it.
+template <class T, int W>
+__device__ __forceinline__ void store_rows_coalesced(T* __restrict__ out, int64_t c0, int n, const T* row,
+                                                     T* buf) {
+  __syncthreads();  // buf may still be read by the caller's earlier phase
+  if ((int)threadIdx.x < n) {
+#pragma unroll
+    for (int k = 0; k < W; ++k) buf[threadIdx.x * W + k] = row[k];
+  }
+  __syncthreads();
+  T* dst = out + c0 * W;
+  for (int i = threadIdx.x; i < n * W; i += blockDim.x) dst[i] = buf[i];
+}
+
+template <class T, int D, int NQ, bool SYM>
+struct GradOut {
+  static constexpr int NV = SYM ? NQ / D : NQ;
+  static constexpr int W = SYM ? NV * D * (D + 1) / 2 : NQ * D;
+  // transposed (coalesced) output when its LDS buffer is at most 32 KiB
+  static constexpr bool LDS = (size_t)KTPB * W * sizeof(T) <= 32768;
+  static constexpr int LDSN = KTPB * (LDS ? (W > NQ ? W : NQ) : NQ);
+};
+
 template <class T, int D, int NQ, bool SYM>
 __global__ __launch_bounds__(KTPB) void k_grad(KArgs<T> a, const T* __restrict__ phi, T* __restrict__ out) {
-  __shared__ T lds[KTPB * NQ];
+  using GO = GradOut<T, D, NQ, SYM>;
+  __shared__ T lds[GO::LDSN];
   const int b = xcd_remap(blockIdx.x, a.cell_per_xcd, a.n_cell_blocks);
   if (b < 0) return;
   const int64_t c0 = (int64_t)b * KTPB;
@@ -736,32 +771,40 @@ __global__ __launch_bounds__(KTPB) void k_grad(KArgs<T> a, const T* __restrict__
   stage_rows(lds, phi, c0, n, NQ);
   __syncthreads();
   const int64_t c = c0 + threadIdx.x;
-  if (c >= a.nc) return;
-  T acc[NQ][D];
-  grad_sums<T, D, NQ>(a, phi, c, acc, lds, c0, n);
-  const T rv = a.rV[c];
-  if constexpr (!SYM) {
+  T res[GO::W];
+  if (c < a.nc) {
+    T acc[NQ][D];
+    grad_sums<T, D, NQ>(a, phi, c, acc, lds, c0, n);
+    const T rv = a.rV[c];
+    if constexpr (!SYM) {
 #pragma unroll
-    for (int k = 0; k < NQ; ++k)
+      for (int k = 0; k < NQ; ++k)
 #pragma unroll
-      for (int x = 0; x < D; ++x) out[(c * NQ + k) * D + x] = acc[k][x] * rv;
-  } else {
-    constexpr int NV = NQ / D;
-    constexpr int NS2 = D * (D + 1) / 2;
+        for (int x = 0; x < D; ++x) res[k * D + x] = acc[k][x] * rv;
+    } else {
+      constexpr int NV = NQ / D;
+      constexpr int NS2 = D * (D + 1) / 2;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      T* o2 = out + (c * NV + v) * NS2;
-      // acc[v*D + i][j] = d/dx_j of G1_i
+      for (int v = 0; v < NV; ++v) {
+        T* o2 = res + v * NS2;
+        // acc[v*D + i][j] = d/dx_j of G1_i
 #pragma unroll
-      for (int i = 0; i < D; ++i) o2[i] = acc[v * D + i][i] * rv;
-      if constexpr (D == 3) {
-        o2[3] = T(0.5) * (acc[v * D + 0][1] + acc[v * D + 1][0]) * rv;
-        o2[4] = T(0.5) * (acc[v * D + 0][2] + acc[v * D + 2][0]) * rv;
-        o2[5] = T(0.5) * (acc[v * D + 1][2] + acc[v * D + 2][1]) * rv;
-      } else {
-        o2[2] = T(0.5) * (acc[v * D + 0][1] + acc[v * D + 1][0]) * rv;
+        for (int i = 0; i < D; ++i) o2[i] = acc[v * D + i][i] * rv;
+        if constexpr (D == 3) {
+          o2[3] = T(0.5) * (acc[v * D + 0][1] + acc[v * D + 1][0]) * rv;
+          o2[4] = T(0.5) * (acc[v * D + 0][2] + acc[v * D + 2][0]) * rv;
+          o2[5] = T(0.5) * (acc[v * D + 1][2] + acc[v * D + 2][1]) * rv;
+        } else {
+          o2[2] = T(0.5) * (acc[v * D + 0][1] + acc[v * D + 1][0]) * rv;
+        }
       }
     }
+  }
+  if constexpr (GO::LDS) {
+    store_rows_coalesced<T, GO::W>(out, c0, n, res, lds);
+  } else if (c < a.nc) {
+#pragma unroll
+    for (int k = 0; k < GO::W; ++k) out[c * GO::W + k] = res[k];
   }
 }
 
@@ -773,26 +816,23 @@ __global__ __launch_bounds__(KTPB) void k_theta(KArgs<T> a, int dcs, float* __re
   if (b < 0) return;
   const int64_t c = (int64_t)b * KTPB + threadIdx.x;
   if (c >= a.nc) return;
-  const int e0 = a.part_ptr[c / a.B];
-  const int s0 = a.slot_ptr[c], s1 = a.slot_ptr[c + 1];
+  const int r0 = a.ell_ptr[b], m = (a.ell_ptr[b + 1] - r0) / KTPB;
   T beta = T(0);
-  for (int s = s0; s < s1; ++s) {
-    const uint16_t sl = a.slots[s];
-    const int64_t e = e0 + (sl & 0x7fff);
-    const bool nb = (sl >> 15) != 0;
-    const int2 pn = a.ent_pn[e];
-    const int64_t o = nb ? pn.x : pn.y;
-    const T* dcp = a.dc + (int64_t)dcs * e;
-    const T sg = nb ? T(-1) : T(1);
+  for (int j = 0; j < m; ++j) {
+    const int64_t r = (int64_t)r0 + (int64_t)j * KTPB + threadIdx.x;
+    GlbPtr<T> rd = as_glb(a.ell_d + 4 * r);
+    const T sg = rd[3];
+    if (sg == T(0)) continue;  // padding
+    const int64_t o = rec_cell(a.ell_sw[4 * r + 3]);
 #pragma unroll
     for (int q = 0; q < (NV == 1 ? 1 : 2); ++q) {
       const int v = q == 0 ? 0 : NV - 1;
       T dot = T(0);
 #pragma unroll
-      for (int x = 0; x < D; ++x) dot += dcp[x] * a.G1[(c * NV + v) * D + x];
+      for (int x = 0; x < D; ++x) dot += rd[x] * a.G1[(c * NV + v) * D + x];
       const T phi0 = a.U[c * NV + v], phi1 = a.U[o * NV + v];
       const T delta = phi1 - phi0;
-      const T sdiff = T(2) * sg * dot - delta;
+      const T sdiff = T(2) * dot - delta;
       const T eps = T(1e-8) * (fabs(phi0) + fabs(phi1)) + T(1e-30);
       const T bf = fdiv(fabs(sdiff - delta), fabs(sdiff) + fabs(delta) + eps);
       beta = fmax(beta, bf);
