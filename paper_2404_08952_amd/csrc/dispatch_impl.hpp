@@ -116,6 +116,15 @@ hipError_t run_flux(dolinc_ctx_s* c, const KArgs<T>& a, hipStream_t s, bool ex) 
   return bl ? flux_by_scheme<T, 3, 3, true>(sch, a, lds, s, ex) : flux_by_scheme<T, 3, 3, false>(sch, a, lds, s, ex);
 }
 
+// 3-D Euler second derivatives: the FP32 kernel is built for 5 waves per SIMD
+template <class T>
+void launch_grad2_euler(dim3 grid, dim3 blk, hipStream_t s, const KArgs<T>& a, const T* g1, T* g2) {
+  if constexpr (sizeof(T) == 4)
+    hipLaunchKernelGGL((k_grad_w5<T, 3, 15, true>), grid, blk, 0, s, a, g1, g2);
+  else
+    hipLaunchKernelGGL((k_grad<T, 3, 15, true>), grid, blk, 0, s, a, g1, g2);
+}
+
 template <class T>
 hipError_t run_gradients(dolinc_ctx_s* c, const void* U, void* G1, void* G2, hipStream_t s) {
   KArgs<T> a = base_args<T>(c);
@@ -133,7 +142,7 @@ hipError_t run_gradients(dolinc_ctx_s* c, const void* U, void* G1, void* G2, hip
     if (g2) hipLaunchKernelGGL((k_grad<T, 3, 3, true>), grid, blk, 0, s, a, (const T*)g1, g2);
   } else {
     hipLaunchKernelGGL((k_grad<T, 3, 5, false>), grid, blk, 0, s, a, u, g1);
-    if (g2) hipLaunchKernelGGL((k_grad<T, 3, 15, true>), grid, blk, 0, s, a, (const T*)g1, g2);
+    if (g2) launch_grad2_euler<T>(grid, blk, s, a, (const T*)g1, g2);
   }
   return hipGetLastError();
 }
@@ -148,7 +157,7 @@ hipError_t run_grad2(dolinc_ctx_s* c, const void* G1, void* G2, hipStream_t s) {
   else if (nv == 1)
     hipLaunchKernelGGL((k_grad<T, 3, 3, true>), grid, blk, 0, s, a, (const T*)G1, (T*)G2);
   else
-    hipLaunchKernelGGL((k_grad<T, 3, 15, true>), grid, blk, 0, s, a, (const T*)G1, (T*)G2);
+    launch_grad2_euler<T>(grid, blk, s, a, (const T*)G1, (T*)G2);
   return hipGetLastError();
 }
 

@@ -220,10 +220,62 @@ __device__ __forceinline__ void load_weights(const MlpDev& m, MlpRegs& R) {
   }
 }
 
+// The network's parameters copied into LDS once per workgroup (bf16 weights
+// as 32-bit words), so the waves of a block read them from LDS instead of
+// each fetching 12 KiB through the vector memory path.
+struct MlpLds {
+  unsigned int w1[MLP_H * MLP_INP / 2];
+  unsigned int w2[MLP_H * MLP_H / 2];
+  float b1[MLP_H], b2[MLP_H], w3[MLP_H], b3[4];
+};
+
+__device__ __forceinline__ void mlp_to_lds(const MlpDev& m, MlpLds* L) {
+  const unsigned int* w1 = reinterpret_cast<const unsigned int*>(m.w1b);
+  const unsigned int* w2 = reinterpret_cast<const unsigned int*>(m.w2b);
+  for (int i = threadIdx.x; i < MLP_H * MLP_INP / 2; i += blockDim.x) L->w1[i] = w1[i];
+  for (int i = threadIdx.x; i < MLP_H * MLP_H / 2; i += blockDim.x) L->w2[i] = w2[i];
+  for (int i = threadIdx.x; i < MLP_H; i += blockDim.x) {
+    L->b1[i] = m.p[OFF_B1 + i];
+    L->b2[i] = m.p[OFF_B2 + i];
+    L->w3[i] = m.p[OFF_W3 + i];
+  }
+  if (threadIdx.x == 0) L->b3[0] = m.p[OFF_B3];
+}
+
+__device__ __forceinline__ v4s lds4(LdsPtr<unsigned int> p) {
+  const unsigned int a = p[0], b = p[1];
+  return v4s{(short)(a & 0xffffu), (short)(a >> 16), (short)(b & 0xffffu), (short)(b >> 16)};
+}
+
+__device__ __forceinline__ void load_weights_lds(const MlpLds* L, MlpRegs& R) {
+  const int l = threadIdx.x & 63;
+  const int r = l & 15, g = l >> 4;
+  for (int t = 0; t < 4; ++t) {
+    for (int kk = 0; kk < 2; ++kk) R.w1[t][kk] = lds4(as_lds(L->w1 + ((16 * t + r) * MLP_INP + 16 * kk + 4 * g) / 2));
+    for (int kk = 0; kk < 4; ++kk) R.w2[t][kk] = lds4(as_lds(L->w2 + ((16 * t + r) * MLP_H + 16 * kk + 4 * g) / 2));
+  }
+}
+
+// Biases and output weights of the network, from HBM (P = const float*)
+// or from LDS (P = LdsPtr<float>).
+template <class P>
+struct MlpVec {
+  P b1, b2, w3;
+  float b3;
+};
+
+__device__ __forceinline__ MlpVec<const float*> mlp_vec(const MlpDev& m) {
+  return {m.p + OFF_B1, m.p + OFF_B2, m.p + OFF_W3, m.p[OFF_B3]};
+}
+__device__ __forceinline__ MlpVec<LdsPtr<float>> mlp_vec(const MlpLds* L) {
+  return {as_lds(L->b1), as_lds(L->b2), as_lds(L->w3), L->b3[0]};
+}
+
 // Forward of 16 cells whose bf16 features are at X (row stride 32; rows
 // beyond nrow read as zero).  Outputs in D layout (lane: units 16t+4g+i of
 // cell l%16): H1 (fp32), H2 (fp32); returns theta of cell l % 16.
-__device__ __forceinline__ float mlp_tile_fwd(const MlpDev& m, const MlpRegs& R, const unsigned short* X, int nrow,
+template <class P>
+__device__ __forceinline__ float mlp_tile_fwd(const MlpVec<P>& m, const MlpRegs& R, const unsigned short* X, int nrow,
                                               v4f* H1, v4f* H2, float* z3out, int xstride = MLP_INP) {
   const int l = threadIdx.x & 63;
   const int r = l & 15, g = l >> 4;
@@ -237,7 +289,7 @@ __device__ __forceinline__ float mlp_tile_fwd(const MlpDev& m, const MlpRegs& R,
   v4s h1b[4];
   for (int t = 0; t < 4; ++t) {
     v4f acc;
-    for (int i = 0; i < 4; ++i) acc[i] = m.p[OFF_B1 + 16 * t + 4 * g + i];
+    for (int i = 0; i < 4; ++i) acc[i] = m.b1[16 * t + 4 * g + i];
     for (int kk = 0; kk < 2; ++kk) acc = mfma16(R.w1[t][kk], xb[kk], acc);
     v4f h;
     for (int i = 0; i < 4; ++i) h[i] = fast_tanh(acc[i]);
@@ -247,18 +299,18 @@ __device__ __forceinline__ float mlp_tile_fwd(const MlpDev& m, const MlpRegs& R,
   float part = 0.f;
   for (int t = 0; t < 4; ++t) {
     v4f acc;
-    for (int i = 0; i < 4; ++i) acc[i] = m.p[OFF_B2 + 16 * t + 4 * g + i];
+    for (int i = 0; i < 4; ++i) acc[i] = m.b2[16 * t + 4 * g + i];
     for (int kk = 0; kk < 4; ++kk) acc = mfma16(R.w2[t][kk], h1b[kk], acc);
     v4f h;
     for (int i = 0; i < 4; ++i) {
       h[i] = fast_tanh(acc[i]);
-      part += m.p[OFF_W3 + 16 * t + 4 * g + i] * h[i];
+      part += m.w3[16 * t + 4 * g + i] * h[i];
     }
     H2[t] = h;
   }
   part += __shfl_xor(part, 16, 64);
   part += __shfl_xor(part, 32, 64);
-  const float z3 = part + m.p[OFF_B3];
+  const float z3 = part + m.b3;
   *z3out = z3;
   return __builtin_amdgcn_rcpf(1.f + __expf(-z3));
 }
@@ -267,6 +319,7 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(MlpDev m, const unsigned short*
                                                  float* __restrict__ theta) {
   MlpRegs R;
   load_weights(m, R);
+  const auto mv = mlp_vec(m);
   const int l = threadIdx.x & 63;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -276,7 +329,7 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(MlpDev m, const unsigned short*
     const int nrow = (int)((n - row0) < 16 ? (n - row0) : 16);
     v4f H1[4], H2[4];
     float z3;
-    const float th = mlp_tile_fwd(m, R, X + row0 * MLP_INP, nrow, H1, H2, &z3);
+    const float th = mlp_tile_fwd(mv, R, X + row0 * MLP_INP, nrow, H1, H2, &z3);
     if (l < nrow) theta[row0 + l] = th;
   }
 }
@@ -293,6 +346,7 @@ __global__ __launch_bounds__(256) void k_mlp_grad(MlpDev m, const unsigned short
   __shared__ float red[MLP_NPARAM + 1];
   MlpRegs R;
   load_weights(m, R);
+  const auto mv = mlp_vec(m);
   const int l = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int r = l & 15, g = l >> 4;
@@ -318,7 +372,7 @@ __global__ __launch_bounds__(256) void k_mlp_grad(MlpDev m, const unsigned short
     const int nrow = (int)((r1 - row0) < 16 ? (r1 - row0) : 16);
     v4f H1[4], H2[4];
     float z3;
-    const float th = mlp_tile_fwd(m, R, X + row0 * MLP_INP, nrow, H1, H2, &z3);
+    const float th = mlp_tile_fwd(mv, R, X + row0 * MLP_INP, nrow, H1, H2, &z3);
     const bool valid = r < nrow;
     const float yy = valid ? y[row0 + r] : 0.f;
     const float g3 = valid ? (th - yy) * invn : 0.f;
@@ -489,6 +543,7 @@ __global__ __launch_bounds__(KTPB) void k_indicator(KArgs<T> a, int dcs, MlpDev 
   __syncthreads();
   MlpRegs R;
   load_weights(m, R);
+  const auto mv = mlp_vec(m);
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   for (int t = 0; t < 4; ++t) {
     const int64_t row0 = c0 + 64 * w + 16 * t;
@@ -496,7 +551,7 @@ __global__ __launch_bounds__(KTPB) void k_indicator(KArgs<T> a, int dcs, MlpDev 
     const int nrow = (int)((a.nc - row0) < 16 ? (a.nc - row0) : 16);
     v4f H1[4], H2[4];
     float z3;
-    const float th = mlp_tile_fwd(m, R, xs + (64 * w + 16 * t) * MLP_INP, nrow, H1, H2, &z3);
+    const float th = mlp_tile_fwd(mv, R, xs + (64 * w + 16 * t) * MLP_INP, nrow, H1, H2, &z3);
     if (l < nrow) theta[row0 + l] = th;
   }
 }
@@ -536,8 +591,14 @@ __global__ __launch_bounds__(KTPB) void k_grad_indicator(KArgs<T> a, int dcs, Ml
   }
   for (int j = MLP_IN; j < MLP_INP; ++j) row[j] = 0;
   store_rows_coalesced<T, NV * D>(G1out, c0, ncl, g, g1buf);  // also orders the xs writes
+  static_assert(sizeof(MlpLds) <= sizeof(g1buf), "network parameters must fit the G1 staging buffer");
+  MlpLds* ml = reinterpret_cast<MlpLds*>(g1buf);
+  __syncthreads();  // the G1 rows have left g1buf
+  mlp_to_lds(m, ml);
+  __syncthreads();
   MlpRegs R;
-  load_weights(m, R);
+  load_weights_lds(ml, R);
+  const auto mv = mlp_vec(ml);
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   for (int t = 0; t < 4; ++t) {
     const int64_t row0 = c0 + 64 * w + 16 * t;
@@ -545,7 +606,7 @@ __global__ __launch_bounds__(KTPB) void k_grad_indicator(KArgs<T> a, int dcs, Ml
     const int nrow = (int)((a.nc - row0) < 16 ? (a.nc - row0) : 16);
     v4f H1[4], H2[4];
     float z3;
-    const float th = mlp_tile_fwd(m, R, xs + (64 * w + 16 * t) * XS, nrow, H1, H2, &z3, XS);
+    const float th = mlp_tile_fwd(mv, R, xs + (64 * w + 16 * t) * XS, nrow, H1, H2, &z3, XS);
     if (l < nrow) theta[row0 + l] = th;
   }
 }

@@ -735,6 +735,63 @@ __device__ __forceinline__ void grad_sums(const KArgs<T>& a, const T* __restrict
   }
 }
 
+// Second derivatives from the gradient rows phi = G1 [nc][NV][D]: the
+// Gauss-linear sums are accumulated directly in symmetrised form,
+// acc2[v][(i,j)] = sum_f (dG_{v,i} Sw_j + dG_{v,j} Sw_i) (i < j) and
+// sum_f dG_{v,i} Sw_i (i = j), 6 (3-D) accumulators per variable instead of 9.
+template <class T, int D, int NV>
+__device__ __forceinline__ void grad2_sums(const KArgs<T>& a, const T* __restrict__ phi, int64_t c,
+                                           T (*acc2)[D * (D + 1) / 2], const T* lds, int64_t c0, int n) {
+  constexpr int NQ = NV * D;
+  constexpr int NS2 = D * (D + 1) / 2;
+  constexpr int GB = 2;
+  const int64_t b = c / KTPB;
+  const int lane = (int)(c - b * KTPB);
+  const int r0 = a.ell_ptr[b], m = (a.ell_ptr[b + 1] - r0) / KTPB;
+  T q[NQ];
+  load_row<T, NQ>(q, lds, phi, c0, n, c);
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int k = 0; k < NS2; ++k) acc2[v][k] = T(0);
+  for (int j = 0; j < m; j += GB) {
+    int64_t o[GB];
+    T Sw[GB][D];
+#pragma unroll
+    for (int jj = 0; jj < GB; ++jj) {
+      const bool ok = j + jj < m;
+      const int64_t r = (int64_t)r0 + (int64_t)(ok ? j + jj : j) * KTPB + lane;
+      GlbPtr<T> rec = as_glb(a.ell_sw + 4 * r);
+      T v[4];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) v[x] = rec[x];
+      o[jj] = ok ? rec_cell(v[3]) : c;
+#pragma unroll
+      for (int x = 0; x < D; ++x) Sw[jj][x] = ok ? v[x] : T(0);
+    }
+    T qo[GB][NQ];
+#pragma unroll
+    for (int jj = 0; jj < GB; ++jj) load_row<T, NQ>(qo[jj], lds, phi, c0, n, o[jj]);
+#pragma unroll
+    for (int jj = 0; jj < GB; ++jj)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        T dq[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) dq[i] = qo[jj][v * D + i] - q[v * D + i];
+#pragma unroll
+        for (int i = 0; i < D; ++i) acc2[v][i] += dq[i] * Sw[jj][i];
+        if constexpr (D == 3) {
+          acc2[v][3] += dq[0] * Sw[jj][1] + dq[1] * Sw[jj][0];
+          acc2[v][4] += dq[0] * Sw[jj][2] + dq[2] * Sw[jj][0];
+          acc2[v][5] += dq[1] * Sw[jj][2] + dq[2] * Sw[jj][1];
+        } else {
+          acc2[v][2] += dq[0] * Sw[jj][1] + dq[1] * Sw[jj][0];
+        }
+      }
+  }
+}
+
 // Rows of W values for the block's cells c0 .. c0+n-1, written by their
 // threads into LDS (row-major), then copied to HBM with consecutive lanes
 // on consecutive addresses.  Every thread of the block must call it.
@@ -761,7 +818,7 @@ struct GradOut {
 };
 
 template <class T, int D, int NQ, bool SYM>
-__global__ __launch_bounds__(KTPB) void k_grad(KArgs<T> a, const T* __restrict__ phi, T* __restrict__ out) {
+__device__ __forceinline__ void grad_block(const KArgs<T>& a, const T* __restrict__ phi, T* __restrict__ out) {
   using GO = GradOut<T, D, NQ, SYM>;
   __shared__ T lds[GO::LDSN];
   const int b = xcd_remap(blockIdx.x, a.cell_per_xcd, a.n_cell_blocks);
@@ -773,10 +830,10 @@ __global__ __launch_bounds__(KTPB) void k_grad(KArgs<T> a, const T* __restrict__
   const int64_t c = c0 + threadIdx.x;
   T res[GO::W];
   if (c < a.nc) {
-    T acc[NQ][D];
-    grad_sums<T, D, NQ>(a, phi, c, acc, lds, c0, n);
     const T rv = a.rV[c];
     if constexpr (!SYM) {
+      T acc[NQ][D];
+      grad_sums<T, D, NQ>(a, phi, c, acc, lds, c0, n);
 #pragma unroll
       for (int k = 0; k < NQ; ++k)
 #pragma unroll
@@ -784,19 +841,14 @@ __global__ __launch_bounds__(KTPB) void k_grad(KArgs<T> a, const T* __restrict__
     } else {
       constexpr int NV = NQ / D;
       constexpr int NS2 = D * (D + 1) / 2;
+      T acc2[NV][NS2];
+      grad2_sums<T, D, NV>(a, phi, c, acc2, lds, c0, n);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        T* o2 = res + v * NS2;
-        // acc[v*D + i][j] = d/dx_j of G1_i
 #pragma unroll
-        for (int i = 0; i < D; ++i) o2[i] = acc[v * D + i][i] * rv;
-        if constexpr (D == 3) {
-          o2[3] = T(0.5) * (acc[v * D + 0][1] + acc[v * D + 1][0]) * rv;
-          o2[4] = T(0.5) * (acc[v * D + 0][2] + acc[v * D + 2][0]) * rv;
-          o2[5] = T(0.5) * (acc[v * D + 1][2] + acc[v * D + 2][1]) * rv;
-        } else {
-          o2[2] = T(0.5) * (acc[v * D + 0][1] + acc[v * D + 1][0]) * rv;
-        }
+        for (int i = 0; i < D; ++i) res[v * NS2 + i] = acc2[v][i] * rv;
+#pragma unroll
+        for (int k = D; k < NS2; ++k) res[v * NS2 + k] = T(0.5) * acc2[v][k] * rv;
       }
     }
   }
@@ -806,6 +858,20 @@ __global__ __launch_bounds__(KTPB) void k_grad(KArgs<T> a, const T* __restrict__
 #pragma unroll
     for (int k = 0; k < GO::W; ++k) out[c * GO::W + k] = res[k];
   }
+}
+
+template <class T, int D, int NQ, bool SYM>
+__global__ __launch_bounds__(KTPB) void k_grad(KArgs<T> a, const T* __restrict__ phi, T* __restrict__ out) {
+  grad_block<T, D, NQ, SYM>(a, phi, out);
+}
+
+// The same with the register budget of 5 waves per SIMD (FP32 second
+// derivatives: 98 registers would otherwise allow only 4).
+template <class T, int D, int NQ, bool SYM>
+__global__ __launch_bounds__(KTPB) __attribute__((amdgpu_waves_per_eu(5))) void k_grad_w5(KArgs<T> a,
+                                                                                     const T* __restrict__ phi,
+                                                                                     T* __restrict__ out) {
+  grad_block<T, D, NQ, SYM>(a, phi, out);
 }
 
 // Classical sensor: beta = |s - Delta| / (|s| + |Delta| + eps) on every face
