@@ -15,6 +15,11 @@ Steps, in the paper's order:
      left:   phi_{n-1}^(m) = g^-1 (phi_{n+1}^(m) - g^n phi_n^(m+1)) + (1-g^-1) phi_n^(m)
 4. Reconstruction on the retrieved template with the coefficients of
    eq:coeff (Sec. 2.4), evaluated numerically on cell widths g^j.
+   ENO3 and WENO5 (end of Sec. 2.4) retrieve cells -2..2 and choose among
+   (ENO: Harten's rule on the printed DOLINC undivided differences) or
+   weight (WENO: Jiang-Shu smoothness indicators, linear weights that
+   reproduce the 5-cell coefficients) the three 3-cell stencils; the
+   quadratics are fitted to the retrieved cell averages directly.
 The right state comes from the same steps in the mirrored (N -> P) frame:
 cells swap, d -> -d and g -> 1/g.
 """
@@ -153,9 +158,107 @@ def cell_derivs(mesh, geo, U, order):
 def scheme_order(scheme):
     """DOLINC order: the highest differential the far cells need.  Cell -n
     (n >= 1) needs phi^(n) of the upwind cell; cell 1 + n needs phi^(n) of
-    the downwind cell."""
+    the downwind cell.  ENO3 and WENO5 choose among, or weight, the three
+    3-cell stencils inside cells -2..2, so they are second-order DOLINC
+    schemes (end of Sec. 2.4)."""
+    if scheme in NONLINEAR:
+        return 2
     k, r = SCHEMES[scheme]
     return max(0, r, k - r - 2)
+
+
+# ------------------------------------------------------------------ ENO3 / WENO5 (Sec. 2.4)
+NONLINEAR = ("ENO3", "WENO5")
+WENO_EPS = 1e-6   # the paper gives no value; the classical choice of Jiang and Shu
+
+
+def substencil_polys(g, r):
+    """Quadratic p(x) = a0 + a1 x + a2 x^2 whose averages over the cells
+    -r .. 2-r (widths g^j, cell 0 = [0, 1]) are the given cell values.
+
+    Returns M [F, 3, 3] with (a0, a1, a2) = M @ (phi_-r, .., phi_{2-r})."""
+    g = np.atleast_1d(np.asarray(g, dtype=np.float64))
+    F = g.shape[0]
+    widths = np.stack([g ** j for j in range(-r, 3 - r)], -1)        # [F, 3]
+    left = np.zeros((F, 4))                                          # cell edges
+    left[:, 1:] = np.cumsum(widths, -1)
+    left -= left[:, r:r + 1]                                         # cell 0 starts at 0
+    A = np.zeros((F, 3, 3))
+    for j in range(3):
+        a, b = left[:, j], left[:, j + 1]
+        for q in range(3):                                           # average of x^q
+            A[:, j, q] = (b ** (q + 1) - a ** (q + 1)) / ((q + 1) * (b - a))
+    return np.linalg.inv(A)
+
+
+def substencil_values_and_smoothness(t, g):
+    """For r = 0, 1, 2 (stencils {0,1,2}, {-1,0,1}, {-2,-1,0}): the value of
+    p_r at the right edge of cell 0 and the Jiang-Shu smoothness indicator
+    beta_r = int_0^1 (p_r')^2 dx + int_0^1 (p_r'')^2 dx (cell 0 has unit
+    width in the growth-scaled frame).  t: retrieved cells -2..2."""
+    q, beta = [], []
+    for r in range(3):
+        M = substencil_polys(g, r)
+        cells = np.stack([t[(j, 0)] for j in range(-r, 3 - r)], 1)     # [F, 3, ...]
+        a = np.einsum("fij,fj...->fi...", M, cells)                    # [F, 3, ...]
+        q.append(a[:, 0] + a[:, 1] + a[:, 2])
+        # p' = a1 + 2 a2 x; int_0^1 p'^2 = a1^2 + 2 a1 a2 + 4/3 a2^2; p'' = 2 a2
+        beta.append(a[:, 1] ** 2 + 2.0 * a[:, 1] * a[:, 2] + (4.0 / 3.0) * a[:, 2] ** 2 + 4.0 * a[:, 2] ** 2)
+    return q, beta
+
+
+def weno5_linear_weights(g):
+    """d_r with sum_r d_r (3-cell coefficients of stencil r) = the 5-cell
+    coefficients of eq:coeff (k = 5, r = 2), solved by least squares over
+    the five cells (the system is consistent for every g)."""
+    g = np.atleast_1d(np.asarray(g, dtype=np.float64))
+    gu, back = np.unique(g, return_inverse=True)                     # weights depend on g only
+    c5 = shu_coefficients(growth_widths(gu, 5, 2), 2)                 # cells -2..2
+    A = np.zeros((gu.shape[0], 5, 3))
+    for r in range(3):
+        c3 = shu_coefficients(growth_widths(gu, 3, r), r)             # cells -r..2-r
+        A[:, 2 - r:5 - r, r] = c3
+    d = np.stack([np.linalg.lstsq(A[f], c5[f], rcond=None)[0] for f in range(gu.shape[0])])
+    back = back.reshape(-1)
+    return d[back], A[back], c5[back]
+
+
+def eno3_select(t, g):
+    """Harten's stencil choice with the DOLINC-form undivided differences of
+    Sec. 2.4: first between {-1,0} and {0,1}, then between the two 3-cell
+    extensions of the winner.  A smaller magnitude wins; ties go to the
+    downwind candidate.  Returns r in {0, 1, 2} per face (and component)."""
+    gb = g.reshape((-1,) + (1,) * (t[(0, 0)].ndim - 1))
+    p = {j: t[(j, 0)] for j in range(-2, 3)}
+    left2 = gb * (p[0] - p[-1])
+    right2 = p[1] - p[0]
+    d3_m2 = gb ** 2 * (p[0] - (1.0 + gb) * p[-1] + gb * p[-2])       # {-2,-1,0}
+    d3_m1 = p[1] - (1.0 + gb) * p[0] + gb * p[-1]                     # {-1,0,1}
+    d3_0 = gb ** -2 * (p[2] - (1.0 + gb) * p[1] + gb * p[0])          # {0,1,2}
+    go_left = np.abs(left2) < np.abs(right2)
+    r_if_left = np.where(np.abs(d3_m2) < np.abs(d3_m1), 2, 1)
+    r_if_right = np.where(np.abs(d3_m1) < np.abs(d3_0), 1, 0)
+    return np.where(go_left, r_if_left, r_if_right)
+
+
+def nonlinear_side(G0, G1c, d, g, scheme):
+    """ENO3 / WENO5 face value at the right edge of cell 0 (upwind)."""
+    D0 = differentials(G0, d, 2)
+    D1 = differentials(G1c, d, 2)
+    table = {}
+    for m in range(3):
+        table[(0, m)] = D0[m]
+        table[(1, m)] = D1[m]
+    t = invert(table, g, -2, 2)
+    q, beta = substencil_values_and_smoothness(t, g)
+    if scheme == "ENO3":
+        r = eno3_select(t, g)
+        return np.where(r == 0, q[0], np.where(r == 1, q[1], q[2]))
+    dl, _A, _c5 = weno5_linear_weights(g)
+    shape = (-1,) + (1,) * (q[0].ndim - 1)
+    alpha = [dl[:, k].reshape(shape) / (WENO_EPS + beta[k]) ** 2 for k in range(3)]
+    tot = alpha[0] + alpha[1] + alpha[2]
+    return (alpha[0] * q[0] + alpha[1] * q[1] + alpha[2] * q[2]) / tot
 
 
 def face_states(mesh, geo, U, scheme, G=None):
@@ -166,6 +269,7 @@ def face_states(mesh, geo, U, scheme, G=None):
     P, N = mesh.owner, mesh.neighbour
     GP = [x[P] for x in G]
     GN = [x[N] for x in G]
-    UL = one_side(GP, GN, geo.d, geo.g, scheme)
-    UR = one_side(GN, GP, -geo.d, 1.0 / geo.g, scheme)
+    side = nonlinear_side if scheme in NONLINEAR else one_side
+    UL = side(GP, GN, geo.d, geo.g, scheme)
+    UR = side(GN, GP, -geo.d, 1.0 / geo.g, scheme)
     return UL, UR, G

@@ -393,3 +393,104 @@ def test_second_order_dolinc_unstable_on_jittered_tets():
     assert blows_up(0.2, "CSR4")
     assert not blows_up(0.2, "USR3")
     assert not blows_up(0.0, "CSR4")
+
+
+# ---------------------------------------------------------------- ENO3 / WENO5
+def test_weno5_linear_weights_uniform_and_consistent():
+    """Uniform mesh: the textbook weights (3/10, 6/10, 1/10) for the stencils
+    {0,1,2}, {-1,0,1}, {-2,-1,0}; on graded meshes the weighted 3-cell
+    coefficients reproduce the 5-cell ones of eq:coeff exactly, the weights
+    stay positive and sum to one."""
+    d, A, c5 = OS.weno5_linear_weights(np.array([1.0]))
+    assert np.allclose(d[0], [0.3, 0.6, 0.1], atol=1e-13)
+    g = np.array([0.5, 0.8, 1.25, 1.7, 2.0])
+    d, A, c5 = OS.weno5_linear_weights(g)
+    assert np.abs(np.einsum("fij,fj->fi", A, d) - c5).max() < 1e-12
+    assert np.all(d > 0) and np.allclose(d.sum(1), 1.0, atol=1e-13)
+    # closed form of the outer weights (middle one by the sum)
+    den = (g ** 2 + 1) * (g ** 4 + g ** 3 + g ** 2 + g + 1)
+    assert np.allclose(d[:, 0], (g ** 2 + g + 1) / den, rtol=1e-12)
+    assert np.allclose(d[:, 2], g ** 6 / den, rtol=1e-12)
+
+
+def test_smoothness_indicators_uniform_jiang_shu():
+    """g = 1: beta_r equal the Jiang-Shu closed forms
+    13/12 (second difference)^2 + 1/4 (one-sided first difference)^2."""
+    rng = np.random.default_rng(3)
+    v = rng.normal(size=(7, 5))                    # cells -2..2 per row
+    t = {(j, 0): v[:, j + 2] for j in range(-2, 3)}
+    q, beta = OS.substencil_values_and_smoothness(t, np.ones(7))
+    a, b, c, d, e = (v[:, k] for k in range(5))    # phi_-2 .. phi_2
+    js = [13 / 12 * (c - 2 * d + e) ** 2 + 1 / 4 * (3 * c - 4 * d + e) ** 2,
+          13 / 12 * (b - 2 * c + d) ** 2 + 1 / 4 * (b - d) ** 2,
+          13 / 12 * (a - 2 * b + c) ** 2 + 1 / 4 * (a - 4 * b + 3 * c) ** 2]
+    for r in range(3):
+        assert np.allclose(beta[r], js[r], rtol=1e-12, atol=1e-13)
+    # and the textbook face values of the three stencils
+    qs = [(2 * c + 5 * d - e) / 6, (-b + 5 * c + 2 * d) / 6, (2 * a - 7 * b + 11 * c) / 6]
+    for r in range(3):
+        assert np.allclose(q[r], qs[r], rtol=1e-12, atol=1e-13)
+
+
+@pytest.mark.parametrize("g", [0.6, 1.0, 1.45])
+def test_eno_weno_exact_for_quadratics(g):
+    """Cell averages of a quadratic on a constant-growth template: every
+    3-cell stencil reproduces the face value, so ENO3 and WENO5 do for any
+    stencil choice and any nonlinear weights; all beta_r coincide and WENO5
+    falls back to the linear weights."""
+    gg = np.array([g])
+    edges = np.concatenate([[0.0], np.cumsum([g ** j for j in range(-2, 3)])])
+    edges -= edges[2]                             # cell 0 = [0, 1]
+    poly = np.polynomial.Polynomial([0.3, -1.2, 0.7])
+    prim = poly.integ()
+    avg = [(prim(edges[j + 1]) - prim(edges[j])) / (edges[j + 1] - edges[j]) for j in range(5)]
+    t = {(j, 0): np.array([avg[j + 2]]) for j in range(-2, 3)}
+    q, beta = OS.substencil_values_and_smoothness(t, gg)
+    for r in range(3):
+        assert abs(q[r][0] - poly(1.0)) < 1e-12
+    assert np.ptp([b[0] for b in beta]) < 1e-11
+    r = OS.eno3_select(t, gg)
+    assert r.shape == (1,)
+
+
+def test_eno3_avoids_a_jump():
+    """A step between cells 0 and 1: ENO3 takes the upwind stencil
+    {-2,-1,0}; a step between cells -1 and 0: the downwind {0,1,2}."""
+    for step_at, want in ((1, 2), (0, 0)):
+        t = {(j, 0): np.array([1.0 if j >= step_at else 0.0]) for j in range(-2, 3)}
+        assert int(OS.eno3_select(t, np.array([1.0]))[0]) == want
+
+
+def _sine_advection_error(N, scheme, cfl, theta=False):
+    mesh = configs.line_1d(N, dim=2)
+    geo = OG.geometry(mesh)
+    c = np.floor(geo.xc[:, 0] * N + 1e-9).astype(int)
+    U0 = fields.cell_averages(mesh, fields.sine1d(), n_pts=8)
+    p = dict(pde="advection", flux="upwind", adv_vel=(1.0, 0.0, 0.0), scheme=scheme)
+    nsteps = int(np.ceil(N / cfl))
+    th = np.zeros(mesh.n_cells) if theta else None
+    U = U0.copy()
+    for _ in range(nsteps):
+        U = SV.rk_step(mesh, geo, U, 1.0 / nsteps, p, theta=th)
+    cnt = np.bincount(c, minlength=N)
+    u = np.bincount(c, weights=U[:, 0], minlength=N) / cnt
+    u0 = np.bincount(c, weights=U0[:, 0], minlength=N) / cnt
+    return np.sqrt(np.mean((u - u0) ** 2))
+
+
+def test_table2_sine_advection_nonoscillatory():
+    """1-D sine advection over one period, SSP-RK3 at a small CFL number,
+    against the paper's Table 2: ENO3, WENO5 and the Van Leer TVD scheme
+    (theta = 0 everywhere) within a few per cent, and their orders."""
+    tab = np.loadtxt(os.path.join(GOLDEN, "table2_sine_advection.txt"))
+    cases = (("ENO3", 3, 0.1, False, (0.04, 0.03)), ("WENO5", 4, 0.05, False, (0.03, 0.02)),
+             ("CD2", 1, 0.1, True, (0.06, 0.02)))
+    for sch, col, cfl, th, (tol0, tol) in cases:
+        Ns = tab[:3, 0].astype(int)
+        errs = np.array([_sine_advection_error(N, sch, cfl, th) for N in Ns])
+        ratio = errs / tab[:3, col]
+        assert abs(ratio[0] - 1) < tol0, (sch, ratio)
+        assert np.all(np.abs(ratio[1:] - 1) < tol), (sch, ratio)
+        orders = np.log2(errs[:-1] / errs[1:])
+        printed = np.log2(tab[:2, col] / tab[1:3, col])
+        assert np.all(np.abs(orders - printed) < 0.1), (sch, orders, printed)
