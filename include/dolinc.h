@@ -53,9 +53,17 @@ typedef enum { DOLINC_ADVECTION = 0, DOLINC_BURGERS = 1, DOLINC_EULER = 2 } doli
 /* k-th order reconstructions of Sec. 2.4 (k cells, r of them upwind of the
  * face): FOU k=1, CD2 k=2, USR3 k=3 r=1, CSR4 k=4 r=1 (first-order DOLINC
  * schemes, inversion eq:lCoeffDLC1 / eq:rCoeffDLC1), USR5 k=5 r=2 (second
- * order DOLINC scheme, inversion eq:lCoeffDLC2). */
+ * order DOLINC scheme, inversion eq:lCoeffDLC2).
+ * ENO3 and WENO5 (end of Sec. 2.4; second-order DOLINC schemes): cells -2..2
+ * of the face's template are retrieved as for USR5; ENO3 takes the 3-cell
+ * stencil that Harten's rule picks with the DOLINC undivided differences
+ * printed there (smaller magnitude wins, ties go downwind); WENO5 weights the
+ * three 3-cell stencils with Jiang-Shu smoothness indicators (epsilon 1e-6)
+ * and the linear weights that reproduce the 5-cell coefficients of eq:coeff
+ * on the graded template.  Applied per conserved variable. */
 typedef enum {
-  DOLINC_FOU = 1, DOLINC_CD2 = 2, DOLINC_USR3 = 3, DOLINC_CSR4 = 4, DOLINC_USR5 = 5
+  DOLINC_FOU = 1, DOLINC_CD2 = 2, DOLINC_USR3 = 3, DOLINC_CSR4 = 4, DOLINC_USR5 = 5,
+  DOLINC_ENO3 = 6, DOLINC_WENO5 = 7
 } dolinc_scheme;
 
 /* UPWIND: advection upwind flux (Sec. 3.2) and the Godunov flux of Burgers

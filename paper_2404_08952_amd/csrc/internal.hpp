@@ -30,7 +30,11 @@ namespace dolinc {
 constexpr int ELL_BLOCK = 256;
 inline int coef_left(int scheme) { return scheme <= 2 ? 1 : scheme == 3 ? 2 : scheme == 4 ? 3 : 4; }
 inline int coef_right(int scheme) { return scheme <= 2 ? 1 : scheme == 3 ? 2 : scheme == 4 ? 0 : 4; }
+// ENO3 / WENO5 records hold d and the growth rate g; their coefficients
+// are rational functions of g evaluated in the kernel.
+inline bool nonlinear_scheme(int scheme) { return scheme >= 6; }
 inline int dc_stride(int scheme) {
+  if (nonlinear_scheme(scheme)) return 4;
   int n = 3 + coef_left(scheme) + coef_right(scheme);
   return (n + 3) & ~3;
 }

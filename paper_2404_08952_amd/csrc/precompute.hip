@@ -242,8 +242,12 @@ __global__ void k_entry_fill(int64_t ne, int dim, int scheme, int dcs, const int
   o[0] = (T)dvec[3 * f + 0];
   o[1] = (T)dvec[3 * f + 1];
   o[2] = (T)dvec[3 * f + 2];
-  double w, k0, k1, k2;
   const double gf = g[f];
+  if (scheme >= 6) {  // ENO3 / WENO5: the growth rate; coefficients follow from it in the kernel
+    o[3] = (T)gf;
+    return;
+  }
+  double w, k0, k1, k2;
   // left state: frame P -> N, growth g; factors 2 and 4 of the DOLINC
   // differentials folded in (they multiply d.G1 and d.G2.d)
   side_coefficients(scheme, gf, &w, &k0, &k1, &k2);

@@ -80,7 +80,8 @@ struct SchemeInfo {
   static constexpr int ORD = SCH <= 2 ? 0 : (SCH <= 4 ? 1 : 2);
   static constexpr int NL = SCH <= 2 ? 1 : (SCH == 3 ? 2 : (SCH == 4 ? 3 : 4));
   static constexpr int NR = SCH <= 2 ? 1 : (SCH == 3 ? 2 : (SCH == 4 ? 0 : 4));
-  static constexpr int DCS = (3 + NL + NR + 3) & ~3;
+  static constexpr bool NONLIN = SCH >= 6;  // ENO3 (6), WENO5 (7): d and g only
+  static constexpr int DCS = NONLIN ? 4 : (3 + NL + NR + 3) & ~3;
 };
 
 // A partition's cells are a contiguous index range, so their rows of a
@@ -409,6 +410,107 @@ __device__ __forceinline__ void flux_hllc_pert(const T* dL, const T* dR, const T
   for (int k = 0; k < D + 2; ++k) F[k] = FK[k] * area;
 }
 
+// ---------------------------------------------------------------- ENO3 / WENO5 (end of Sec. 2.4)
+// Template cells -2..2 of one side (cell 0 upwind, width 1, cell j of width
+// gamma^j).  The coefficients of the three quadratics (stencils {0,1,2},
+// {-1,0,1}, {-2,-1,0}) are closed forms of eq:coeff and of the derivatives
+// of the fitted quadratic, as rational functions of gamma:
+//   q_r : value at the face, s_r : slope at the centre of cell 0,
+//   k_r : second derivative, w_r : linear weights that reproduce the 5-cell
+//   coefficients.
+template <class T>
+struct NonlinCoef {
+  T q[3][3], s[3][3], k[3][3], w[3], g, ig;
+};
+
+template <class T>
+__device__ __forceinline__ void nonlin_coef(T g, NonlinCoef<T>& c) {
+  const T g2 = g * g, g3 = g2 * g, g4 = g2 * g2;
+  const T A = g + T(1), B = g2 + g + T(1);
+  const T ig = fdiv(T(1), g), iB = fdiv(T(1), B), iAB = fdiv(T(1), A * B);
+  const T iCQ = fdiv(T(1), (g2 + T(1)) * (g4 + g3 + g2 + g + T(1)));
+  c.g = g;
+  c.ig = ig;
+  // r = 0: cells 0, 1, 2
+  c.q[0][0] = g2 * iB;
+  c.q[0][1] = (g2 + T(2) * g + T(2)) * iAB;
+  c.q[0][2] = -iAB;
+  c.s[0][0] = -(T(2) * g2 + T(4) * g + T(3)) * iAB;
+  c.s[0][1] = (T(2) * g3 + T(4) * g2 + T(5) * g + T(1)) * ig * iAB;
+  c.s[0][2] = -(T(2) * g + T(1)) * ig * iAB;
+  c.k[0][0] = T(6) * iAB;
+  c.k[0][1] = T(-6) * ig * iB;
+  c.k[0][2] = T(6) * ig * iAB;
+  // r = 1: cells -1, 0, 1
+  c.q[1][0] = -g3 * iAB;
+  c.q[1][1] = g * (T(2) * g2 + T(2) * g + T(1)) * iAB;
+  c.q[1][2] = iB;
+  c.s[1][0] = -g2 * (T(2) * g + T(1)) * iAB;
+  c.s[1][1] = (g - T(1)) * (T(2) * g2 + T(3) * g + T(2)) * iAB;
+  c.s[1][2] = (g + T(2)) * iAB;
+  c.k[1][0] = T(6) * g2 * iAB;
+  c.k[1][1] = T(-6) * g * iB;
+  c.k[1][2] = T(6) * g * iAB;
+  // r = 2: cells -2, -1, 0
+  c.q[2][0] = g3 * iB;
+  c.q[2][1] = -g * (g3 + T(3) * g2 + T(2) * g + T(1)) * iAB;
+  c.q[2][2] = (T(3) * g3 + T(4) * g2 + T(3) * g + T(1)) * iAB;
+  c.s[2][0] = g3 * (g + T(2)) * iAB;
+  c.s[2][1] = -g * (g3 + T(5) * g2 + T(4) * g + T(2)) * iAB;
+  c.s[2][2] = g * (T(3) * g2 + T(4) * g + T(2)) * iAB;
+  c.k[2][0] = T(6) * g4 * iAB;
+  c.k[2][1] = T(-6) * g3 * iB;
+  c.k[2][2] = T(6) * g3 * iAB;
+  c.w[0] = B * iCQ;
+  c.w[1] = g2 * A * B * iCQ;
+  c.w[2] = g3 * g3 * iCQ;
+}
+
+// Face value at the right edge of cell 0 from the upwind cell values
+// a0 = phi_0, a1 = phi_1 and the DOLINC differentials D0 = phi_0^(1),
+// D1 = phi_1^(1), E0 = phi_0^(2) of this side's frame.  Far cells by the
+// recursions of Sec. 2.3 (eq:diffDLC and its one-sided forms).
+template <class T, int SCH>
+__device__ __forceinline__ T nonlin_side(const NonlinCoef<T>& c, T a0, T a1, T D0, T D1, T E0) {
+  const T g = c.g, ig = c.ig;
+  const T pm1 = (a1 - D0) * ig + (T(1) - ig) * a0;
+  const T pm1_1 = (D1 - E0) * ig + (T(1) - ig) * D0;
+  const T pm2 = (a0 - pm1_1 * ig) * ig + (T(1) - ig) * pm1;
+  const T p2 = g * (a0 + D1) + (T(1) - g) * a1;
+  const T f[3][3] = {{a0, a1, p2}, {pm1, a0, a1}, {pm2, pm1, a0}};  // stencil r: cells -r .. 2-r
+  if constexpr (SCH == 6) {
+    // Harten's choice with the undivided differences printed for ENO3
+    const T left2 = g * (a0 - pm1), right2 = a1 - a0;
+    const T d3m2 = g * g * (a0 - (T(1) + g) * pm1 + g * pm2);
+    const T d3m1 = a1 - (T(1) + g) * a0 + g * pm1;
+    const T d3p0 = ig * ig * (p2 - (T(1) + g) * a1 + g * a0);
+    int r;
+    if (fabs(left2) < fabs(right2))
+      r = fabs(d3m2) < fabs(d3m1) ? 2 : 1;
+    else
+      r = fabs(d3m1) < fabs(d3p0) ? 1 : 0;
+    T out = T(0);
+#pragma unroll
+    for (int rr = 0; rr < 3; ++rr)
+      if (rr == r) out = c.q[rr][0] * f[rr][0] + c.q[rr][1] * f[rr][1] + c.q[rr][2] * f[rr][2];
+    return out;
+  } else {
+    T num = T(0), den = T(0);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const T q = c.q[r][0] * f[r][0] + c.q[r][1] * f[r][1] + c.q[r][2] * f[r][2];
+      const T sl = c.s[r][0] * f[r][0] + c.s[r][1] * f[r][1] + c.s[r][2] * f[r][2];
+      const T kk = c.k[r][0] * f[r][0] + c.k[r][1] * f[r][1] + c.k[r][2] * f[r][2];
+      const T beta = sl * sl + T(13.0 / 12.0) * kk * kk;
+      const T e = T(1e-6) + beta;
+      const T alpha = fdiv(c.w[r], e * e);
+      num += alpha * q;
+      den += alpha;
+    }
+    return fdiv(num, den);
+  }
+}
+
 // ---------------------------------------------------------------- face evaluation
 // Loads one face entry, reconstructs (U_L, U_R) and returns the
 // face-integrated flux F.S (owner -> neighbour).
@@ -466,6 +568,19 @@ __device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T
     contract_cell<T, NV, D, 2>(st.G2, a.G2, st.c0, st.nG2, N, dc, hN);
   }
   // reconstruction in the DOLINC representation (coefficients from precompute)
+  if constexpr (SchemeInfo<SCH>::NONLIN) {
+    // left state: frame P -> N, growth g; right state: frame N -> P,
+    // growth 1/g, d -> -d (odd differentials change sign)
+    NonlinCoef<T> cf;
+    nonlin_coef<T>(dc[3], cf);
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      UL[v] = nonlin_side<T, SCH>(cf, uP[v], uN[v], T(2) * gP[v], T(2) * gN[v], T(4) * hP[v]);
+    nonlin_coef<T>(fdiv(T(1), dc[3]), cf);
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      UR[v] = nonlin_side<T, SCH>(cf, uN[v], uP[v], T(-2) * gN[v], T(-2) * gP[v], T(4) * hN[v]);
+  } else
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     if constexpr (SCH <= 2) {
