@@ -53,9 +53,12 @@ def flux_kernel_bytes(nc, nf, nv, dim, el, scheme, blend=False):
     """Algorithmic bytes of one flux + update launch: every array it needs
     read once, its output written once (Un counted in 2 of 3 stages)."""
     ord_ = 0 if scheme in ("FOU", "CD2") else (1 if scheme in ("USR3", "CSR4") else 2)
-    nl = {"FOU": 1, "CD2": 1, "USR3": 2, "CSR4": 3, "USR5": 4}[scheme]
-    nr = {"FOU": 1, "CD2": 1, "USR3": 2, "CSR4": 0, "USR5": 4}[scheme]
-    dcs = (3 + nl + nr + 3) & ~3
+    if scheme in ("ENO3", "WENO5"):
+        dcs = 4  # d and the growth rate; coefficients are evaluated in the kernel
+    else:
+        nl = {"FOU": 1, "CD2": 1, "USR3": 2, "CSR4": 3, "USR5": 4}[scheme]
+        nr = {"FOU": 1, "CD2": 1, "USR3": 2, "CSR4": 0, "USR5": 4}[scheme]
+        dcs = (3 + nl + nr + 3) & ~3
     ns2 = dim * (dim + 1) // 2
     per_cell = nv * el + (nv * dim * el if ord_ >= 1 or blend else 0) + (nv * ns2 * el if ord_ >= 2 else 0) \
         + el + 4 + nv * el + (2.0 / 3.0) * nv * el + (4 if blend else 0)
@@ -67,10 +70,10 @@ def grad_kernel_bytes(nc, nf, nq, dim, el, out_per_cell):
     return nc * (nq * el + out_per_cell * el + el + 4) + nf * (8 + 4 * el + 4)
 
 
-def time_path(s, case, precision, extra, steps, warmup):
+def time_path(s, case, precision, extra, steps, warmup, params=None):
     import torch
     t0 = time.time()
-    s.configure(**case.params, precision=precision, **extra)
+    s.configure(**(params or case.params), precision=precision, **extra)
     if extra.get("blend") == "learned":
         s.mlp_set(indicator_weights())
     log(f"[bench] {precision}: precompute {time.time() - t0:.1f} s")
@@ -241,6 +244,19 @@ def main():
         ex = dict(extra, **(fp32_extra if prec == "fp32" else {}))
         res[prec] = time_path(solver, case, prec, ex, args.steps, args.warmup)
         log(f"[bench] {prec}: {res[prec]['ms_per_step']:.3f} ms/step, kernels ms {res[prec]['kernel_ms']}")
+    # the non-oscillatory DOLINC schemes on the same mesh (FP32, no blend)
+    nonlin = {}
+    if args.workload == "tgv3d":
+        for sch in ("WENO5", "ENO3"):
+            r = time_path(solver, case, "fp32", dict(fp32_extra, blend="none"), max(1, min(args.steps, 5)), 1,
+                          params=dict(case.params, scheme=sch))
+            fb = flux_kernel_bytes(nc, nf, nv, dim, 4, sch)[0]
+            fl = r["kernel_ms"][3] / max(r["kernel_n"][3], 1)
+            nonlin[sch] = dict(ms_per_step=r["ms_per_step"],
+                               value=nc * 3 / (r["ms_per_step"] * 1e-3),
+                               flux_kernel_avg_ms=fl, flux_kernel_gbps=fb / (fl * 1e-3) / 1e9, finite=r["finite"],
+                               min_rho=r["min_rho"], min_p=r["min_p"])
+            log(f"[bench] fp32 {sch}: {r['ms_per_step']:.3f} ms/step, kernels ms {r['kernel_ms']}")
     solver.close()
     gbps_copy = copy_bandwidth()
     log(f"[bench] streaming y = -x: {gbps_copy:.0f} GB/s")
@@ -297,6 +313,8 @@ def main():
         "fp32_detail": s32,
         "fp64_detail": s64,
         "fp32_over_fp64": s32["value"] / s64["value"],
+        "nonoscillatory_fp32": {k: dict(v, unit="cell-updates/s", scheme=k, flux="hllc", blend="none")
+                                for k, v in nonlin.items()},
         "device": dev,
         "copy_gbps": gbps_copy,
     }
