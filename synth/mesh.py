@@ -39,6 +39,10 @@ class Mesh:
     n_cells: int
     lengths: tuple             # periodic box size per axis
     info: dict = field(default_factory=dict)
+    # boundary faces: neighbour = -1 and patch[f] >= 0 (the owner is the
+    # adjacent cell, the face normal points out of the domain); None when
+    # every face is interior or periodic
+    patch: np.ndarray | None = None
 
     @property
     def n_faces(self) -> int:
@@ -56,9 +60,47 @@ class Mesh:
             ph = np.empty_like(info["parent_hex"])
             ph[p] = info["parent_hex"]
             info["parent_hex"] = ph
+        nei = np.where(self.neighbour >= 0, p[np.maximum(self.neighbour, 0)], -1)
         return Mesh(self.dim, self.nodes, self.face_ptr, self.face_nodes,
-                    p[self.owner].astype(np.int32), p[self.neighbour].astype(np.int32),
-                    self.shift, self.n_cells, self.lengths, info)
+                    p[self.owner].astype(np.int32), nei.astype(np.int32),
+                    self.shift, self.n_cells, self.lengths, info, self.patch)
+
+
+def bounded(mesh: Mesh, axis: int = 0) -> Mesh:
+    """Open the periodic direction ``axis`` of a lattice mesh made by
+    ``periodic_2d`` / ``periodic_3d`` (before any permutation): every face
+    that wrapped around becomes two boundary faces, the one at the far end
+    (patch 2 axis + 1, owned by the last cell) and its copy on the node layer
+    at the origin (patch 2 axis, owned by the first cell, nodes reversed so
+    that the normal points out of the domain)."""
+    n = mesh.info["lattice"]
+    NX = n[0] + 1
+    NY = n[1] + 1
+    stride = (1, NX, NX * NY)[axis]
+    wrap = mesh.shift[:, axis] != 0.0
+    fi = np.nonzero(wrap)[0]
+    cnt = np.diff(mesh.face_ptr)
+    new_nodes, new_cnt = [], []
+    for f in fi:
+        nodes = mesh.face_nodes[mesh.face_ptr[f]:mesh.face_ptr[f + 1]].astype(np.int64)
+        new_nodes.append((nodes - n[axis] * stride)[::-1])
+        new_cnt.append(cnt[f])
+    owner = np.concatenate([mesh.owner, mesh.neighbour[fi]]).astype(np.int32)
+    neigh = mesh.neighbour.copy()
+    neigh[fi] = -1
+    neigh = np.concatenate([neigh, np.full(fi.size, -1, dtype=np.int32)]).astype(np.int32)
+    patch = np.full(owner.size, -1, dtype=np.int32)
+    patch[fi] = 2 * axis + 1
+    patch[mesh.n_faces:] = 2 * axis
+    shift = np.concatenate([mesh.shift, np.zeros((fi.size, mesh.dim))])
+    shift[fi] = 0.0
+    lens = np.concatenate([cnt, np.asarray(new_cnt, dtype=np.int64)])
+    ptr = np.zeros(lens.size + 1, dtype=np.int64)
+    np.cumsum(lens, out=ptr[1:])
+    fn = np.concatenate([mesh.face_nodes] + [x.astype(np.int32) for x in new_nodes]).astype(np.int32)
+    info = dict(mesh.info)
+    info["open_axis"] = axis
+    return Mesh(mesh.dim, mesh.nodes, ptr, fn, owner, neigh, shift, mesh.n_cells, mesh.lengths, info, patch)
 
 
 def _lattice_coords(n, L, coords):
