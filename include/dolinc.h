@@ -16,8 +16,14 @@
  *     mesh is renumbered for locality at creation); dolinc_permutation()
  *     returns the map.  Face arrays exported by the library use the caller's
  *     face order.
- *   - Layout of a state U is [n_cells][n_v] (row-major), n_v = 1 for
+ *   - Layout of a state U is [n_rows][n_v] (row-major), n_v = 1 for
  *     advection / Burgers and dim + 2 for Euler (rho, rho*u.., rho*E).
+ *     n_rows = n_cells + the number of boundary faces: rows n_cells .. hold
+ *     the auxiliary cells of the non-coupled boundary faces (Sec. 2.6); the
+ *     library rewrites them from the boundary conditions at every stage, so
+ *     their content on input does not matter.  Without boundary faces
+ *     n_rows = n_cells.  Per-cell arrays (gradients, theta, features)
+ *     likewise have n_rows rows.
  *   - The element type of U, R and the exported gradients is double for
  *     DOLINC_FP64 and float for DOLINC_FP32_MIXED.
  *   - Return values: DOLINC_OK or an error code; dolinc_last_error() gives a
@@ -57,7 +63,8 @@ typedef enum { DOLINC_ADVECTION = 0, DOLINC_BURGERS = 1, DOLINC_EULER = 2 } doli
  * ENO3 and WENO5 (end of Sec. 2.4; second-order DOLINC schemes): cells -2..2
  * of the face's template are retrieved as for USR5; ENO3 takes the 3-cell
  * stencil that Harten's rule picks with the DOLINC undivided differences
- * printed there (smaller magnitude wins, ties go downwind); WENO5 weights the
+ * printed there (the upwind candidate wins when smaller by a relative 1e-10
+ * in FP64, 1e-5 in FP32, else the downwind one); WENO5 weights the
  * three 3-cell stencils with Jiang-Shu smoothness indicators (epsilon 1e-6)
  * and the linear weights that reproduce the 5-cell coefficients of eq:coeff
  * on the graded template.  Applied per conserved variable. */
@@ -105,7 +112,25 @@ typedef struct {
                                  /* geometry into the owner's frame (periodic)       */
   int32_t renumber;              /* 0 keep, 1 reverse Cuthill-McKee, 2 Hilbert curve */
   int32_t part_cells;            /* cells per partition (0 = default 256; <= 1024)   */
+  /* Non-coupled boundaries (Sec. 2.6).  NULL: every face has two cells.
+   * Otherwise host [n_faces]: -1 for a two-cell face; for a boundary face
+   * (neighbour[f] == -1, owner[f] the cell, normal pointing out of the
+   * domain, neigh_shift ignored) its boundary patch in [0, n_patches). */
+  const int32_t* face_patch;
+  int32_t n_patches;
 } dolinc_mesh_desc;
+
+/* Boundary conditions of a patch (Sec. 2.6): the auxiliary cell behind each
+ * boundary face takes T_O = T_C + 2 (T_f - T_C) with T_f the boundary-face
+ * value: DIRICHLET values[v] = T_f; NEUMANN values[v] = q, the outward normal
+ * gradient, T_f = T_C + q d_fC (d_fC: normal distance from the cell centre to
+ * the face; the auxiliary cell is the cell's mirror image in the face plane);
+ * ZERO_GRADIENT T_f = T_C (transmissive); SLIP_WALL (Euler) density and
+ * energy copied, momentum reflected in the face plane.  The auxiliary cell's
+ * DOLINC differentials are those of the field continued by the same rule. */
+typedef enum {
+  DOLINC_BC_ZERO_GRADIENT = 0, DOLINC_BC_DIRICHLET = 1, DOLINC_BC_NEUMANN = 2, DOLINC_BC_SLIP_WALL = 3
+} dolinc_bc;
 
 typedef struct {
   int32_t pde;                   /* dolinc_pde        */
@@ -125,13 +150,18 @@ typedef struct {
 
 typedef struct {                 /* host-side partition statistics                    */
   int64_t n_parts, n_entries, max_entries, max_cell_faces, n_slots;
+  int64_t n_rows;                /* rows of device cell arrays (cells + boundary faces) */
+  int64_t n_boundary_faces;
 } dolinc_mesh_stats;
 
 /* Validate the mesh, renumber cells, build partitions and face entries and
  * upload them (hipMalloc + synchronous copies on the null stream).  Defines
  * the problem of Sec. 2.1-2.2: cell averages on a face-addressed mesh, every
- * face shared by two cells, periodic faces carrying a translation (Sec. 2.6).
- * EMESH for unpaired / self faces, out-of-range indices or non-closed cells. */
+ * face shared by two cells (periodic faces carrying a translation, Sec. 2.6)
+ * or, with face_patch, a boundary face of one cell on a boundary patch
+ * (Sec. 2.6; an auxiliary cell is appended for it, see dolinc_set_boundary).
+ * EMESH for unpaired / self faces, out-of-range indices, boundary faces
+ * without a valid patch or non-closed cells. */
 dolinc_status dolinc_create(const dolinc_mesh_desc* mesh, dolinc_ctx* out);
 
 /* The host part of dolinc_create only (validation, renumbering, partitions);
@@ -139,9 +169,19 @@ dolinc_status dolinc_create(const dolinc_mesh_desc* mesh, dolinc_ctx* out);
 dolinc_status dolinc_mesh_prepare(const dolinc_mesh_desc* mesh, int32_t* new_of_old,
                                   dolinc_mesh_stats* stats);
 
-/* new_of_old: host [n_cells]; internal index of each caller cell. */
+/* new_of_old: host [n_cells]; internal index of each caller cell (the
+ * auxiliary cell of the k-th boundary face, in caller face order, is row
+ * n_cells + k). */
 dolinc_status dolinc_permutation(dolinc_ctx ctx, int32_t* new_of_old);
 dolinc_status dolinc_stats(dolinc_ctx ctx, dolinc_mesh_stats* stats);
+
+/* Condition of boundary patch `patch` (dolinc_bc); values: host double
+ * [n_v] for DIRICHLET / NEUMANN (ignored, may be NULL, otherwise).  Every
+ * patch starts as ZERO_GRADIENT.  Takes effect for the following calls;
+ * needs dolinc_precompute first (n_v comes from the params).  EINVAL for a
+ * patch out of range, an unknown type, missing or non-finite values, or
+ * SLIP_WALL outside the Euler equations. */
+dolinc_status dolinc_set_boundary(dolinc_ctx ctx, int32_t patch, int32_t type, const double* values);
 
 /* FP64 precompute on the device (Sec. 2.2 growth rate g and weight omega,
  * centre distance d; Sec. 2.3-2.4 inversion and reconstruction coefficients

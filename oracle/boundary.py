@@ -12,8 +12,12 @@ d_fC from the cell centre to the face centre, T_f = T_C + q d_fC, so that
 (T_O - T_C) / (2 d_fC) = q again.
 
 Readings taken here (the paper gives the values only):
-* O sits at the point reflection of x_C through the face centre, so the
-  face is midway (omega = 1/2, g = 1, d = 2 (x_f - x_C)), with V_O = V_C.
+* O is the mirror image of C in the face plane (through x_f, normal n):
+  x_O = x_C + 2 ((x_f - x_C).n) n, V_O = V_C, so the face is midway
+  (omega = 1/2, g = 1) and d = x_O - x_C is normal to the face; d_fC is the
+  normal distance (x_f - x_C).n.  With d along n the auxiliary field is the
+  exact mirror image of the cell's, so a slip wall passes no mass even on
+  skewed cells.
 * Conditions: Dirichlet (face value given), Neumann (outward normal
   gradient given), zero gradient (Neumann with q = 0, the transmissive end
   of a shock tube) and, for the Euler equations, a slip wall (density and
@@ -51,7 +55,7 @@ class Extended:
     ghost_face: np.ndarray  # [nb] its boundary face
     patch: np.ndarray       # [nb]
     normal: np.ndarray      # [nb, dim] outward unit normal
-    dist: np.ndarray        # [nb] |x_f - x_C|
+    dist: np.ndarray        # [nb] (x_f - x_C).n
 
 
 def extend(mesh):
@@ -67,12 +71,12 @@ def extend(mesh):
     with np.errstate(divide="ignore", invalid="ignore"):
         V, xc = _geom.cell_geometry(ext, S, xf, fan_c)
     C = mesh.owner[bf].astype(np.int64)
+    n = S[bf] / np.linalg.norm(S[bf], axis=1)[:, None]
+    dist = np.einsum("ka,ka->k", xf[bf] - xc[C], n)
     V[nc:] = V[C]
-    xc[nc:] = 2.0 * xf[bf] - xc[C]
+    xc[nc:] = xc[C] + 2.0 * dist[:, None] * n
     d, omega, g = _geom.face_scalars(ext, xc, xf)
     geo = _geom.Geometry(S, xf, V, xc, d, omega, g)
-    n = S[bf] / np.linalg.norm(S[bf], axis=1)[:, None]
-    dist = np.linalg.norm(xf[bf] - xc[C], axis=1)
     return Extended(ext, geo, nc, C, bf, mesh.patch[bf].astype(np.int64), n, dist)
 
 

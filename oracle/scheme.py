@@ -170,6 +170,7 @@ def scheme_order(scheme):
 # ------------------------------------------------------------------ ENO3 / WENO5 (Sec. 2.4)
 NONLINEAR = ("ENO3", "WENO5")
 WENO_EPS = 1e-6   # the paper gives no value; the classical choice of Jiang and Shu
+ENO_TIE = 1e-10   # relative margin below which two ENO candidates count as tied
 
 
 def substencil_polys(g, r):
@@ -226,8 +227,10 @@ def weno5_linear_weights(g):
 def eno3_select(t, g):
     """Harten's stencil choice with the DOLINC-form undivided differences of
     Sec. 2.4: first between {-1,0} and {0,1}, then between the two 3-cell
-    extensions of the winner.  A smaller magnitude wins; ties go to the
-    downwind candidate.  Returns r in {0, 1, 2} per face (and component)."""
+    extensions of the winner.  The upwind candidate wins only when its
+    magnitude is smaller by more than a relative ENO_TIE (ties, which the
+    mirror symmetry of a boundary produces exactly, go to the downwind
+    candidate whatever the rounding).  Returns r in {0, 1, 2} per face."""
     gb = g.reshape((-1,) + (1,) * (t[(0, 0)].ndim - 1))
     p = {j: t[(j, 0)] for j in range(-2, 3)}
     left2 = gb * (p[0] - p[-1])
@@ -235,9 +238,10 @@ def eno3_select(t, g):
     d3_m2 = gb ** 2 * (p[0] - (1.0 + gb) * p[-1] + gb * p[-2])       # {-2,-1,0}
     d3_m1 = p[1] - (1.0 + gb) * p[0] + gb * p[-1]                     # {-1,0,1}
     d3_0 = gb ** -2 * (p[2] - (1.0 + gb) * p[1] + gb * p[0])          # {0,1,2}
-    go_left = np.abs(left2) < np.abs(right2)
-    r_if_left = np.where(np.abs(d3_m2) < np.abs(d3_m1), 2, 1)
-    r_if_right = np.where(np.abs(d3_m1) < np.abs(d3_0), 1, 0)
+    keep = 1.0 - ENO_TIE
+    go_left = np.abs(left2) < keep * np.abs(right2)
+    r_if_left = np.where(np.abs(d3_m2) < keep * np.abs(d3_m1), 2, 1)
+    r_if_right = np.where(np.abs(d3_m1) < keep * np.abs(d3_0), 1, 0)
     return np.where(go_left, r_if_left, r_if_right)
 
 

@@ -29,7 +29,8 @@ class MeshDesc(C.Structure):
     _fields_ = [("dim", C.c_int32), ("n_nodes", C.c_int64), ("n_cells", C.c_int64), ("n_faces", C.c_int64),
                 ("node_xyz", C.c_void_p), ("face_node_ptr", C.c_void_p), ("face_nodes", C.c_void_p),
                 ("owner", C.c_void_p), ("neighbour", C.c_void_p), ("neigh_shift", C.c_void_p),
-                ("renumber", C.c_int32), ("part_cells", C.c_int32)]
+                ("renumber", C.c_int32), ("part_cells", C.c_int32), ("face_patch", C.c_void_p),
+                ("n_patches", C.c_int32)]
 
 
 class Params(C.Structure):
@@ -40,7 +41,8 @@ class Params(C.Structure):
 
 class MeshStats(C.Structure):
     _fields_ = [("n_parts", C.c_int64), ("n_entries", C.c_int64), ("max_entries", C.c_int64),
-                ("max_cell_faces", C.c_int64), ("n_slots", C.c_int64)]
+                ("max_cell_faces", C.c_int64), ("n_slots", C.c_int64), ("n_rows", C.c_int64),
+                ("n_boundary_faces", C.c_int64)]
 
 
 class DolincError(RuntimeError):
@@ -56,6 +58,7 @@ SIGNATURES = {
     "dolinc_mesh_prepare": [C.POINTER(MeshDesc), C.c_void_p, C.POINTER(MeshStats)],
     "dolinc_permutation": [C.c_void_p, C.c_void_p],
     "dolinc_stats": [C.c_void_p, C.POINTER(MeshStats)],
+    "dolinc_set_boundary": [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p],
     "dolinc_precompute": [C.c_void_p, C.POINTER(Params), C.c_void_p],
     "dolinc_residual": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
     "dolinc_rk_step": [C.c_void_p, C.c_void_p, C.c_double, C.c_void_p],
@@ -110,11 +113,19 @@ def mesh_desc(mesh, renumber=2, part_cells=0):
                 own=np.ascontiguousarray(mesh.owner, dtype=np.int32),
                 nei=np.ascontiguousarray(mesh.neighbour, dtype=np.int32),
                 sh=np.ascontiguousarray(mesh.shift, dtype=np.float64))
+    patch = getattr(mesh, "patch", None)
+    n_patches = 0
+    if patch is not None:
+        keep["patch"] = np.ascontiguousarray(patch, dtype=np.int32)
+        n_patches = int(keep["patch"].max()) + 1 if keep["patch"].size else 0
     d = MeshDesc(mesh.dim, mesh.n_nodes, mesh.n_cells, mesh.n_faces,
                  keep["nodes"].ctypes.data, keep["fptr"].ctypes.data, keep["fn"].ctypes.data,
                  keep["own"].ctypes.data, keep["nei"].ctypes.data, keep["sh"].ctypes.data,
-                 renumber, part_cells)
+                 renumber, part_cells, keep["patch"].ctypes.data if patch is not None else None, n_patches)
     return d, keep
+
+
+BC = {"zero_gradient": 0, "dirichlet": 1, "neumann": 2, "slip_wall": 3}
 
 
 def mesh_prepare(mesh, renumber=2, part_cells=0):
@@ -173,6 +184,9 @@ class Solver:
         _check(self.lib, self.lib.dolinc_permutation(self.h, self.perm.ctypes.data))
         self.inv = np.empty_like(self.perm)
         self.inv[self.perm] = np.arange(mesh.n_cells, dtype=np.int32)
+        st = MeshStats()
+        _check(self.lib, self.lib.dolinc_stats(self.h, C.byref(st)))
+        self.n_rows = int(st.n_rows)          # device rows: cells, then boundary auxiliary cells
         self.configure(pde, scheme, flux, precision, blend, gamma, adv_vel, burgers_dir, u_ref)
 
     def configure(self, pde, scheme, flux="upwind", precision="fp64", blend="none", gamma=1.4,
@@ -198,13 +212,23 @@ class Solver:
             raise ValueError(f"expected shape {shape}, got {tuple(t.shape)}")
         return C.c_void_p(t.data_ptr())
 
+    def set_boundary(self, patch, kind, values=None):
+        """Boundary condition of a patch: kind in BC ("zero_gradient",
+        "dirichlet", "neumann", "slip_wall"); values per conserved variable:
+        the face values (dirichlet) or outward normal gradients (neumann)."""
+        v = None
+        if values is not None:
+            v = np.ascontiguousarray(np.broadcast_to(np.asarray(values, dtype=np.float64), (self.nv,)))
+        _check(self.lib, self.lib.dolinc_set_boundary(self.h, int(patch), BC[kind],
+                                                      v.ctypes.data if v is not None else None))
+
     def empty_state(self):
-        return self.torch.empty((self.n_cells, self.nv), dtype=self.dtype, device=self.device)
+        return self.torch.empty((self.n_rows, self.nv), dtype=self.dtype, device=self.device)
 
     def to_internal(self, U):
         """Host array in caller order -> device tensor in internal order."""
         U = np.asarray(U).reshape(self.n_cells, -1)
-        out = np.empty_like(U)
+        out = np.zeros((self.n_rows, U.shape[1]), dtype=U.dtype)   # auxiliary rows: set by the library
         out[self.perm] = U
         return self.torch.from_numpy(np.ascontiguousarray(out)).to(self.device, self.dtype)
 
@@ -216,25 +240,25 @@ class Solver:
     # -- calls
     def residual(self, U, R=None):
         R = self.empty_state() if R is None else R
-        _check(self.lib, self.lib.dolinc_residual(self.h, self._ptr(U, (self.n_cells, self.nv), self.dtype),
-                                                  self._ptr(R, (self.n_cells, self.nv), self.dtype),
+        _check(self.lib, self.lib.dolinc_residual(self.h, self._ptr(U, (self.n_rows, self.nv), self.dtype),
+                                                  self._ptr(R, (self.n_rows, self.nv), self.dtype),
                                                   self._stream()))
         return R
 
     def rk_step(self, U, dt):
-        _check(self.lib, self.lib.dolinc_rk_step(self.h, self._ptr(U, (self.n_cells, self.nv), self.dtype),
+        _check(self.lib, self.lib.dolinc_rk_step(self.h, self._ptr(U, (self.n_rows, self.nv), self.dtype),
                                                  float(dt), self._stream()))
         return U
 
     def advance(self, U, dt, n):
-        _check(self.lib, self.lib.dolinc_advance(self.h, self._ptr(U, (self.n_cells, self.nv), self.dtype),
+        _check(self.lib, self.lib.dolinc_advance(self.h, self._ptr(U, (self.n_rows, self.nv), self.dtype),
                                                  float(dt), int(n), self._stream()))
         return U
 
     def gradients(self, U, second=False):
         t = self.torch
-        G1 = t.empty((self.n_cells, self.nv, self.dim), dtype=self.dtype, device=self.device)
-        G2 = t.empty((self.n_cells, self.nv, self.dim * (self.dim + 1) // 2), dtype=self.dtype,
+        G1 = t.empty((self.n_rows, self.nv, self.dim), dtype=self.dtype, device=self.device)
+        G2 = t.empty((self.n_rows, self.nv, self.dim * (self.dim + 1) // 2), dtype=self.dtype,
                      device=self.device) if second else None
         _check(self.lib, self.lib.dolinc_gradients(self.h, self._ptr(U), self._ptr(G1), self._ptr(G2),
                                                    self._stream()))
@@ -249,19 +273,19 @@ class Solver:
         return UL, UR, F
 
     def set_theta(self, theta):
-        _check(self.lib, self.lib.dolinc_set_theta(self.h, self._ptr(theta, (self.n_cells,),
+        _check(self.lib, self.lib.dolinc_set_theta(self.h, self._ptr(theta, (self.n_rows,),
                                                                      self.torch.float32), self._stream()))
 
     def classical_theta(self, U):
-        th = self.torch.empty(self.n_cells, dtype=self.torch.float32, device=self.device)
+        th = self.torch.empty(self.n_rows, dtype=self.torch.float32, device=self.device)
         _check(self.lib, self.lib.dolinc_classical_theta(self.h, self._ptr(U), self._ptr(th), self._stream()))
         return th
 
     def geometry(self):
         t = self.torch
         f64 = dict(dtype=t.float64, device=self.device)
-        V = t.empty(self.n_cells, **f64)
-        xc = t.empty((self.n_cells, self.dim), **f64)
+        V = t.empty(self.n_rows, **f64)
+        xc = t.empty((self.n_rows, self.dim), **f64)
         S = t.empty((self.n_faces, self.dim), **f64)
         xf = t.empty((self.n_faces, self.dim), **f64)
         om = t.empty(self.n_faces, **f64)
@@ -286,8 +310,8 @@ class Solver:
     # -- learned indicator
     def features(self, U, fp32=True, bf16=True):
         t = self.torch
-        X32 = t.empty((self.n_cells, N_FEATURES), dtype=t.float32, device=self.device) if fp32 else None
-        Xb = t.empty((self.n_cells, FEATURE_STRIDE), dtype=t.int16, device=self.device) if bf16 else None
+        X32 = t.empty((self.n_rows, N_FEATURES), dtype=t.float32, device=self.device) if fp32 else None
+        Xb = t.empty((self.n_rows, FEATURE_STRIDE), dtype=t.int16, device=self.device) if bf16 else None
         _check(self.lib, self.lib.dolinc_features(self.h, self._ptr(U), self._ptr(X32), self._ptr(Xb),
                                                   self._stream()))
         return X32, Xb

@@ -21,7 +21,8 @@ ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(os.path.dirname(HERE), "include")]
-SOURCES = ["mesh_prep.cpp", "api.cpp", "precompute.hip", "kernels_f64.hip", "kernels_f32.hip", "indicator.hip"]
+SOURCES = ["mesh_prep.cpp", "api.cpp", "precompute.hip", "kernels_f64.hip", "kernels_f32.hip", "indicator.hip",
+           "boundary.hip"]
 
 
 def _compile(src):

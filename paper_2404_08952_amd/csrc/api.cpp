@@ -94,6 +94,8 @@ void free_all(dolinc_ctx c) {
   DevMesh& m = c->m;
   dfree_t(m.part_ptr); dfree_t(m.ent_face); dfree_t(m.ent_pn); dfree_t(m.slot_ptr); dfree_t(m.slots);
   dfree_t(m.ell_ptr);
+  dfree_t(m.gh_cell); dfree_t(m.gh_face); dfree_t(m.gh_patch); dfree_t(m.gh_n); dfree_t(m.gh_dist);
+  dfree_t(m.bc_type); dfree_t(m.bc_val);
   dfree_t(m.face_ent); dfree_t(m.face_own); dfree_t(m.face_nei);
   dfree_t(m.nodes); dfree_t(m.fptr); dfree_t(m.fnodes); dfree_t(m.shift);
   dfree_t(m.V); dfree_t(m.xc); dfree_t(m.S); dfree_t(m.xf); dfree_t(m.fanc); dfree_t(m.omega); dfree_t(m.g);
@@ -157,15 +159,35 @@ struct TimedLaunch {
   }
 };
 
+// Auxiliary rows of a state the caller passed as const: the state is copied
+// into W1 first (only when the mesh has boundary faces).
+hipError_t ghost_input(dolinc_ctx c, const void*& U, hipStream_t s) {
+  if (!c->n_ghost) return hipSuccess;
+  hipError_t e = hipMemcpyAsync(c->w.W1, U, (size_t)c->n_cells * c->w.nv * c->w.elem, hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return e;
+  U = c->w.W1;
+  return launch_ghost(c, GHOST_U, c->w.W1, s);
+}
+
+hipError_t grad2_launch(dolinc_ctx c, const void* G1, void* G2, hipStream_t s) {
+  hipError_t e;
+  {
+    TimedLaunch t(c, s, 1);
+    e = c->w.precision == DOLINC_FP64 ? grad2_f64(c, G1, G2, s) : grad2_f32(c, G1, G2, s);
+  }
+  if (e != hipSuccess) return e;
+  return launch_ghost(c, GHOST_G2, G2, s);
+}
+
 hipError_t grad_dispatch(dolinc_ctx c, const void* U, void* G1, void* G2, hipStream_t s) {
   hipError_t e;
   {
     TimedLaunch t(c, s, 0);
     e = c->w.precision == DOLINC_FP64 ? grad_f64(c, U, G1, nullptr, s) : grad_f32(c, U, G1, nullptr, s);
   }
+  if (e == hipSuccess) e = launch_ghost(c, GHOST_G1, G1, s);
   if (e != hipSuccess || !G2) return e;
-  TimedLaunch t(c, s, 1);
-  return c->w.precision == DOLINC_FP64 ? grad2_f64(c, G1, G2, s) : grad2_f32(c, G1, G2, s);
+  return grad2_launch(c, G1, G2, s);
 }
 
 // gradients (and classical theta) that one residual evaluation of U needs
@@ -179,24 +201,26 @@ hipError_t prepare_stage(dolinc_ctx c, const void* U, hipStream_t s) {
       hipError_t e = grad_indicator_launch(c, U, c->w.G1, c->w.theta, s);
       if (e != hipSuccess) return e;
     }
-    if (ord < 2) return hipSuccess;
-    TimedLaunch t(c, s, 1);
-    return c->w.precision == DOLINC_FP64 ? grad2_f64(c, c->w.G1, c->w.G2, s) : grad2_f32(c, c->w.G1, c->w.G2, s);
+    hipError_t e = launch_ghost(c, GHOST_G1, c->w.G1, s);
+    if (e == hipSuccess) e = launch_ghost(c, GHOST_THETA, c->w.theta, s);
+    if (e != hipSuccess || ord < 2) return e;
+    return grad2_launch(c, c->w.G1, c->w.G2, s);
   }
   if (ord >= 1 || bl) {
     hipError_t e = grad_dispatch(c, U, c->w.G1, ord >= 2 ? c->w.G2 : nullptr, s);
     if (e != hipSuccess) return e;
   }
+  hipError_t e = hipSuccess;
   if (c->params.blend == DOLINC_BLEND_CLASSICAL) {
     TimedLaunch t(c, s, 2);
-    return c->w.precision == DOLINC_FP64 ? theta_f64(c, U, c->w.G1, c->w.theta, s)
-                                         : theta_f32(c, U, c->w.G1, c->w.theta, s);
-  }
-  if (c->params.blend == DOLINC_BLEND_LEARNED) {
+    e = c->w.precision == DOLINC_FP64 ? theta_f64(c, U, c->w.G1, c->w.theta, s)
+                                      : theta_f32(c, U, c->w.G1, c->w.theta, s);
+  } else if (c->params.blend == DOLINC_BLEND_LEARNED) {
     TimedLaunch t(c, s, 2);
-    return indicator_launch(c, U, c->w.theta, s);
+    e = indicator_launch(c, U, c->w.theta, s);
   }
-  return hipSuccess;
+  if (e != hipSuccess || !bl) return e;
+  return launch_ghost(c, GHOST_THETA, c->w.theta, s);
 }
 
 hipError_t stage(dolinc_ctx c, const void* Us, const void* Un, void* out, int mode, double al, double be, double dt,
@@ -256,16 +280,21 @@ dolinc_status dolinc_mesh_prepare(const dolinc_mesh_desc* mesh, int32_t* new_of_
   if (!mesh) return fail(DOLINC_EINVAL, "mesh is NULL");
   try {
     Prepared P;
+    ExtendedDesc X;
     std::string msg;
-    dolinc_status st = prepare_mesh(*mesh, P, msg);
+    dolinc_status st = extend_desc(*mesh, X, msg);
     if (st != DOLINC_OK) return fail(st, msg);
-    if (new_of_old) std::memcpy(new_of_old, P.new_of_old.data(), P.new_of_old.size() * sizeof(int32_t));
+    st = prepare_mesh(X.d, P, msg, X.n_interior);
+    if (st != DOLINC_OK) return fail(st, msg);
+    if (new_of_old) std::memcpy(new_of_old, P.new_of_old.data(), (size_t)X.n_interior * sizeof(int32_t));
     if (stats) {
       stats->n_parts = P.n_parts;
       stats->n_entries = (int64_t)P.ent_face.size();
       stats->max_entries = P.max_entries;
       stats->max_cell_faces = P.max_cell_faces;
       stats->n_slots = (int64_t)P.slots.size();
+      stats->n_rows = P.n_cells;
+      stats->n_boundary_faces = (int64_t)X.bface.size();
     }
   } catch (const std::bad_alloc&) {
     return fail(DOLINC_ENOMEM, "host allocation failed");
@@ -279,8 +308,11 @@ dolinc_status dolinc_create(const dolinc_mesh_desc* mesh, dolinc_ctx* out) {
   dolinc_ctx c = nullptr;
   try {
     Prepared P;
+    ExtendedDesc X;
     std::string msg;
-    dolinc_status st = prepare_mesh(*mesh, P, msg);
+    dolinc_status st = extend_desc(*mesh, X, msg);
+    if (st != DOLINC_OK) return fail(st, msg);
+    st = prepare_mesh(X.d, P, msg, X.n_interior);
     if (st != DOLINC_OK) return fail(st, msg);
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return fail(DOLINC_EHIP, "no HIP device");
@@ -295,14 +327,17 @@ dolinc_status dolinc_create(const dolinc_mesh_desc* mesh, dolinc_ctx* out) {
     c->max_entries = P.max_entries;
     c->max_cell_faces = P.max_cell_faces;
     c->new_of_old = P.new_of_old;
+    c->n_interior = X.n_interior;
+    c->n_ghost = (int64_t)X.bface.size();
+    c->n_patches = mesh->face_patch ? mesh->n_patches : 0;
     const int dim = P.dim;
     const int64_t nf = P.n_faces;
     std::vector<int2> pn(c->n_entries);
     for (int64_t e = 0; e < c->n_entries; ++e) pn[e] = make_int2(P.ent_p[e], P.ent_n[e]);
     std::vector<int32_t> fo(nf), fn(nf);
     for (int64_t f = 0; f < nf; ++f) {
-      fo[f] = P.new_of_old[mesh->owner[f]];
-      fn[f] = P.new_of_old[mesh->neighbour[f]];
+      fo[f] = P.new_of_old[X.d.owner[f]];
+      fn[f] = P.new_of_old[X.d.neighbour[f]];
     }
     DevMesh& m = c->m;
     hipError_t e = hipSuccess;
@@ -319,7 +354,23 @@ dolinc_status dolinc_create(const dolinc_mesh_desc* mesh, dolinc_ctx* out) {
     UP(m.nodes, mesh->node_xyz, mesh->n_nodes * dim);
     UP(m.fptr, mesh->face_node_ptr, nf + 1);
     UP(m.fnodes, mesh->face_nodes, mesh->face_node_ptr[nf]);
-    UP(m.shift, mesh->neigh_shift, nf * dim);
+    UP(m.shift, X.d.neigh_shift, nf * dim);
+    if (c->n_ghost) {
+      std::vector<int32_t> gc(c->n_ghost), gp(c->n_ghost);
+      for (int64_t k = 0; k < c->n_ghost; ++k) {
+        gc[k] = P.new_of_old[mesh->owner[X.bface[k]]];
+        gp[k] = mesh->face_patch[X.bface[k]];
+      }
+      UP(m.gh_cell, gc.data(), gc.size());
+      UP(m.gh_face, X.bface.data(), X.bface.size());
+      UP(m.gh_patch, gp.data(), gp.size());
+      std::vector<int32_t> bt(c->n_patches, DOLINC_BC_ZERO_GRADIENT);
+      std::vector<double> bv((size_t)c->n_patches * 5, 0.0);
+      UP(m.bc_type, bt.data(), bt.size());
+      UP(m.bc_val, bv.data(), bv.size());
+      if (e == hipSuccess) e = hipMalloc((void**)&m.gh_n, (size_t)c->n_ghost * 3 * sizeof(double));
+      if (e == hipSuccess) e = hipMalloc((void**)&m.gh_dist, (size_t)c->n_ghost * sizeof(double));
+    }
     {
       // sliced-ELL offsets: ELL_BLOCK cells per block, as many records per
       // cell as the block's widest cell has faces
@@ -376,7 +427,7 @@ dolinc_status dolinc_create(const dolinc_mesh_desc* mesh, dolinc_ctx* out) {
 dolinc_status dolinc_permutation(dolinc_ctx c, int32_t* new_of_old) {
   if (!valid_ctx(c)) return fail(DOLINC_ESTATE, "invalid or destroyed context");
   if (!new_of_old) return fail(DOLINC_EINVAL, "NULL output");
-  std::memcpy(new_of_old, c->new_of_old.data(), c->new_of_old.size() * sizeof(int32_t));
+  std::memcpy(new_of_old, c->new_of_old.data(), (size_t)c->n_interior * sizeof(int32_t));
   return DOLINC_OK;
 }
 
@@ -388,6 +439,28 @@ dolinc_status dolinc_stats(dolinc_ctx c, dolinc_mesh_stats* st) {
   st->max_entries = c->max_entries;
   st->max_cell_faces = c->max_cell_faces;
   st->n_slots = 2 * c->n_faces;
+  st->n_rows = c->n_cells;
+  st->n_boundary_faces = c->n_ghost;
+  return DOLINC_OK;
+}
+
+dolinc_status dolinc_set_boundary(dolinc_ctx c, int32_t patch, int32_t type, const double* values) {
+  if (!valid_ctx(c)) return fail(DOLINC_ESTATE, "invalid or destroyed context");
+  if (!c->precomputed) return fail(DOLINC_ESTATE, "dolinc_precompute has not been called");
+  if (patch < 0 || patch >= c->n_patches) return fail(DOLINC_EINVAL, "patch out of range");
+  if (type < DOLINC_BC_ZERO_GRADIENT || type > DOLINC_BC_SLIP_WALL) return fail(DOLINC_EINVAL, "unknown boundary type");
+  if (type == DOLINC_BC_SLIP_WALL && c->params.pde != DOLINC_EULER)
+    return fail(DOLINC_EINVAL, "a slip wall needs the Euler equations");
+  double v[5] = {0, 0, 0, 0, 0};
+  if (type == DOLINC_BC_DIRICHLET || type == DOLINC_BC_NEUMANN) {
+    if (!values) return fail(DOLINC_EINVAL, "this boundary type needs values");
+    for (int k = 0; k < c->w.nv; ++k) {
+      if (!std::isfinite(values[k])) return fail(DOLINC_EINVAL, "non-finite boundary value");
+      v[k] = values[k];
+    }
+  }
+  HIPCHK(hipMemcpy(c->m.bc_type + patch, &type, sizeof(int32_t), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(c->m.bc_val + 5 * (size_t)patch, v, sizeof(v), hipMemcpyHostToDevice));
   return DOLINC_OK;
 }
 
@@ -458,6 +531,7 @@ dolinc_status dolinc_residual(dolinc_ctx c, const void* U, void* R, dolinc_strea
   if (st != DOLINC_OK) return st;
   if (!U || !R) return fail(DOLINC_EINVAL, "NULL state");
   if (U == R) return fail(DOLINC_EINVAL, "U and R must differ");
+  HIPCHK(ghost_input(c, U, (hipStream_t)stream));
   HIPCHK(stage(c, U, nullptr, R, 0, 0.0, 0.0, 0.0, (hipStream_t)stream));
   return DOLINC_OK;
 }
@@ -465,8 +539,12 @@ dolinc_status dolinc_residual(dolinc_ctx c, const void* U, void* R, dolinc_strea
 static dolinc_status rk_step_impl(dolinc_ctx c, void* U, double dt, hipStream_t s) {
   // SSP-RK3 (third-order TVD Runge-Kutta, Sec. 3); stage outputs in W1, W2,
   // the last stage overwrites U cell by cell after reading it
+  // (auxiliary rows of each stage input rewritten from the boundary conditions)
+  HIPCHK(launch_ghost(c, GHOST_U, U, s));
   HIPCHK(stage(c, U, U, c->w.W1, 1, 0.0, 1.0, dt, s));
+  HIPCHK(launch_ghost(c, GHOST_U, c->w.W1, s));
   HIPCHK(stage(c, c->w.W1, U, c->w.W2, 1, 0.75, 0.25, dt, s));
+  HIPCHK(launch_ghost(c, GHOST_U, c->w.W2, s));
   HIPCHK(stage(c, c->w.W2, U, U, 1, 1.0 / 3.0, 2.0 / 3.0, dt, s));
   return DOLINC_OK;
 }
@@ -499,6 +577,7 @@ dolinc_status dolinc_set_theta(dolinc_ctx c, const float* theta, dolinc_stream s
   if (!theta) return fail(DOLINC_EINVAL, "NULL theta");
   HIPCHK(hipMemcpyAsync(c->w.theta, theta, (size_t)c->n_cells * sizeof(float), hipMemcpyDeviceToDevice,
                         (hipStream_t)stream));
+  HIPCHK(launch_ghost(c, GHOST_THETA, c->w.theta, (hipStream_t)stream));
   return DOLINC_OK;
 }
 
@@ -508,8 +587,10 @@ dolinc_status dolinc_classical_theta(dolinc_ctx c, const void* U, float* theta, 
   if (!U || !theta) return fail(DOLINC_EINVAL, "NULL argument");
   if (!c->w.G1) return fail(DOLINC_ESTATE, "no gradient workspace (scheme of order 0 without blend)");
   hipStream_t s = (hipStream_t)stream;
+  HIPCHK(ghost_input(c, U, s));
   HIPCHK(grad_dispatch(c, U, c->w.G1, nullptr, s));
   HIPCHK(c->w.precision == DOLINC_FP64 ? theta_f64(c, U, c->w.G1, theta, s) : theta_f32(c, U, c->w.G1, theta, s));
+  HIPCHK(launch_ghost(c, GHOST_THETA, theta, s));
   return DOLINC_OK;
 }
 
@@ -517,6 +598,7 @@ dolinc_status dolinc_gradients(dolinc_ctx c, const void* U, void* G1, void* G2, 
   dolinc_status st = need_ready(c, false);
   if (st != DOLINC_OK) return st;
   if (!U || !G1) return fail(DOLINC_EINVAL, "NULL argument");
+  HIPCHK(ghost_input(c, U, (hipStream_t)stream));
   HIPCHK(grad_dispatch(c, U, G1, G2, (hipStream_t)stream));
   return DOLINC_OK;
 }
@@ -526,6 +608,7 @@ dolinc_status dolinc_face_states(dolinc_ctx c, const void* U, void* UL, void* UR
   if (st != DOLINC_OK) return st;
   if (!U || !UL || !UR) return fail(DOLINC_EINVAL, "NULL argument");
   hipStream_t s = (hipStream_t)stream;
+  HIPCHK(ghost_input(c, U, s));
   HIPCHK(prepare_stage(c, U, s));
   HIPCHK(c->w.precision == DOLINC_FP64 ? export_f64(c, U, UL, UR, F, s) : export_f32(c, U, UL, UR, F, s));
   return DOLINC_OK;
@@ -556,7 +639,7 @@ dolinc_status dolinc_diagnostics(dolinc_ctx c, const void* U, double* out, dolin
   if (!U || !out) return fail(DOLINC_EINVAL, "NULL argument");
   hipStream_t s = (hipStream_t)stream;
   const int nv = c->w.nv, nout = nv + 3;
-  int nb = (int)((c->n_cells + KTPB_HOST - 1) / KTPB_HOST);
+  int nb = (int)((c->n_interior + KTPB_HOST - 1) / KTPB_HOST);
   if (nb > 1024) nb = 1024;
   HIPCHK(c->w.precision == DOLINC_FP64 ? diag_f64(c, U, c->w.diag, nb, s) : diag_f32(c, U, c->w.diag, nb, s));
   std::vector<double> part((size_t)nb * nout);
@@ -586,6 +669,7 @@ dolinc_status dolinc_features(dolinc_ctx c, const void* U, float* X32, uint16_t*
   if (c->params.pde != DOLINC_EULER) return fail(DOLINC_EUNSUPPORTED, "features are built for the Euler equations");
   if (!c->w.G1) return fail(DOLINC_ESTATE, "no gradient workspace (scheme of order 0 without blend)");
   hipStream_t s = (hipStream_t)stream;
+  HIPCHK(ghost_input(c, U, s));
   HIPCHK(grad_dispatch(c, U, c->w.G1, nullptr, s));
   HIPCHK(features_launch(c, U, X32, (unsigned short*)Xbf, s));
   return DOLINC_OK;

@@ -232,7 +232,8 @@ __global__ __launch_bounds__(KTPB) void k_diag(int64_t nc, int nv, int euler, T 
 template <class T>
 hipError_t run_diag(dolinc_ctx_s* c, const void* U, double* part, int nblocks, hipStream_t s) {
   const int euler = c->params.pde == DOLINC_EULER;
-  hipLaunchKernelGGL(k_diag<T>, dim3(nblocks), dim3(KTPB), 0, s, c->n_cells, c->w.nv, euler, (T)c->params.gamma,
+  // interior cells only (auxiliary rows follow them)
+  hipLaunchKernelGGL(k_diag<T>, dim3(nblocks), dim3(KTPB), 0, s, c->n_interior, c->w.nv, euler, (T)c->params.gamma,
                      (const T*)U, c->m.V, part);
   return hipGetLastError();
 }

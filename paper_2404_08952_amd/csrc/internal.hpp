@@ -48,6 +48,14 @@ struct DevMesh {
   int32_t* slot_ptr = nullptr;
   uint16_t* slots = nullptr;
   int32_t* ell_ptr = nullptr;    // [n_cells / ELL_BLOCK + 1] record offsets
+  // auxiliary cells of non-coupled boundary faces (row n_interior + k)
+  int32_t* gh_cell = nullptr;    // [n_ghost] internal boundary cell
+  int32_t* gh_face = nullptr;    // [n_ghost] caller face
+  int32_t* gh_patch = nullptr;   // [n_ghost]
+  double* gh_n = nullptr;        // [n_ghost][3] outward unit normal
+  double* gh_dist = nullptr;     // [n_ghost] (x_f - x_C).n
+  int32_t* bc_type = nullptr;    // [n_patches]
+  double* bc_val = nullptr;      // [n_patches][5]
   int32_t* face_ent = nullptr;   // one entry per caller face
   int32_t* face_own = nullptr;   // internal owner per caller face
   int32_t* face_nei = nullptr;
@@ -103,6 +111,8 @@ struct dolinc_ctx_s {
   int64_t n_cells = 0, n_faces = 0, n_nodes = 0, n_entries = 0, n_parts = 0;
   int part_cells = 256;
   int64_t max_entries = 0, max_cell_faces = 0, n_ell = 0;
+  int64_t n_interior = 0, n_ghost = 0;  // n_cells = n_interior + n_ghost rows
+  int32_t n_patches = 0;
   std::vector<int32_t> new_of_old;
   dolinc::DevMesh m;
   dolinc::Work w;
@@ -118,6 +128,10 @@ struct dolinc_ctx_s {
 };
 
 namespace dolinc {
+
+// Auxiliary-cell rows rewritten from the boundary conditions (boundary.hip)
+enum { GHOST_U = 0, GHOST_G1 = 1, GHOST_G2 = 2, GHOST_THETA = 3 };
+hipError_t launch_ghost(dolinc_ctx_s* c, int what, void* arr, hipStream_t s);
 
 // Launchers (kernels.hip / precompute.hip).  Return hipSuccess or an error.
 hipError_t launch_geometry(dolinc_ctx_s* c, hipStream_t s);

@@ -213,7 +213,37 @@ void rcm_order(int64_t n, const std::vector<int64_t>& ptr, const std::vector<int
   for (int64_t i = 0; i < n; ++i) new_of_old[order[n - 1 - i]] = (int32_t)i;
 }
 
-dolinc_status prepare_mesh(const dolinc_mesh_desc& d, Prepared& P, std::string& msg) {
+dolinc_status extend_desc(const dolinc_mesh_desc& in, ExtendedDesc& X, std::string& msg) {
+  X = ExtendedDesc();
+  X.d = in;
+  X.n_interior = in.n_cells;
+  if (!in.face_patch) return DOLINC_OK;
+  if (!in.owner || !in.neighbour || !in.neigh_shift) { msg = "null mesh array"; return DOLINC_EINVAL; }
+  if (in.n_patches <= 0 || in.n_patches > 1 << 20) { msg = "n_patches must be in [1, 2^20]"; return DOLINC_EINVAL; }
+  const int64_t nf = in.n_faces;
+  const int dim = in.dim == 2 ? 2 : 3;
+  X.nei.assign(in.neighbour, in.neighbour + nf);
+  X.shift.assign(in.neigh_shift, in.neigh_shift + nf * dim);
+  for (int64_t f = 0; f < nf; ++f) {
+    const int32_t p = in.face_patch[f];
+    if (in.neighbour[f] == -1) {
+      if (p < 0 || p >= in.n_patches) { msg = "boundary face " + std::to_string(f) + " has no valid patch"; return DOLINC_EMESH; }
+      X.nei[f] = (int32_t)(in.n_cells + (int64_t)X.bface.size());
+      for (int a = 0; a < dim; ++a) X.shift[f * dim + a] = 0.0;
+      X.bface.push_back((int32_t)f);
+    } else if (p != -1) {
+      msg = "face " + std::to_string(f) + " has two cells and a boundary patch";
+      return DOLINC_EMESH;
+    }
+  }
+  if (in.n_cells + (int64_t)X.bface.size() >= (int64_t)INT32_MAX) { msg = "mesh too large for 32-bit indices"; return DOLINC_EINVAL; }
+  X.d.n_cells = in.n_cells + (int64_t)X.bface.size();
+  X.d.neighbour = X.nei.data();
+  X.d.neigh_shift = X.shift.data();
+  return DOLINC_OK;
+}
+
+dolinc_status prepare_mesh(const dolinc_mesh_desc& d, Prepared& P, std::string& msg, int64_t n_interior) {
   if (d.dim != 2 && d.dim != 3) { msg = "dim must be 2 or 3"; return DOLINC_EINVAL; }
   if (d.n_cells <= 0 || d.n_faces <= 0 || d.n_nodes <= 0) { msg = "empty mesh"; return DOLINC_EINVAL; }
   if (d.n_cells >= (int64_t)INT32_MAX || d.n_faces >= (int64_t)INT32_MAX / 2 || d.n_nodes >= (int64_t)INT32_MAX) {
@@ -251,15 +281,20 @@ dolinc_status prepare_mesh(const dolinc_mesh_desc& d, Prepared& P, std::string& 
   build_cell_faces(d, cf);
   clk.lap("cell faces");
   int64_t maxcf = 0;
+  const int64_t nint = n_interior < 0 ? nc : n_interior;
   for (int64_t c = 0; c < nc; ++c) {
     int64_t k = cf.ptr[c + 1] - cf.ptr[c];
-    if (k < dim + 1) { msg = "cell " + std::to_string(c) + " is not closed (" + std::to_string(k) + " faces)"; return DOLINC_EMESH; }
+    if (c < nint && k < dim + 1) {
+      msg = "cell " + std::to_string(c) + " is not closed (" + std::to_string(k) + " faces)";
+      return DOLINC_EMESH;
+    }
     maxcf = std::max(maxcf, k);
   }
   if (maxcf > 255) { msg = "a cell has more than 255 faces"; return DOLINC_EMESH; }
 
   P = Prepared();
   P.dim = dim; P.n_cells = nc; P.n_faces = nf; P.n_nodes = nn; P.part_cells = B;
+  P.n_interior = nint;
   P.max_cell_faces = maxcf;
   if (d.renumber == 0) {
     P.new_of_old.resize(nc);
@@ -296,6 +331,16 @@ dolinc_status prepare_mesh(const dolinc_mesh_desc& d, Prepared& P, std::string& 
       }
     });
     hilbert_order(dim, nc, pts, P.new_of_old);
+  }
+  if (nint < nc) {
+    // auxiliary cells keep their rows after the renumbered interior cells
+    std::vector<int32_t> order(nc), nn2(nc);
+    for (int64_t c = 0; c < nc; ++c) order[P.new_of_old[c]] = (int32_t)c;
+    int32_t next = 0;
+    for (int64_t i = 0; i < nc; ++i)
+      if (order[i] < nint) nn2[order[i]] = next++;
+    for (int64_t c = nint; c < nc; ++c) nn2[c] = (int32_t)c;
+    P.new_of_old.swap(nn2);
   }
   clk.lap("renumber");
   P.old_of_new.resize(nc);

@@ -19,6 +19,7 @@ namespace dolinc {
 struct Prepared {
   int dim = 0;
   int64_t n_cells = 0, n_faces = 0, n_nodes = 0;
+  int64_t n_interior = 0;              // caller cells; rows n_interior.. are auxiliary cells
   int part_cells = 256;
   std::vector<int32_t> new_of_old, old_of_new;
   // partitions
@@ -32,8 +33,22 @@ struct Prepared {
   int64_t max_entries = 0, max_cell_faces = 0;
 };
 
-// Returns DOLINC_OK or an error; msg receives a description.
-dolinc_status prepare_mesh(const dolinc_mesh_desc& d, Prepared& out, std::string& msg);
+// A mesh description with non-coupled boundary faces turned into two-cell
+// faces: the k-th boundary face (in face order) gets the auxiliary cell
+// n_cells + k as its neighbour (zero shift).  Owns the arrays it points to.
+struct ExtendedDesc {
+  dolinc_mesh_desc d{};
+  std::vector<int32_t> nei;
+  std::vector<double> shift;
+  std::vector<int32_t> bface;  // caller face of auxiliary cell k
+  int64_t n_interior = 0;
+};
+dolinc_status extend_desc(const dolinc_mesh_desc& in, ExtendedDesc& X, std::string& msg);
+
+// Returns DOLINC_OK or an error; msg receives a description.  Cells from
+// n_interior on (default: none) are auxiliary cells: they need not be
+// closed and keep their indices (after the renumbered interior cells).
+dolinc_status prepare_mesh(const dolinc_mesh_desc& d, Prepared& out, std::string& msg, int64_t n_interior = -1);
 
 // Renumbering helpers (exposed for tests through dolinc_mesh_prepare).
 void rcm_order(int64_t n, const std::vector<int64_t>& adj_ptr, const std::vector<int32_t>& adj,

@@ -273,6 +273,29 @@ __global__ void k_entry_fill(int64_t ne, int dim, int scheme, int dcs, const int
   }
 }
 
+// Auxiliary cells of boundary faces: the mirror image of the boundary cell
+// in the face plane, x_O = x_C + 2 ((x_f - x_C).n) n, the same volume;
+// outward unit normal and normal centre-to-face distance for the conditions.
+__global__ void k_ghost_geom(int64_t ng, int64_t n_int, const int32_t* __restrict__ gh_cell,
+                             const int32_t* __restrict__ gh_face, const double* __restrict__ S,
+                             const double* __restrict__ xf, double* __restrict__ V, double* __restrict__ xc,
+                             double* __restrict__ gh_n, double* __restrict__ gh_dist) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= ng) return;
+  const int64_t C = gh_cell[k], O = n_int + k, f = gh_face[k];
+  V[O] = V[C];
+  double a2 = 0.0;
+  for (int x = 0; x < 3; ++x) a2 += S[3 * f + x] * S[3 * f + x];
+  const double ia = 1.0 / sqrt(a2);
+  double dn = 0.0;
+  for (int x = 0; x < 3; ++x) {
+    gh_n[3 * k + x] = S[3 * f + x] * ia;
+    dn += (xf[3 * f + x] - xc[3 * C + x]) * gh_n[3 * k + x];
+  }
+  for (int x = 0; x < 3; ++x) xc[3 * O + x] = xc[3 * C + x] + 2.0 * dn * gh_n[3 * k + x];
+  gh_dist[k] = dn;
+}
+
 // Sliced-ELL face records of every cell (layout: see internal.hpp), from
 // the per-entry records sw and dc already in the working type.
 template <class T>
@@ -335,9 +358,12 @@ hipError_t launch_geometry(dolinc_ctx_s* c, hipStream_t s) {
   DevMesh& m = c->m;
   hipLaunchKernelGGL(k_face_geom, dim3(nblk(c->n_faces)), dim3(TPB), 0, s, c->n_faces, c->dim, m.fptr, m.fnodes,
                      m.nodes, m.S, m.xf, m.fanc);
-  hipLaunchKernelGGL(k_cell_geom, dim3(nblk(c->n_cells)), dim3(TPB), 0, s, c->n_cells, c->dim, c->part_cells,
+  hipLaunchKernelGGL(k_cell_geom, dim3(nblk(c->n_interior)), dim3(TPB), 0, s, c->n_interior, c->dim, c->part_cells,
                      m.part_ptr, m.ent_face, m.slot_ptr, m.slots, m.fptr, m.fnodes, m.nodes, m.shift, m.S, m.xf,
                      m.fanc, m.V, m.xc, c->w.flag);
+  if (c->n_ghost)
+    hipLaunchKernelGGL(k_ghost_geom, dim3(nblk(c->n_ghost)), dim3(TPB), 0, s, c->n_ghost, c->n_interior, m.gh_cell,
+                       m.gh_face, m.S, m.xf, m.V, m.xc, m.gh_n, m.gh_dist);
   hipLaunchKernelGGL(k_face_scalars, dim3(nblk(c->n_faces)), dim3(TPB), 0, s, c->n_faces, c->dim, m.face_own,
                      m.face_nei, m.xc, m.shift, m.xf, m.dvec, m.omega, m.g, c->w.flag);
   return hipGetLastError();

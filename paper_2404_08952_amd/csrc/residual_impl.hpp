@@ -484,11 +484,15 @@ __device__ __forceinline__ T nonlin_side(const NonlinCoef<T>& c, T a0, T a1, T D
     const T d3m2 = g * g * (a0 - (T(1) + g) * pm1 + g * pm2);
     const T d3m1 = a1 - (T(1) + g) * a0 + g * pm1;
     const T d3p0 = ig * ig * (p2 - (T(1) + g) * a1 + g * a0);
+    // the upwind candidate must be smaller by a relative margin above the
+    // working precision's rounding (1e-10 FP64, 1e-5 FP32): exact ties (a
+    // boundary's mirror symmetry makes them) go downwind whatever the rounding
+    const T keep = T(1) - (sizeof(T) == 4 ? T(1e-5) : T(1e-10));
     int r;
-    if (fabs(left2) < fabs(right2))
-      r = fabs(d3m2) < fabs(d3m1) ? 2 : 1;
+    if (fabs(left2) < keep * fabs(right2))
+      r = fabs(d3m2) < keep * fabs(d3m1) ? 2 : 1;
     else
-      r = fabs(d3m1) < fabs(d3p0) ? 1 : 0;
+      r = fabs(d3m1) < keep * fabs(d3p0) ? 1 : 0;
     T out = T(0);
 #pragma unroll
     for (int rr = 0; rr < 3; ++rr)

@@ -69,10 +69,11 @@ class Mesh:
 def bounded(mesh: Mesh, axis: int = 0) -> Mesh:
     """Open the periodic direction ``axis`` of a lattice mesh made by
     ``periodic_2d`` / ``periodic_3d`` (before any permutation): every face
-    that wrapped around becomes two boundary faces, the one at the far end
-    (patch 2 axis + 1, owned by the last cell) and its copy on the node layer
-    at the origin (patch 2 axis, owned by the first cell, nodes reversed so
-    that the normal points out of the domain)."""
+    that wrapped around becomes two boundary faces, one per end of the
+    lattice, each owned by the cell next to it with its normal pointing out of
+    the domain (the copy has its nodes moved to the other end's node layer
+    and reversed).  Patch 2 axis is the end at the origin, 2 axis + 1 the far
+    end."""
     n = mesh.info["lattice"]
     NX = n[0] + 1
     NY = n[1] + 1
@@ -81,17 +82,21 @@ def bounded(mesh: Mesh, axis: int = 0) -> Mesh:
     fi = np.nonzero(wrap)[0]
     cnt = np.diff(mesh.face_ptr)
     new_nodes, new_cnt = [], []
-    for f in fi:
+    # shift > 0: the owner is the last cell and the face sits on the far node
+    # layer; shift < 0: the owner is the first cell, face on the origin layer
+    high = mesh.shift[fi, axis] > 0
+    for f, hi in zip(fi, high):
         nodes = mesh.face_nodes[mesh.face_ptr[f]:mesh.face_ptr[f + 1]].astype(np.int64)
-        new_nodes.append((nodes - n[axis] * stride)[::-1])
+        moved = nodes - n[axis] * stride if hi else nodes + n[axis] * stride
+        new_nodes.append(moved[::-1])
         new_cnt.append(cnt[f])
     owner = np.concatenate([mesh.owner, mesh.neighbour[fi]]).astype(np.int32)
     neigh = mesh.neighbour.copy()
     neigh[fi] = -1
     neigh = np.concatenate([neigh, np.full(fi.size, -1, dtype=np.int32)]).astype(np.int32)
     patch = np.full(owner.size, -1, dtype=np.int32)
-    patch[fi] = 2 * axis + 1
-    patch[mesh.n_faces:] = 2 * axis
+    patch[fi] = np.where(high, 2 * axis + 1, 2 * axis)
+    patch[mesh.n_faces:] = np.where(high, 2 * axis, 2 * axis + 1)
     shift = np.concatenate([mesh.shift, np.zeros((fi.size, mesh.dim))])
     shift[fi] = 0.0
     lens = np.concatenate([cnt, np.asarray(new_cnt, dtype=np.int64)])

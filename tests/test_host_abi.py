@@ -103,3 +103,24 @@ def test_no_device_is_an_error_not_a_fallback():
     assert st == b.EHIP
     assert lib.dolinc_residual(ctypes.c_void_p(1), None, None, None) == b.ESTATE
     del keep
+
+
+def test_mesh_prepare_with_boundary_faces():
+    """Boundary faces (neighbour -1 with a patch) become auxiliary rows after
+    the interior cells; a boundary face without a patch, or a two-cell face
+    with one, is a mesh error."""
+    from paper_2404_08952_amd import binding as B
+    from synth import mesh as M
+    m = M.bounded(M.periodic_3d(6, 4, 3, jitter=0.2, seed=7), 0)
+    nb = int((m.neighbour < 0).sum())
+    perm, st = B.mesh_prepare(m)
+    assert st["n_rows"] == m.n_cells + nb and st["n_boundary_faces"] == nb
+    assert np.array_equal(np.sort(perm), np.arange(m.n_cells))
+    bad = M.Mesh(m.dim, m.nodes, m.face_ptr, m.face_nodes, m.owner, m.neighbour, m.shift, m.n_cells,
+                 m.lengths, dict(m.info), np.where(m.patch >= 0, -1, m.patch).astype(np.int32))
+    with pytest.raises(B.DolincError, match="patch"):
+        B.mesh_prepare(bad)
+    bad2 = M.Mesh(m.dim, m.nodes, m.face_ptr, m.face_nodes, m.owner, m.neighbour, m.shift, m.n_cells,
+                  m.lengths, dict(m.info), np.where(m.patch >= 0, m.patch, 0).astype(np.int32))
+    with pytest.raises(B.DolincError, match="patch"):
+        B.mesh_prepare(bad2)
