@@ -56,8 +56,8 @@ def flux_kernel_bytes(nc, nf, nv, dim, el, scheme, blend=False):
     if scheme in ("ENO3", "WENO5"):
         dcs = 4  # d and the growth rate; coefficients are evaluated in the kernel
     else:
-        nl = {"FOU": 1, "CD2": 1, "USR3": 2, "CSR4": 3, "USR5": 4}[scheme]
-        nr = {"FOU": 1, "CD2": 1, "USR3": 2, "CSR4": 0, "USR5": 4}[scheme]
+        nl = {"FOU": 1, "CD2": 1, "USR3": 2, "CSR4": 3, "USR5": 4, "CSR6": 5}[scheme]
+        nr = {"FOU": 1, "CD2": 1, "USR3": 2, "CSR4": 0, "USR5": 4, "CSR6": 0}[scheme]
         dcs = (3 + nl + nr + 3) & ~3
     ns2 = dim * (dim + 1) // 2
     per_cell = nv * el + (nv * dim * el if ord_ >= 1 or blend else 0) + (nv * ns2 * el if ord_ >= 2 else 0) \
@@ -288,10 +288,10 @@ def main():
         ex = dict(extra, **(fp32_extra if prec == "fp32" else {}))
         res[prec] = time_path(solver, case, prec, ex, args.steps, args.warmup)
         log(f"[bench] {prec}: {res[prec]['ms_per_step']:.3f} ms/step, kernels ms {res[prec]['kernel_ms']}")
-    # the non-oscillatory DOLINC schemes on the same mesh (FP32, no blend)
+    # the non-oscillatory DOLINC schemes and CSR6 on the same mesh (FP32, no blend)
     nonlin = {}
     if args.workload == "tgv3d":
-        for sch in ("WENO5", "ENO3"):
+        for sch in ("WENO5", "ENO3", "CSR6"):
             r = time_path(solver, case, "fp32", dict(fp32_extra, blend="none"), max(1, min(args.steps, 5)), 1,
                           params=dict(case.params, scheme=sch))
             fb = flux_kernel_bytes(nc, nf, nv, dim, 4, sch)[0]
@@ -359,8 +359,8 @@ def main():
         "fp32_detail": s32,
         "fp64_detail": s64,
         "fp32_over_fp64": s32["value"] / s64["value"],
-        "nonoscillatory_fp32": {k: dict(v, unit="cell-updates/s", scheme=k, flux="hllc", blend="none")
-                                for k, v in nonlin.items()},
+        "other_schemes_fp32": {k: dict(v, unit="cell-updates/s", scheme=k, flux="hllc", blend="none")
+                               for k, v in nonlin.items()},
         "bounded_fp32": tube,
         "device": dev,
         "copy_gbps": gbps_copy,

@@ -59,7 +59,9 @@ typedef enum { DOLINC_ADVECTION = 0, DOLINC_BURGERS = 1, DOLINC_EULER = 2 } doli
 /* k-th order reconstructions of Sec. 2.4 (k cells, r of them upwind of the
  * face): FOU k=1, CD2 k=2, USR3 k=3 r=1, CSR4 k=4 r=1 (first-order DOLINC
  * schemes, inversion eq:lCoeffDLC1 / eq:rCoeffDLC1), USR5 k=5 r=2 (second
- * order DOLINC scheme, inversion eq:lCoeffDLC2).
+ * order DOLINC scheme, inversion eq:lCoeffDLC2), CSR6 k=6 r=2 (the central
+ * second-order DOLINC scheme named in Sec. 2.4; one state per face, both
+ * cells' second differentials, eq:lCoeffDLC2 / eq:rCoeffDLC2).
  * ENO3 and WENO5 (end of Sec. 2.4; second-order DOLINC schemes): cells -2..2
  * of the face's template are retrieved as for USR5; ENO3 takes the 3-cell
  * stencil that Harten's rule picks with the DOLINC undivided differences
@@ -70,7 +72,7 @@ typedef enum { DOLINC_ADVECTION = 0, DOLINC_BURGERS = 1, DOLINC_EULER = 2 } doli
  * on the graded template.  Applied per conserved variable. */
 typedef enum {
   DOLINC_FOU = 1, DOLINC_CD2 = 2, DOLINC_USR3 = 3, DOLINC_CSR4 = 4, DOLINC_USR5 = 5,
-  DOLINC_ENO3 = 6, DOLINC_WENO5 = 7
+  DOLINC_ENO3 = 6, DOLINC_WENO5 = 7, DOLINC_CSR6 = 8
 } dolinc_scheme;
 
 /* UPWIND: advection upwind flux (Sec. 3.2) and the Godunov flux of Burgers

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libdolinc.so")
 
 OK, EINVAL, EMESH, ENOMEM, EHIP, ESTATE, EUNSUPPORTED = range(7)
 PDE = {"advection": 0, "burgers": 1, "euler": 2}
-SCHEME = {"FOU": 1, "CD2": 2, "USR3": 3, "CSR4": 4, "USR5": 5, "ENO3": 6, "WENO5": 7}
+SCHEME = {"FOU": 1, "CD2": 2, "USR3": 3, "CSR4": 4, "USR5": 5, "ENO3": 6, "WENO5": 7, "CSR6": 8}
 FLUX = {"upwind": 0, "rusanov": 1, "hllc": 2}
 PRECISION = {"fp64": 0, "fp32": 1}
 BLEND = {"none": 0, "theta": 1, "classical": 2, "learned": 3}

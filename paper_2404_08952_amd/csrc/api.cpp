@@ -107,7 +107,7 @@ void free_all(dolinc_ctx c) {
 dolinc_status check_params(const dolinc_params* p, int dim) {
   if (!p) return fail(DOLINC_EINVAL, "params is NULL");
   if (p->pde < 0 || p->pde > 2) return fail(DOLINC_EINVAL, "unknown pde");
-  if (p->scheme < 1 || p->scheme > 7) return fail(DOLINC_EINVAL, "unknown scheme");
+  if (p->scheme < 1 || p->scheme > 8) return fail(DOLINC_EINVAL, "unknown scheme");
   if (p->precision < 0 || p->precision > 1) return fail(DOLINC_EINVAL, "unknown precision");
   if (p->blend < 0 || p->blend > 3) return fail(DOLINC_EINVAL, "unknown blend");
   if (p->flux < 0 || p->flux > 2) return fail(DOLINC_EINVAL, "unknown flux");

@@ -95,6 +95,7 @@ hipError_t flux_by_scheme(int sch, const KArgs<T>& a, size_t lds, hipStream_t s,
     case 5: return go_flux<T, D, PK, 5, BL>(a, lds, s, ex);
     case 6: return go_flux<T, D, PK, 6, BL>(a, lds, s, ex);
     case 7: return go_flux<T, D, PK, 7, BL>(a, lds, s, ex);
+    case 8: return go_flux<T, D, PK, 8, BL>(a, lds, s, ex);
   }
   return hipErrorInvalidValue;
 }

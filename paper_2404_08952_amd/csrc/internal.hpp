@@ -28,11 +28,13 @@ namespace dolinc {
 //                  sum_r (phi_o - phi_c) ell_sw[r][0..D).
 //   ell_d[r][4]  : sigma d_x, sigma d_y, sigma d_z, sigma (0 for padding).
 constexpr int ELL_BLOCK = 256;
-inline int coef_left(int scheme) { return scheme <= 2 ? 1 : scheme == 3 ? 2 : scheme == 4 ? 3 : 4; }
-inline int coef_right(int scheme) { return scheme <= 2 ? 1 : scheme == 3 ? 2 : scheme == 4 ? 0 : 4; }
+inline int coef_left(int scheme) {
+  return scheme <= 2 ? 1 : scheme == 3 ? 2 : scheme == 4 ? 3 : scheme == 8 ? 5 : 4;
+}
+inline int coef_right(int scheme) { return scheme <= 2 ? 1 : scheme == 3 ? 2 : (scheme == 4 || scheme == 8) ? 0 : 4; }
 // ENO3 / WENO5 records hold d and the growth rate g; their coefficients
 // are rational functions of g evaluated in the kernel.
-inline bool nonlinear_scheme(int scheme) { return scheme >= 6; }
+inline bool nonlinear_scheme(int scheme) { return scheme == 6 || scheme == 7; }
 inline int dc_stride(int scheme) {
   if (nonlinear_scheme(scheme)) return 4;
   int n = 3 + coef_left(scheme) + coef_right(scheme);

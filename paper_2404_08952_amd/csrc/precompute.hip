@@ -172,7 +172,8 @@ __global__ void k_face_scalars(int64_t nf, int dim, const int32_t* __restrict__ 
 
 // DOLINC representation of one side (self = upwind cell of this frame,
 // growth rate g from self to other).  w, k0, k1, k2 as in the file comment.
-__device__ void side_coefficients(int scheme, double g, double* w, double* k0, double* k1, double* k2) {
+__device__ void side_coefficients(int scheme, double g, double* w, double* k0, double* k1, double* k2,
+                                  double* k3 = nullptr) {
   *k0 = 0.0; *k1 = 0.0; *k2 = 0.0;
   const double ig = 1.0 / g;
   const double g2 = g * g, g3 = g2 * g, g4 = g3 * g, g5 = g4 * g;
@@ -220,6 +221,20 @@ __device__ void side_coefficients(int scheme, double g, double* w, double* k0, d
       *k2 = c0 * ig3;
       return;
     }
+    case DOLINC_CSR6: {
+      // eq:coeff on the six cells -2..3 with the far cells from eq:lCoeffDLC2
+      // (phi_-2), eq:lCoeffDLC1 (phi_-1), eq:rCoeffDLC1 (phi_2) and
+      // eq:rCoeffDLC2 (phi_3), collected on phi_0, phi_1 and the differentials
+      // (closed forms in g; 1/2, 3/20, -3/20, 1/60, 1/60 at g = 1)
+      const double gm = g2 - g + 1.0;
+      const double den = G2 * (1.0 + g2) * G5;
+      *w = g * (g5 * g + 5.0 * g5 + 4.0 * g4 + 2.0 * g3 + 2.0 * g2 - g - 3.0) / den;
+      *k0 = g2 * (2.0 * g5 * g + g3 - g + 1.0) / (den * gm);
+      *k1 = -g * (g5 * g - g5 + g3 + 2.0) / (den * gm);
+      *k2 = g4 * g5 / (den * gm * G3);
+      if (k3) *k3 = g2 / (den * gm * G3);
+      return;
+    }
     default:
       *w = 1.0;
   }
@@ -243,15 +258,19 @@ __global__ void k_entry_fill(int64_t ne, int dim, int scheme, int dcs, const int
   o[1] = (T)dvec[3 * f + 1];
   o[2] = (T)dvec[3 * f + 2];
   const double gf = g[f];
-  if (scheme >= 6) {  // ENO3 / WENO5: the growth rate; coefficients follow from it in the kernel
+  if (scheme == DOLINC_ENO3 || scheme == DOLINC_WENO5) {  // the growth rate; coefficients follow in the kernel
     o[3] = (T)gf;
     return;
   }
-  double w, k0, k1, k2;
+  double w, k0, k1, k2, k3 = 0.0;
   // left state: frame P -> N, growth g; factors 2 and 4 of the DOLINC
   // differentials folded in (they multiply d.G1 and d.G2.d)
-  side_coefficients(scheme, gf, &w, &k0, &k1, &k2);
+  side_coefficients(scheme, gf, &w, &k0, &k1, &k2, &k3);
   int k = 3;
+  if (scheme == DOLINC_CSR6) {  // symmetric template: one state per face
+    o[k++] = (T)w; o[k++] = (T)(2.0 * k0); o[k++] = (T)(2.0 * k1); o[k++] = (T)(4.0 * k2); o[k++] = (T)(4.0 * k3);
+    return;
+  }
   if (scheme <= DOLINC_CD2) {
     o[k++] = (T)w;
   } else if (scheme == DOLINC_USR3) {

@@ -78,9 +78,9 @@ struct NVars {
 template <int SCH>
 struct SchemeInfo {
   static constexpr int ORD = SCH <= 2 ? 0 : (SCH <= 4 ? 1 : 2);
-  static constexpr int NL = SCH <= 2 ? 1 : (SCH == 3 ? 2 : (SCH == 4 ? 3 : 4));
-  static constexpr int NR = SCH <= 2 ? 1 : (SCH == 3 ? 2 : (SCH == 4 ? 0 : 4));
-  static constexpr bool NONLIN = SCH >= 6;  // ENO3 (6), WENO5 (7): d and g only
+  static constexpr int NL = SCH <= 2 ? 1 : (SCH == 3 ? 2 : (SCH == 4 ? 3 : (SCH == 8 ? 5 : 4)));
+  static constexpr int NR = SCH <= 2 ? 1 : (SCH == 3 ? 2 : ((SCH == 4 || SCH == 8) ? 0 : 4));
+  static constexpr bool NONLIN = SCH == 6 || SCH == 7;  // ENO3, WENO5: d and g only
   static constexpr int DCS = NONLIN ? 4 : (3 + NL + NR + 3) & ~3;
 };
 
@@ -595,6 +595,9 @@ __device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T
       UR[v] = uP[v] + dc[5] * (uN[v] - uP[v]) + dc[6] * gN[v];
     } else if constexpr (SCH == 4) {
       UL[v] = uN[v] + dc[3] * (uP[v] - uN[v]) + dc[4] * gP[v] + dc[5] * gN[v];
+      UR[v] = UL[v];
+    } else if constexpr (SCH == 8) {  // CSR6: symmetric template, both second differentials
+      UL[v] = uN[v] + dc[3] * (uP[v] - uN[v]) + dc[4] * gP[v] + dc[5] * gN[v] + dc[6] * hP[v] + dc[7] * hN[v];
       UR[v] = UL[v];
     } else {
       UL[v] = uN[v] + dc[3] * (uP[v] - uN[v]) + dc[4] * gP[v] + dc[5] * gN[v] + dc[6] * hP[v];

@@ -93,7 +93,7 @@ def test_gradient_parity(name, geos):
     _close(G2.cpu().numpy()[s.perm], r2p)
 
 
-@pytest.mark.parametrize("scheme", ["FOU", "CD2", "USR3", "CSR4", "USR5"])
+@pytest.mark.parametrize("scheme", ["FOU", "CD2", "USR3", "CSR4", "USR5", "CSR6"])
 @pytest.mark.parametrize("name", ["tri2d", "mixed2d", "mixed3d"])
 def test_face_state_parity(name, scheme, geos):
     mesh, geo = MESHES[name], geos[name]
@@ -102,8 +102,11 @@ def test_face_state_parity(name, scheme, geos):
     s = _solver(mesh, pde="advection", scheme=scheme)
     UL, UR, F = s.face_states(s.to_internal(U))
     rL, rR, _ = OS.face_states(mesh, geo, U, scheme)
-    _close(UL.cpu().numpy(), rL)
-    _close(UR.cpu().numpy(), rR)
+    # the six-cell template's coefficients grow like g^5 on the most skewed
+    # faces of the jittered meshes, which amplifies rounding tenfold there
+    rtol = 1e-9 if scheme == "CSR6" else 1e-10
+    _close(UL.cpu().numpy(), rL, rtol=rtol)
+    _close(UR.cpu().numpy(), rR, rtol=rtol)
 
 
 RES_CASES = [
@@ -121,6 +124,8 @@ RES_CASES = [
     ("hex3d", dict(pde="euler", scheme="CD2", flux="rusanov")),
     ("mixed3d", dict(pde="euler", scheme="USR3", flux="rusanov")),
     ("mixed3d", dict(pde="euler", scheme="USR5", flux="hllc")),
+    ("hex3d", dict(pde="euler", scheme="CSR6", flux="rusanov")),
+    ("mixed2d", dict(pde="burgers", scheme="CSR6")),
 ]
 
 
@@ -140,11 +145,12 @@ def test_residual_parity(name, kw, geos):
     s = _solver(mesh, **kw)
     R = s.to_external(s.residual(s.to_internal(U)))
     ref = SV.residual(mesh, geo, U, oracle_params(kw))
+    rtol = 1e-9 if kw["scheme"] == "CSR6" else 1e-10
     for v in range(ref.shape[1]):
-        _close(R[:, v], ref[:, v])
+        _close(R[:, v], ref[:, v], rtol=rtol)
     # exported face fluxes against the oracle's face fluxes
     _UL, _UR, F = s.face_states(s.to_internal(U))
-    _close(F.cpu().numpy(), SV.face_flux(mesh, geo, U, oracle_params(kw)))
+    _close(F.cpu().numpy(), SV.face_flux(mesh, geo, U, oracle_params(kw)), rtol=rtol)
 
 
 @pytest.mark.parametrize("name,kw", [RES_CASES[1], RES_CASES[5], RES_CASES[10], RES_CASES[8]],
@@ -163,8 +169,9 @@ def test_rk_step_parity(name, kw, geos):
     _close(s.to_external(Ud), ref, rtol=1e-10, afloor=1e-12)
 
 
-@pytest.mark.parametrize("name,kw", [RES_CASES[0], RES_CASES[4], RES_CASES[5], RES_CASES[8], RES_CASES[10]],
-                         ids=["adv-USR3", "burgers-USR3", "burgers-CSR4", "euler-CSR4", "euler-USR5"])
+@pytest.mark.parametrize("name,kw", [RES_CASES[0], RES_CASES[4], RES_CASES[5], RES_CASES[8], RES_CASES[10],
+                                     RES_CASES[14]],
+                         ids=["adv-USR3", "burgers-USR3", "burgers-CSR4", "euler-CSR4", "euler-USR5", "euler-CSR6"])
 def test_fp32_stage_error(name, kw, geos):
     """FP32 bulk with FP64-derived coefficients: per-variable relative L2 of
     R32 against the FP64 oracle on the same FP32-rounded input <= 1e-5."""
@@ -293,9 +300,10 @@ def test_c1_end_to_end_against_oracle_and_exact():
 
 
 def test_design_order_on_uniform_line():
-    """USR3 / CSR4 advection of a sine on a uniform periodic line through the
-    GPU path with SSP-RK3 at a small CFL: observed orders 3 and 4."""
-    for scheme, order in (("USR3", 3.0), ("CSR4", 4.0)):
+    """USR3 / CSR4 / CSR6 advection of a sine on a uniform periodic line
+    through the GPU path with SSP-RK3 at a small CFL: observed orders 3, 4
+    and 6."""
+    for scheme, order in (("USR3", 3.0), ("CSR4", 4.0), ("CSR6", 6.0)):
         errs = []
         for n in (32, 64):
             mesh = configs.line_1d(n, dim=2)

@@ -116,7 +116,7 @@ def test_inversion_recovers_far_cells(g):
             assert abs(t[(j, 0)][0, 0] - ucol[i + j]) < 1e-13 * scale
 
 
-@pytest.mark.parametrize("scheme", ["USR3", "CSR4", "USR5"])
+@pytest.mark.parametrize("scheme", ["USR3", "CSR4", "USR5", "CSR6"])
 @pytest.mark.parametrize("g", [0.8, 1.0, 1.25])
 def test_dolinc_equals_classical_reconstruction(scheme, g):
     """On constant growth the DOLINC face value equals the classical
@@ -494,3 +494,28 @@ def test_table2_sine_advection_nonoscillatory():
         orders = np.log2(errs[:-1] / errs[1:])
         printed = np.log2(tab[:2, col] / tab[1:3, col])
         assert np.all(np.abs(orders - printed) < 0.1), (sch, orders, printed)
+
+
+def test_csr6_design_order_on_sine_advection():
+    """CSR6 (k = 6, the central second-order DOLINC scheme of Sec. 2.4) on
+    the 1-D sine advection with exact time integration (as for Table 1):
+    sixth-order error decay, and at every N below CSR4's error."""
+    errs = {}
+    for sch in ("CSR4", "CSR6"):
+        errs[sch] = []
+        for N in (20, 40, 80):
+            mesh = configs.line_1d(N, dim=2)
+            geo = OG.geometry(mesh)
+            c = np.floor(geo.xc[:, 0] * N + 1e-9).astype(int)
+            p = dict(pde="advection", flux="upwind", adv_vel=(1.0, 0.0, 0.0), scheme=sch)
+            R = SV.residual(mesh, geo, (c == 0).astype(float)[:, None], p)[:, 0]
+            a = np.bincount(c, weights=R, minlength=N) / np.bincount(c, minlength=N)
+            lam = np.fft.fft(a)
+            U0 = fields.cell_averages(mesh, fields.sine1d(), n_pts=8)[:, 0]
+            u0 = np.bincount(c, weights=U0, minlength=N) / np.bincount(c, minlength=N)
+            uT = np.real(np.fft.ifft(np.exp(lam) * np.fft.fft(u0)))
+            errs[sch].append(np.sqrt(np.mean((uT - u0) ** 2)))
+    e6 = np.array(errs["CSR6"])
+    orders = np.log2(e6[:-1] / e6[1:])
+    assert np.all(np.abs(orders - 6.0) < 0.15), orders
+    assert np.all(e6 < np.array(errs["CSR4"]))
