@@ -24,8 +24,8 @@ namespace dolinc {
 namespace {
 
 constexpr int BTPB = 256;
-constexpr int BC_ZG = DOLINC_BC_ZERO_GRADIENT, BC_DIR = DOLINC_BC_DIRICHLET, BC_NEU = DOLINC_BC_NEUMANN,
-              BC_WALL = DOLINC_BC_SLIP_WALL;
+// (zero gradient is the default branch: T_f = T_C)
+constexpr int BC_DIR = DOLINC_BC_DIRICHLET, BC_NEU = DOLINC_BC_NEUMANN, BC_WALL = DOLINC_BC_SLIP_WALL;
 
 struct GhostArgs {
   int64_t ng, n_int;
