@@ -181,3 +181,29 @@ def test_reflecting_wall_on_gpu():
     near = x > 0.5
     assert np.mean(np.abs(U[near, 0] - ex[0][near])) < 0.02
     assert U[x > 0.95, 0].min() > 1.4
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_theta_blend_with_boundaries(precision, meshes):
+    """Blend with given per-cell weights next to walls and a Dirichlet inflow:
+    the auxiliary cells take their boundary cell's weight."""
+    mesh, X = meshes["mixed3d"]
+    rng = np.random.default_rng(25)
+    U = _euler_state(mesh.n_cells, rng)
+    if precision == "fp32":
+        U = U.astype(np.float32).astype(np.float64)
+    theta = rng.random(mesh.n_cells).astype(np.float32)
+    bcs = {0: (OB.DIRICHLET, [1.05, 0.1, 0.0, 0.0, 2.5]), 1: (OB.SLIP_WALL,)}
+    kw = dict(pde="euler", scheme="USR5", flux="hllc")
+    extra = dict(u_ref=_uref(U)) if precision == "fp32" else {}
+    s = _solver(mesh, bcs, blend="theta", precision=precision, **kw, **extra)
+    th = np.zeros(s.n_rows, dtype=np.float32)
+    th[s.perm] = theta
+    s.set_theta(s.torch.from_numpy(th).to(s.device))
+    R = s.to_external(s.residual(s.to_internal(U)))
+    ref = OB.residual(X, U, oracle_params(kw), bcs, theta=theta.astype(np.float64))
+    if precision == "fp64":
+        for v in range(ref.shape[1]):
+            _close(R[:, v], ref[:, v])
+    else:
+        assert max(_group_errors(R, ref)) <= 1e-5
