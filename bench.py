@@ -59,10 +59,10 @@ def flux_kernel_bytes(nc, nf, nv, dim, el, scheme, blend=False):
         nl = {"FOU": 1, "CD2": 1, "USR3": 2, "CSR4": 3, "USR5": 4, "CSR6": 5}[scheme]
         nr = {"FOU": 1, "CD2": 1, "USR3": 2, "CSR4": 0, "USR5": 4, "CSR6": 0}[scheme]
         dcs = (3 + nl + nr + 3) & ~3
-    ns2 = dim * (dim + 1) // 2
-    per_cell = nv * el + (nv * dim * el if ord_ >= 1 or blend else 0) + (nv * ns2 * el if ord_ >= 2 else 0) \
+    # second differentials arrive contracted with d, one value per face side
+    per_cell = nv * el + (nv * dim * el if ord_ >= 1 or blend else 0) \
         + el + 4 + nv * el + (2.0 / 3.0) * nv * el + (4 if blend else 0)
-    per_face = 8 + 4 * el + dcs * el + 4
+    per_face = 8 + 4 * el + dcs * el + 4 + (2 * nv * el if ord_ >= 2 else 0)
     return nc * per_cell + nf * per_face, per_cell, per_face
 
 

@@ -24,6 +24,8 @@ hipError_t grad_f64(dolinc_ctx_s*, const void*, void*, void*, hipStream_t);
 hipError_t grad_f32(dolinc_ctx_s*, const void*, void*, void*, hipStream_t);
 hipError_t grad2_f64(dolinc_ctx_s*, const void*, void*, hipStream_t);
 hipError_t grad2_f32(dolinc_ctx_s*, const void*, void*, hipStream_t);
+hipError_t hface_f64(dolinc_ctx_s*, const void*, void*, hipStream_t);
+hipError_t hface_f32(dolinc_ctx_s*, const void*, void*, hipStream_t);
 hipError_t theta_f64(dolinc_ctx_s*, const void*, const void*, float*, hipStream_t);
 hipError_t theta_f32(dolinc_ctx_s*, const void*, const void*, float*, hipStream_t);
 hipError_t diag_f64(dolinc_ctx_s*, const void*, double*, int, hipStream_t);
@@ -80,7 +82,7 @@ void dfree_t(X*& p) {
 
 void free_work(dolinc_ctx c) {
   Work& w = c->w;
-  dfree(w.sw); dfree(w.ell_sw); dfree(w.ell_d); dfree(w.dc); dfree(w.rV); dfree(w.G1); dfree(w.G2); dfree(w.W1); dfree(w.W2);
+  dfree(w.sw); dfree(w.ell_sw); dfree(w.ell_d); dfree(w.dc); dfree(w.rV); dfree(w.G1); dfree(w.Hf); dfree(w.W1); dfree(w.W2);
   dfree_t(w.theta);
   w.scheme = w.precision = -1;
   w.nv = 0;
@@ -93,8 +95,8 @@ void free_all(dolinc_ctx c) {
   free_mlp(c);
   DevMesh& m = c->m;
   dfree_t(m.part_ptr); dfree_t(m.ent_face); dfree_t(m.ent_pn); dfree_t(m.slot_ptr); dfree_t(m.slots);
-  dfree_t(m.ell_ptr);
-  dfree_t(m.gh_cell); dfree_t(m.gh_face); dfree_t(m.gh_patch); dfree_t(m.gh_n); dfree_t(m.gh_dist);
+  dfree_t(m.ent_rec); dfree_t(m.ell_ptr);
+  dfree_t(m.gh_cell); dfree_t(m.gh_face); dfree_t(m.gh_patch); dfree_t(m.gh_ent); dfree_t(m.gh_n); dfree_t(m.gh_dist);
   dfree_t(m.bc_type); dfree_t(m.bc_val);
   dfree_t(m.face_ent); dfree_t(m.face_own); dfree_t(m.face_nei);
   dfree_t(m.nodes); dfree_t(m.fptr); dfree_t(m.fnodes); dfree_t(m.shift);
@@ -179,6 +181,17 @@ hipError_t grad2_launch(dolinc_ctx c, const void* G1, void* G2, hipStream_t s) {
   return launch_ghost(c, GHOST_G2, G2, s);
 }
 
+// second differentials of a stage, contracted per face record into w.Hf
+hipError_t hface_launch(dolinc_ctx c, const void* G1, hipStream_t s) {
+  hipError_t e;
+  {
+    TimedLaunch t(c, s, 1);
+    e = c->w.precision == DOLINC_FP64 ? hface_f64(c, G1, c->w.Hf, s) : hface_f32(c, G1, c->w.Hf, s);
+  }
+  if (e != hipSuccess) return e;
+  return launch_ghost(c, GHOST_HF, c->w.Hf, s);
+}
+
 hipError_t grad_dispatch(dolinc_ctx c, const void* U, void* G1, void* G2, hipStream_t s) {
   hipError_t e;
   {
@@ -204,10 +217,11 @@ hipError_t prepare_stage(dolinc_ctx c, const void* U, hipStream_t s) {
     hipError_t e = launch_ghost(c, GHOST_G1, c->w.G1, s);
     if (e == hipSuccess) e = launch_ghost(c, GHOST_THETA, c->w.theta, s);
     if (e != hipSuccess || ord < 2) return e;
-    return grad2_launch(c, c->w.G1, c->w.G2, s);
+    return hface_launch(c, c->w.G1, s);
   }
   if (ord >= 1 || bl) {
-    hipError_t e = grad_dispatch(c, U, c->w.G1, ord >= 2 ? c->w.G2 : nullptr, s);
+    hipError_t e = grad_dispatch(c, U, c->w.G1, nullptr, s);
+    if (e == hipSuccess && ord >= 2) e = hface_launch(c, c->w.G1, s);
     if (e != hipSuccess) return e;
   }
   hipError_t e = hipSuccess;
@@ -356,12 +370,20 @@ dolinc_status dolinc_create(const dolinc_mesh_desc* mesh, dolinc_ctx* out) {
     UP(m.fnodes, mesh->face_nodes, mesh->face_node_ptr[nf]);
     UP(m.shift, X.d.neigh_shift, nf * dim);
     if (c->n_ghost) {
-      std::vector<int32_t> gc(c->n_ghost), gp(c->n_ghost);
+      std::vector<int32_t> gc(c->n_ghost), gp(c->n_ghost), ge(c->n_ghost);
       for (int64_t k = 0; k < c->n_ghost; ++k) {
         gc[k] = P.new_of_old[mesh->owner[X.bface[k]]];
         gp[k] = mesh->face_patch[X.bface[k]];
+        // the face's entry in its cell's partition: owner (side 0) = the cell
+        ge[k] = P.face_first_ent[X.bface[k]];
+        if (P.ent_p[ge[k]] != gc[k] || P.ent_n[ge[k]] != (int32_t)(X.n_interior + k)) {
+          free_all(c);
+          delete c;
+          return fail(DOLINC_EMESH, "internal: boundary face entry does not join its cell and auxiliary cell");
+        }
       }
       UP(m.gh_cell, gc.data(), gc.size());
+      UP(m.gh_ent, ge.data(), ge.size());
       UP(m.gh_face, X.bface.data(), X.bface.size());
       UP(m.gh_patch, gp.data(), gp.size());
       std::vector<int32_t> bt(c->n_patches, DOLINC_BC_ZERO_GRADIENT);
@@ -387,6 +409,24 @@ dolinc_status dolinc_create(const dolinc_mesh_desc* mesh, dolinc_ctx* out) {
       if (tot > INT32_MAX && e == hipSuccess) e = hipErrorInvalidValue;  // reported below
       c->n_ell = tot;
       UP(m.ell_ptr, ep.data(), ep.size());
+      // every entry names the record of its face in the owner's and in the
+      // neighbour's list (a seam face's two entries name the same records)
+      std::vector<int2> er(c->n_entries, make_int2(-1, -1));
+      for (int64_t cc = 0; cc < P.n_cells; ++cc) {
+        const int64_t b = cc / ELL_BLOCK, ln = cc % ELL_BLOCK;
+        const int64_t e0 = P.part_ent_ptr[cc / P.part_cells];
+        for (int32_t s = P.slot_ptr[cc]; s < P.slot_ptr[cc + 1]; ++s) {
+          const int32_t r = (int32_t)(ep[b] + (int64_t)(s - P.slot_ptr[cc]) * ELL_BLOCK + ln);
+          const int side = P.slots[s] >> 15;
+          const int64_t eo = e0 + (P.slots[s] & 0x7fff);
+          (side ? er[eo].y : er[eo].x) = r;
+          const int32_t tw = P.slot_twin[s];
+          if (tw >= 0) ((tw & 1) ? er[tw >> 1].y : er[tw >> 1].x) = r;
+        }
+      }
+      for (int64_t k = 0; k < c->n_entries; ++k)
+        if ((er[k].x < 0 || er[k].y < 0) && e == hipSuccess) e = hipErrorInvalidValue;  // reported below
+      UP(m.ent_rec, er.data(), er.size());
     }
 #undef UP
     const size_t nc = (size_t)P.n_cells;
@@ -504,7 +544,7 @@ dolinc_status dolinc_precompute(dolinc_ctx c, const dolinc_params* p, dolinc_str
     al(&c->w.dc, ne * (size_t)dc_stride(p->scheme) * el);
     al(&c->w.rV, nc * el);
     if (ord >= 1 || bl) al(&c->w.G1, nc * nv * c->dim * el);
-    if (ord >= 2) al(&c->w.G2, nc * nv * (c->dim * (c->dim + 1) / 2) * el);
+    if (ord >= 2) al(&c->w.Hf, (size_t)c->n_ell * nv * el);
     al(&c->w.W1, nc * nv * el);
     al(&c->w.W2, nc * nv * el);
     if (bl) al((void**)&c->w.theta, nc * sizeof(float));

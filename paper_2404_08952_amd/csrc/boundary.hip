@@ -17,7 +17,11 @@
 // of a slip wall, a reflected vector field: R grad_C R and
 // sum_j R_ij R hess_C,j R); Dirichlet grad_O = -R grad_C, hess_O = -R hess_C R.
 // These kernels rewrite the auxiliary rows of U, G1, G2 and theta after each
-// of them has been produced for the interior cells.
+// of them has been produced for the interior cells.  The stage path keeps
+// second differentials only as d.H.d per face record; on the face of
+// an auxiliary cell d is normal to the face (R d = -d), so
+// d.(R H R).d = d.H.d: the auxiliary side takes the cell side's value, negated
+// for Dirichlet, and for the momentum of a slip wall sum_j R_ij h_j.
 #include "internal.hpp"
 
 namespace dolinc {
@@ -31,6 +35,8 @@ struct GhostArgs {
   int64_t ng, n_int;
   int dim, nv, euler;
   const int32_t* cell;
+  const int32_t* ent;  // [ng] entry of the boundary face (cell side 0)
+  const int2* ent_rec; // [entries] face records of the entry's two cells
   const int32_t* patch;
   const double* n;     // [ng][3]
   const double* dist;  // [ng] (x_f - x_C).n
@@ -144,6 +150,28 @@ __global__ void k_ghost_hess(GhostArgs a, T* __restrict__ H) {
   }
 }
 
+// Hf [records][nv]: the auxiliary cell's record of every boundary face
+template <class T>
+__global__ void k_ghost_hface(GhostArgs a, T* __restrict__ Hf) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= a.ng) return;
+  const int typ = a.bc_type[a.patch[k]];
+  const int2 rc = a.ent_rec[a.ent[k]];
+  const T* hc = Hf + (int64_t)rc.x * a.nv;
+  T* ho = Hf + (int64_t)rc.y * a.nv;
+  const T sgn = typ == BC_DIR ? T(-1) : T(1);
+  for (int v = 0; v < a.nv; ++v) ho[v] = sgn * hc[v];
+  if (a.euler && typ == BC_WALL) {
+    double R[3][3];
+    reflection(a, k, R);
+    for (int i = 0; i < a.dim; ++i) {
+      T m = T(0);
+      for (int j = 0; j < a.dim; ++j) m += (T)R[i][j] * hc[1 + j];
+      ho[1 + i] = m;
+    }
+  }
+}
+
 __global__ void k_ghost_theta(GhostArgs a, float* __restrict__ th) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= a.ng) return;
@@ -158,6 +186,8 @@ GhostArgs ghost_args(dolinc_ctx_s* c) {
   a.nv = c->w.nv;
   a.euler = c->params.pde == DOLINC_EULER;
   a.cell = c->m.gh_cell;
+  a.ent = c->m.gh_ent;
+  a.ent_rec = c->m.ent_rec;
   a.patch = c->m.gh_patch;
   a.n = c->m.gh_n;
   a.dist = c->m.gh_dist;
@@ -185,6 +215,10 @@ hipError_t launch_ghost(dolinc_ctx_s* c, int what, void* arr, hipStream_t s) {
     case GHOST_G2:
       if (f64) hipLaunchKernelGGL(k_ghost_hess<double>, grid, blk, 0, s, a, (double*)arr);
       else hipLaunchKernelGGL(k_ghost_hess<float>, grid, blk, 0, s, a, (float*)arr);
+      break;
+    case GHOST_HF:
+      if (f64) hipLaunchKernelGGL(k_ghost_hface<double>, grid, blk, 0, s, a, (double*)arr);
+      else hipLaunchKernelGGL(k_ghost_hface<float>, grid, blk, 0, s, a, (float*)arr);
       break;
     case GHOST_THETA:
       hipLaunchKernelGGL(k_ghost_theta, grid, blk, 0, s, a, (float*)arr);

@@ -27,7 +27,8 @@ KArgs<T> base_args(dolinc_ctx_s* c) {
   a.dc = (const T*)c->w.dc;
   a.rV = (const T*)c->w.rV;
   a.G1 = (const T*)c->w.G1;
-  a.G2 = (const T*)c->w.G2;
+  a.Hf = (const T*)c->w.Hf;
+  a.ent_rec = c->m.ent_rec;
   a.theta = c->w.theta;
   a.gamma = (T)c->params.gamma;
   for (int k = 0; k < 3; ++k) {
@@ -71,11 +72,11 @@ hipError_t go_flux(const KArgs<T>& a0, size_t lds, hipStream_t s, bool exporting
   KArgs<T> a = a0;
   const size_t limit = flux_lds_limit();
   // Rows are gathered straight from HBM/L2 by default: staging the
-  // partition's own rows in LDS (mask bits 1 G1, 2 G2, 4 U and theta) cost
-  // more in occupancy and the extra barrier than it saved on this workload.
+  // partition's own rows in LDS (mask bits 1 G1, 4 U and theta) cost more
+  // in occupancy and the extra barrier than it saved on this workload.
   int mask = 0;
   if (const char* env = std::getenv("DOLINC_STAGE_MASK")) {  // tuning override (still bounded by the limit)
-    mask = std::atoi(env) & 7;
+    mask = std::atoi(env) & 5;
   }
   if (lds + FS::bytes(a.B, mask) > limit) mask = 0;
   a.stage_mask = mask;
@@ -161,6 +162,28 @@ hipError_t run_grad2(dolinc_ctx_s* c, const void* G1, void* G2, hipStream_t s) {
     hipLaunchKernelGGL((k_grad<T, 3, 3, true>), grid, blk, 0, s, a, (const T*)G1, (T*)G2);
   else
     launch_grad2_euler<T>(grid, blk, s, a, (const T*)G1, (T*)G2);
+  return hipGetLastError();
+}
+
+// Second differentials contracted per face entry (stage path).  3-D Euler
+// in FP32 is built for 5 waves per SIMD like the row kernel.
+template <class T>
+hipError_t run_hface(dolinc_ctx_s* c, const void* G1, void* Hf, hipStream_t s) {
+  KArgs<T> a = base_args<T>(c);
+  const dim3 grid(8 * a.cell_per_xcd), blk(KTPB);
+  const int nv = c->w.nv;
+  const T* g1 = (const T*)G1;
+  T* hf = (T*)Hf;
+  if (c->dim == 2) {
+    if (nv != 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_hface<T, 2, 1>), grid, blk, 0, s, a, g1, hf);
+  } else if (nv == 1) {
+    hipLaunchKernelGGL((k_hface<T, 3, 1>), grid, blk, 0, s, a, g1, hf);
+  } else if constexpr (sizeof(T) == 4) {
+    hipLaunchKernelGGL((k_hface_w5<T, 3, 5>), grid, blk, 0, s, a, g1, hf);
+  } else {
+    hipLaunchKernelGGL((k_hface<T, 3, 5>), grid, blk, 0, s, a, g1, hf);
+  }
   return hipGetLastError();
 }
 

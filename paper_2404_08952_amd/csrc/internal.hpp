@@ -49,11 +49,13 @@ struct DevMesh {
   int2* ent_pn = nullptr;
   int32_t* slot_ptr = nullptr;
   uint16_t* slots = nullptr;
+  int2* ent_rec = nullptr;       // [entries] ELL record of the face in its owner / neighbour cell
   int32_t* ell_ptr = nullptr;    // [n_cells / ELL_BLOCK + 1] record offsets
   // auxiliary cells of non-coupled boundary faces (row n_interior + k)
   int32_t* gh_cell = nullptr;    // [n_ghost] internal boundary cell
   int32_t* gh_face = nullptr;    // [n_ghost] caller face
   int32_t* gh_patch = nullptr;   // [n_ghost]
+  int32_t* gh_ent = nullptr;     // [n_ghost] entry of the boundary face (cell side 0, auxiliary side 1)
   double* gh_n = nullptr;        // [n_ghost][3] outward unit normal
   double* gh_dist = nullptr;     // [n_ghost] (x_f - x_C).n
   int32_t* bc_type = nullptr;    // [n_patches]
@@ -96,7 +98,9 @@ struct Work {
   void* dc = nullptr;
   void* rV = nullptr;
   void* G1 = nullptr;
-  void* G2 = nullptr;
+  // second differentials contracted with each face's d, per face record:
+  // Hf[r][nv] = d.H.d of record r's cell (ELL order)
+  void* Hf = nullptr;
   void* W1 = nullptr;
   void* W2 = nullptr;
   float* theta = nullptr;
@@ -132,7 +136,7 @@ struct dolinc_ctx_s {
 namespace dolinc {
 
 // Auxiliary-cell rows rewritten from the boundary conditions (boundary.hip)
-enum { GHOST_U = 0, GHOST_G1 = 1, GHOST_G2 = 2, GHOST_THETA = 3 };
+enum { GHOST_U = 0, GHOST_G1 = 1, GHOST_G2 = 2, GHOST_THETA = 3, GHOST_HF = 4 };
 hipError_t launch_ghost(dolinc_ctx_s* c, int what, void* arr, hipStream_t s);
 
 // Launchers (kernels.hip / precompute.hip).  Return hipSuccess or an error.

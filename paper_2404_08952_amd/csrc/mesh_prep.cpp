@@ -389,7 +389,7 @@ dolinc_status prepare_mesh(const dolinc_mesh_desc& d, Prepared& P, std::string& 
     P.part_ent_ptr[p + 1] = P.part_ent_ptr[p] + (int32_t)pfaces[p].size();
     P.max_entries = std::max(P.max_entries, maxloc[p]);
   }
-  if ((int64_t)P.part_ent_ptr[P.n_parts] >= (int64_t)INT32_MAX) { msg = "too many face entries"; return DOLINC_EMESH; }
+  if ((int64_t)P.part_ent_ptr[P.n_parts] >= (int64_t)INT32_MAX / 2) { msg = "too many face entries"; return DOLINC_EMESH; }
   const int64_t ne = P.part_ent_ptr[P.n_parts];
   P.ent_face.resize(ne);
   P.ent_p.resize(ne);
@@ -422,6 +422,25 @@ dolinc_status prepare_mesh(const dolinc_mesh_desc& d, Prepared& P, std::string& 
   });
   // first entry of every face (lowest partition wins)
   for (int64_t e = ne - 1; e >= 0; --e) P.face_first_ent[P.ent_face[e]] = (int32_t)e;
+  // a seam face has a second entry; every slot names the other one
+  {
+    std::vector<int32_t> second(nf, -1);
+    for (int64_t e = 0; e < ne; ++e)
+      if (P.face_first_ent[P.ent_face[e]] != (int32_t)e) second[P.ent_face[e]] = (int32_t)e;
+    P.slot_twin.assign(P.slots.size(), -1);
+    parallel_for(P.n_parts, [&](int64_t p0, int64_t p1) {
+      for (int64_t p = p0; p < p1; ++p) {
+        const int64_t e0 = P.part_ent_ptr[p];
+        const int64_t c0 = p * B, c1 = std::min<int64_t>(c0 + B, nc);
+        for (int64_t s = P.slot_ptr[c0]; s < P.slot_ptr[c1]; ++s) {
+          const int64_t e = e0 + (P.slots[s] & 0x7fff);
+          const int32_t f = P.ent_face[e];
+          const int32_t o = P.face_first_ent[f] == (int32_t)e ? second[f] : P.face_first_ent[f];
+          P.slot_twin[s] = o < 0 ? -1 : 2 * o + (P.slots[s] >> 15);
+        }
+      }
+    });
+  }
   clk.lap("partitions");
   if ((int64_t)P.ent_face.size() >= (int64_t)INT32_MAX) { msg = "too many face entries"; return DOLINC_EMESH; }
   return DOLINC_OK;

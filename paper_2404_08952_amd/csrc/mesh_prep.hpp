@@ -30,6 +30,9 @@ struct Prepared {
   std::vector<int32_t> face_first_ent; // [n_faces] one entry of every face
   std::vector<int32_t> slot_ptr;       // [n_cells + 1] (internal order)
   std::vector<uint16_t> slots;         // local entry | side << 15
+  // per slot: 2 * e + side for the face's entry e in the partition across a
+  // seam (the same face seen from the other cell's partition), else -1
+  std::vector<int32_t> slot_twin;
   int64_t max_entries = 0, max_cell_faces = 0;
 };
 

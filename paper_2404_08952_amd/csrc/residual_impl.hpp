@@ -43,7 +43,8 @@ struct KArgs {
   const T* rV;
   const T* U;
   const T* G1;
-  const T* G2;
+  const T* Hf;          // [records][NV] second differentials contracted with the record's d
+  const int2* ent_rec;  // [entries] record of the face in its owner / neighbour
   const float* theta;
   const T* Un;
   T* out;
@@ -54,7 +55,7 @@ struct KArgs {
   T bdir[3];
   int use_ref;
   T uref[5];
-  int stage_mask;  // k_flux rows staged in LDS: 1 G1, 2 G2, 4 U and theta
+  int stage_mask;  // k_flux rows staged in LDS: 1 G1, 4 U and theta
   const int32_t* face_ent;
   int64_t nf;
   T* eUL;
@@ -526,10 +527,9 @@ struct Stage {
   // them stay LDS loads.
   const T* U = nullptr;
   const T* G1 = nullptr;
-  const T* G2 = nullptr;
   const float* th = nullptr;
   int64_t c0 = 0;
-  int nU = 0, nG1 = 0, nG2 = 0, nth = 0;
+  int nU = 0, nG1 = 0, nth = 0;
 };
 
 template <class T, int D, int PK, int SCH, bool BLEND>
@@ -538,7 +538,6 @@ __device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T
   constexpr int NV = NVars<PK, D>::value;
   constexpr int ORD = SchemeInfo<SCH>::ORD;
   constexpr int DCS = SchemeInfo<SCH>::DCS;
-  constexpr int NS2 = D * (D + 1) / 2;
   const int2 pn = a.ent_pn[e];
   const int64_t P = pn.x, N = pn.y;
   const T* swp = a.sw + 4 * e;
@@ -567,9 +566,15 @@ __device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T
     contract_cell<T, NV, D, 1>(st.G1, a.G1, st.c0, st.nG1, P, dc, gP);
     contract_cell<T, NV, D, 1>(st.G1, a.G1, st.c0, st.nG1, N, dc, gN);
   }
-  if constexpr (ORD >= 2) {
-    contract_cell<T, NV, D, 2>(st.G2, a.G2, st.c0, st.nG2, P, dc, hP);
-    contract_cell<T, NV, D, 2>(st.G2, a.G2, st.c0, st.nG2, N, dc, hN);
+  if constexpr (ORD >= 2) {  // d.H.d of both cells, written per face record by the second-derivative kernel
+    const int2 rc = a.ent_rec[e];
+    GlbPtr<T> hp = as_glb(a.Hf + (int64_t)rc.x * NV);
+    GlbPtr<T> hn = as_glb(a.Hf + (int64_t)rc.y * NV);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      hP[v] = hp[v];
+      hN[v] = hn[v];
+    }
   }
   // reconstruction in the DOLINC representation (coefficients from precompute)
   if constexpr (SchemeInfo<SCH>::NONLIN) {
@@ -679,18 +684,14 @@ __device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T
 }
 
 // ---------------------------------------------------------------- kernels
-// Rows of one cell staged by k_flux: U, G1 (if used), G2 (FP32 only), theta.
+// Rows of one cell staged by k_flux: U, G1 (if used), theta.
 template <class T, int D, int PK, int SCH, bool BLEND>
 struct FluxStage {
   static constexpr int NV = NVars<PK, D>::value;
   static constexpr bool G1 = SchemeInfo<SCH>::ORD >= 1 || BLEND;
-  static constexpr bool G2 = SchemeInfo<SCH>::ORD >= 2;
   // bytes of LDS for the staged rows of B cells (theta as T-sized slots)
   static constexpr size_t bytes(int B, int mask) {
-    return (size_t)B *
-           ((mask & 4 ? NV + (BLEND ? 1 : 0) : 0) + ((mask & 1) && G1 ? NV * D : 0) +
-            ((mask & 2) && G2 ? NV * D * (D + 1) / 2 : 0)) *
-           sizeof(T);
+    return (size_t)B * ((mask & 4 ? NV + (BLEND ? 1 : 0) : 0) + ((mask & 1) && G1 ? NV * D : 0)) * sizeof(T);
   }
 };
 
@@ -707,7 +708,7 @@ __global__ __launch_bounds__(KTPB) void k_flux(KArgs<T> a) {
   T* lds = reinterpret_cast<T*>(smem_raw);
   Stage<T> st;
   st.c0 = c0;
-  st.U = st.G1 = st.G2 = lds;
+  st.U = st.G1 = lds;
   st.th = reinterpret_cast<const float*>(lds);
   size_t off = 0;
   if (a.stage_mask & 4) {
@@ -721,15 +722,6 @@ __global__ __launch_bounds__(KTPB) void k_flux(KArgs<T> a) {
       st.G1 = lds + off;
       st.nG1 = ncl;
       off += (size_t)a.B * NV * D;
-    }
-  }
-  if constexpr (FS::G2) {
-    if (a.stage_mask & 2) {
-      constexpr int NS2 = D * (D + 1) / 2;
-      stage_rows(lds + off, a.G2, c0, ncl, NV * NS2);
-      st.G2 = lds + off;
-      st.nG2 = ncl;
-      off += (size_t)a.B * NV * NS2;
     }
   }
   if constexpr (BLEND) {
@@ -994,6 +986,67 @@ __global__ __launch_bounds__(KTPB) __attribute__((amdgpu_waves_per_eu(5))) void 
                                                                                      const T* __restrict__ phi,
                                                                                      T* __restrict__ out) {
   grad_block<T, D, NQ, SYM>(a, phi, out);
+}
+
+// Second differentials of a stage in the form the faces use them: for every
+// face record of cell c, h_v = d . H_v . d (H_v the symmetrised Gauss-linear
+// derivative of the gradient rows phi = G1, d the face's centre-to-centre
+// vector; the quadratic form does not see the record's sign), written to
+// Hf[r] of the face record r (ELL order: consecutive lanes, consecutive
+// records), so that the flux kernel reads 5 values per side instead of
+// gathering both cells' second-derivative rows.  The arithmetic (sums,
+// symmetrised values rounded to T, contraction) is that of the row kernel
+// followed by the contraction the flux kernel did before.
+template <class T, int D, int NV>
+__device__ __forceinline__ void hface_block(const KArgs<T>& a, const T* __restrict__ phi, T* __restrict__ out) {
+  constexpr int NQ = NV * D;
+  constexpr int NS2 = D * (D + 1) / 2;
+  __shared__ T lds[KTPB * NQ];
+  const int b = xcd_remap(blockIdx.x, a.cell_per_xcd, a.n_cell_blocks);
+  if (b < 0) return;
+  const int64_t c0 = (int64_t)b * KTPB;
+  const int n = (int)(a.nc - c0 < KTPB ? a.nc - c0 : KTPB);
+  stage_rows(lds, phi, c0, n, NQ);
+  __syncthreads();
+  const int64_t c = c0 + threadIdx.x;
+  if (c >= a.nc) return;
+  T acc2[NV][NS2];
+  grad2_sums<T, D, NV>(a, phi, c, acc2, lds, c0, n);
+  const T rv = a.rV[c];
+  T H[NV * NS2];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+#pragma unroll
+    for (int i = 0; i < D; ++i) H[v * NS2 + i] = acc2[v][i] * rv;
+#pragma unroll
+    for (int k = D; k < NS2; ++k) H[v * NS2 + k] = T(0.5) * acc2[v][k] * rv;
+  }
+  const int r0 = a.ell_ptr[b];
+  const int nfc = a.slot_ptr[c + 1] - a.slot_ptr[c];
+  for (int j = 0; j < nfc; ++j) {
+    const int64_t r = (int64_t)r0 + (int64_t)j * KTPB + threadIdx.x;
+    GlbPtr<T> rd = as_glb(a.ell_d + 4 * r);
+    T d[3];
+#pragma unroll
+    for (int x = 0; x < D; ++x) d[x] = rd[x];
+    T h[NV];
+    contract2<T, NV, D>(static_cast<const T*>(H), d, h);
+    T* o = out + r * NV;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) o[v] = h[v];
+  }
+}
+
+template <class T, int D, int NV>
+__global__ __launch_bounds__(KTPB) void k_hface(KArgs<T> a, const T* __restrict__ phi, T* __restrict__ out) {
+  hface_block<T, D, NV>(a, phi, out);
+}
+
+template <class T, int D, int NV>
+__global__ __launch_bounds__(KTPB) __attribute__((amdgpu_waves_per_eu(5))) void k_hface_w5(KArgs<T> a,
+                                                                                     const T* __restrict__ phi,
+                                                                                     T* __restrict__ out) {
+  hface_block<T, D, NV>(a, phi, out);
 }
 
 // Classical sensor: beta = |s - Delta| / (|s| + |Delta| + eps) on every face
