@@ -26,12 +26,12 @@ def _interior_points(mesh):
         fc[:, a] = np.bincount(idx, weights=mesh.nodes[mesh.face_nodes, a],
                                minlength=mesh.n_faces) / cnt
     acc = np.zeros((mesh.n_cells, d))
-    num = np.bincount(mesh.owner, minlength=mesh.n_cells) + \
-        np.bincount(mesh.neighbour, minlength=mesh.n_cells)
+    two = mesh.neighbour >= 0  # boundary faces have one cell
+    nei = mesh.neighbour[two]
+    num = np.bincount(mesh.owner, minlength=mesh.n_cells) + np.bincount(nei, minlength=mesh.n_cells)
     for a in range(d):
         acc[:, a] = (np.bincount(mesh.owner, weights=fc[:, a], minlength=mesh.n_cells) +
-                     np.bincount(mesh.neighbour, weights=fc[:, a] - mesh.shift[:, a],
-                                 minlength=mesh.n_cells))
+                     np.bincount(nei, weights=fc[two, a] - mesh.shift[two, a], minlength=mesh.n_cells))
     return acc / num[:, None], fc
 
 
@@ -47,7 +47,7 @@ def cell_simplices(mesh):
     cnt = np.diff(mesh.face_ptr)
     out_v, out_c = [], []
     for m in np.unique(cnt):
-        fs = np.nonzero(cnt == m)[0]
+        fs = fs0 = np.nonzero(cnt == m)[0]
         base = mesh.face_ptr[fs]
         P = np.stack([mesh.nodes[mesh.face_nodes[base + k]] for k in range(m)], 1)  # [nf,m,d]
         for side in (0, 1):
@@ -56,6 +56,8 @@ def cell_simplices(mesh):
                 Q = P
                 fcs = fcen[fs]
             else:
+                fs = fs[mesh.neighbour[fs] >= 0]
+                P = P[mesh.neighbour[fs0] >= 0]
                 cells = mesh.neighbour[fs]
                 Q = P[:, ::-1, :] - mesh.shift[fs][:, None, :]
                 fcs = fcen[fs] - mesh.shift[fs]
@@ -176,6 +178,53 @@ def burgers_diag(t=0.0, mean=0.5, amp=0.25):
                 break
         return u[:, None]
     return f
+
+
+class Blasius:
+    """The laminar flat-plate boundary layer (Blasius): f''' + f f'' / 2 = 0,
+    f(0) = f'(0) = 0, f'(inf) = 1, solved by shooting on f''(0) with an
+    adaptive Runge-Kutta integrator (rtol 1e-12).  With eta = y / sqrt(nu x / U)
+    the velocity is u = U f'(eta), v = sqrt(nu U / x) (eta f' - f) / 2.
+    (Input data only: the plate flow is the workload of the single-step
+    reconstruction study, not part of the finite-volume method.)"""
+
+    def __init__(self, eta_max=15.0):
+        from scipy.integrate import solve_ivp
+        from scipy.optimize import brentq
+
+        def rhs(_eta, y):
+            return [y[1], y[2], -0.5 * y[0] * y[2]]
+
+        def shoot(s, dense=False):
+            return solve_ivp(rhs, (0.0, eta_max), [0.0, 0.0, s], method="DOP853", rtol=1e-12, atol=1e-14,
+                             dense_output=dense)
+
+        self.fpp0 = brentq(lambda s: shoot(s).y[1, -1] - 1.0, 0.2, 0.5, xtol=1e-15)
+        self._sol = shoot(self.fpp0, dense=True).sol
+        self.eta_max = eta_max
+
+    def f_and_fp(self, eta):
+        eta = np.asarray(eta, dtype=np.float64)
+        e = np.clip(eta, 0.0, self.eta_max)
+        y = self._sol(e.ravel())
+        f, fp = y[0].reshape(e.shape), y[1].reshape(e.shape)
+        # beyond eta_max: f' = 1, f grows linearly
+        f = np.where(eta > self.eta_max, f + (eta - self.eta_max), f)
+        return f, fp
+
+    def velocity(self, x, y, nu=1.0, U=1.0):
+        """(u, v) at plate distance x > 0 and wall distance y >= 0."""
+        d = np.sqrt(nu * x / U)
+        eta = y / d
+        f, fp = self.f_and_fp(eta)
+        return U * fp, 0.5 * np.sqrt(nu * U / x) * (eta * fp - f)
+
+    def field(self, x0=1.0):
+        """fn(points) -> [n, 2] (u, v), the lattice's x measured from x0."""
+        def fn(pts):
+            u, v = self.velocity(x0 + pts[:, 0], pts[:, 1])
+            return np.stack([u, v], axis=1)
+        return fn
 
 
 def prim_to_cons(rho, vel, p, gamma=GAMMA):

@@ -108,6 +108,32 @@ def bounded(mesh: Mesh, axis: int = 0) -> Mesh:
     return Mesh(mesh.dim, mesh.nodes, ptr, fn, owner, neigh, shift, mesh.n_cells, mesh.lengths, info, patch)
 
 
+def graded_spacing(h1, growth, height):
+    """Node coordinates 0 .. height whose spacings grow geometrically from
+    h1 by the factor growth (the last cell absorbs the remainder, merged into
+    its neighbour when it would be thinner than half of it)."""
+    ys = [0.0]
+    h = h1
+    while ys[-1] + h < height:
+        ys.append(ys[-1] + h)
+        h *= growth
+    if len(ys) > 2 and height - ys[-1] < 0.5 * (ys[-1] - ys[-2]):
+        ys[-1] = height
+    else:
+        ys.append(height)
+    return np.asarray(ys)
+
+
+def boundary_layer_2d(nx, length, h1, growth, height):
+    """Quadrilateral boundary-layer mesh: nx uniform columns over [0, length]
+    (periodic in x) and rows growing away from the wall y = 0 by the factor
+    growth from the first height h1 up to height; y is open (patch 2: the
+    wall, patch 3: the top)."""
+    ys = graded_spacing(h1, growth, height)
+    m = periodic_2d(nx, ys.size - 1, lengths=(length, height), ycoords=ys)
+    return bounded(m, 1)
+
+
 def _lattice_coords(n, L, coords):
     if coords is None:
         return np.linspace(0.0, L, n + 1)
