@@ -1,0 +1,59 @@
+"""Graded boundary-layer mesh (growth rates 1.1 - 1.5 away from a wall,
+Sec. 3.1) through the C ABI: the GPU face states of one reconstruction of the
+Blasius velocity equal the FP64 oracle's element by element for every DOLINC
+scheme, and the GPU path shows the paper's error trends (error grows with
+the growth rate; CSR4 well below USR3)."""
+import numpy as np
+import pytest
+
+from . import graded_study as GS
+from .test_gpu_parity import _close
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cases():
+    return {r: GS.case(r) for r in GS.GROWTHS}
+
+
+def _gpu_faces(m, U1, scheme, precision="fp64"):
+    from paper_2404_08952_amd import Solver
+    s = Solver(m, pde="advection", scheme=scheme, precision=precision, adv_vel=(1.0, 0.0, 0.0))
+    s.set_boundary(2, "dirichlet", [0.0])
+    UL, UR, _F = s.face_states(s.to_internal(U1[:, None]))
+    out = UL.cpu().numpy()[:, 0].astype(np.float64), UR.cpu().numpy()[:, 0].astype(np.float64)
+    s.close()
+    return out
+
+
+@pytest.mark.parametrize("scheme", ["CD2", "USR3", "CSR4", "USR5", "CSR6", "ENO3", "WENO5"])
+@pytest.mark.parametrize("growth", [1.2, 1.5])
+def test_face_states_equal_oracle(cases, growth, scheme):
+    m, X, U, _ex = cases[growth]
+    rtol = 1e-9 if scheme == "CSR6" else 1e-10
+    for comp in (0, 1):
+        gL, gR = _gpu_faces(m, U[:, comp], scheme)
+        oL, oR = GS.oracle_face_states(X, U[:, comp], scheme)
+        _close(gL, oL, rtol=rtol, afloor=1e-13)
+        _close(gR, oR, rtol=rtol, afloor=1e-13)
+
+
+def test_gpu_error_trends_and_fp32(cases):
+    for comp in (0, 1):
+        err = {}
+        for r in GS.GROWTHS:
+            m, X, U, ex = cases[r]
+            sel = GS.measured_faces(X)
+            for sch in ("USR3", "CSR4", "USR5"):
+                gL, gR = _gpu_faces(m, U[:, comp], sch)
+                err[(r, sch)] = GS.rel_error(gL, gR, ex[:, comp], sel)
+                if r == 1.5:
+                    fL, fR = _gpu_faces(m, U[:, comp], sch, "fp32")
+                    e32 = GS.rel_error(fL, fR, ex[:, comp], sel)
+                    assert abs(e32 - err[(r, sch)]) < 1e-3 * err[(r, sch)], (sch, e32, err[(r, sch)])
+        for sch in ("USR3", "CSR4", "USR5"):
+            e = [err[(r, sch)] for r in GS.GROWTHS]
+            assert e[-1] > 10 * e[0], (comp, sch, e)
+        for r in GS.GROWTHS:
+            assert err[(r, "CSR4")] < 0.7 * err[(r, "USR3")] and err[(r, "USR5")] < err[(r, "CSR4")], (comp, r)
