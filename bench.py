@@ -160,6 +160,51 @@ def shock_tube_line(args):
     return out
 
 
+MLP_FWD_FLOP = 2 * (24 * 64 + 64 * 64 + 64 * 1)   # multiply-adds of 24 -> 64 -> 64 -> 1, per cell
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def indicator_line(args):
+    """The indicator network alone: inference (forward) and training (forward,
+    backward, Adam) throughput on 5M synthetic bf16 feature rows, the size of
+    the shock workload's training set; achieved FLOP/s against the dense BF16
+    matrix-core peak (the in-stage fused kernel is k_grad_indicator)."""
+    import torch
+    from paper_2404_08952_amd import Solver
+    from paper_2404_08952_amd import binding as B
+    from synth import mesh as M
+    n = 5_000_000
+    s = Solver(M.periodic_3d(8, 8, 8), pde="euler", scheme="USR3", flux="rusanov", blend="learned")
+    s.mlp_set(indicator_weights())
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(51)
+    X = torch.zeros(n, B.FEATURE_STRIDE, dtype=torch.float32, device="cuda")
+    X[:, :B.N_FEATURES] = torch.randn(n, B.N_FEATURES, generator=gen, device="cuda")
+    Xb = X.to(torch.bfloat16).view(torch.int16)
+    del X
+    y = torch.rand(n, generator=gen, device="cuda")
+    out = {}
+    for kind, call, reps, flop in (("inference", lambda: s.mlp_forward(Xb), 20, MLP_FWD_FLOP),
+                                   ("training", lambda: s.mlp_train_step(Xb, y, 1e-4), 10, 3 * MLP_FWD_FLOP)):
+        call()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            call()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        tf = flop * n / (ms * 1e-3) / 1e12
+        out[kind] = dict(rows=n, ms=ms, rows_per_s=n / (ms * 1e-3), tflops=tf, mfma_frac=tf / BF16_PEAK_TFLOPS)
+        log(f"[bench] indicator {kind}: {ms:.3f} ms for {n:,} rows, {tf:.1f} TFLOP/s")
+    s.close()
+    del Xb, y
+    torch.cuda.empty_cache()
+    return out
+
+
 def copy_bandwidth():
     import torch
     n = 1 << 29  # 2 GiB of float32 per buffer
@@ -259,6 +304,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--cpu-baseline-only", action="store_true")
+    ap.add_argument("--indicator-only", action="store_true",
+                    help="only the indicator network's inference / training throughput (for counter runs)")
     args = ap.parse_args()
 
     if args.cpu_baseline_only:
@@ -272,6 +319,9 @@ def main():
     from paper_2404_08952_amd import Solver
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
+    if args.indicator_only:
+        print(json.dumps(indicator_line(args)))
+        return
     dev = torch.cuda.get_device_name(0)
     t0 = time.time()
     case, desc, extra, fp32_extra = make_case(args.workload)
@@ -304,6 +354,7 @@ def main():
     solver.close()
     del solver
     tube = shock_tube_line(args) if args.workload == "tgv3d" else None
+    mlp = indicator_line(args) if args.workload == "tgv3d" else None
     gbps_copy = copy_bandwidth()
     log(f"[bench] streaming y = -x: {gbps_copy:.0f} GB/s")
 
@@ -362,6 +413,7 @@ def main():
         "other_schemes_fp32": {k: dict(v, unit="cell-updates/s", scheme=k, flux="hllc", blend="none")
                                for k, v in nonlin.items()},
         "bounded_fp32": tube,
+        "indicator_network": mlp,
         "device": dev,
         "copy_gbps": gbps_copy,
     }

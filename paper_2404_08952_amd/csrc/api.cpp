@@ -263,14 +263,25 @@ void free_mlp(dolinc_ctx c) {
 }
 
 constexpr int MLP_N = DOLINC_MLP_PARAMS;
-constexpr int MLP_ROWS_PER_BLOCK = 256;
+// Training batches: blocks of at least 256 rows, at most 2048 blocks (each
+// block writes one partial gradient, so the reduction reads at most 2048).
+constexpr int64_t MLP_MIN_ROWS = 256, MLP_MAX_BLOCKS = 2048;
+void mlp_grid(int64_t n, int* nblocks, int* rows_per_block) {
+  int64_t nb = (n + MLP_MIN_ROWS - 1) / MLP_MIN_ROWS;
+  if (nb > MLP_MAX_BLOCKS) nb = MLP_MAX_BLOCKS;
+  int64_t rows = (n + nb - 1) / nb;
+  rows = (rows + 63) / 64 * 64;
+  *rows_per_block = (int)rows;
+  *nblocks = (int)((n + rows - 1) / rows);
+}
 
 dolinc_status mlp_batch_check(dolinc_ctx c, const uint16_t* X, const float* y, int64_t n) {
   if (!valid_ctx(c)) return fail(DOLINC_ESTATE, "invalid or destroyed context");
   if (!c->mlp.p) return fail(DOLINC_ESTATE, "dolinc_mlp_set has not been called");
   if (!X || !y) return fail(DOLINC_EINVAL, "NULL batch");
   if (n <= 0 || n > (int64_t)1 << 30) return fail(DOLINC_EINVAL, "batch size must be in [1, 2^30]");
-  const int64_t nb = (n + MLP_ROWS_PER_BLOCK - 1) / MLP_ROWS_PER_BLOCK;
+  int nb = 0, rows = 0;
+  mlp_grid(n, &nb, &rows);
   if (nb > c->mlp.part_blocks) {
     dfree_t(c->mlp.part);
     dfree_t(c->mlp.loss_part);
@@ -278,7 +289,7 @@ dolinc_status mlp_batch_check(dolinc_ctx c, const uint16_t* X, const float* y, i
     if (hipMalloc((void**)&c->mlp.part, (size_t)nb * MLP_N * sizeof(float)) != hipSuccess ||
         hipMalloc((void**)&c->mlp.loss_part, (size_t)nb * sizeof(float)) != hipSuccess)
       return fail(DOLINC_ENOMEM, "gradient workspace allocation failed");
-    c->mlp.part_blocks = (int)nb;
+    c->mlp.part_blocks = nb;
   }
   return DOLINC_OK;
 }
@@ -765,11 +776,12 @@ dolinc_status dolinc_mlp_train_step(dolinc_ctx c, const uint16_t* X, const float
   dolinc_status st = mlp_batch_check(c, X, y, n);
   if (st != DOLINC_OK) return st;
   if (!(std::isfinite(lr) && lr > 0.f)) return fail(DOLINC_EINVAL, "lr must be finite and > 0");
-  const int nb = (int)((n + MLP_ROWS_PER_BLOCK - 1) / MLP_ROWS_PER_BLOCK);
+  int nb = 0, rows = 0;
+  mlp_grid(n, &nb, &rows);
   const int64_t t = c->mlp.step + 1;
   const float c1 = (float)(1.0 - std::pow(0.9, (double)t));
   const float c2 = (float)(1.0 - std::pow(0.999, (double)t));
-  HIPCHK(mlp_grad_launch(c, (const unsigned short*)X, y, n, nb, MLP_ROWS_PER_BLOCK, nullptr, loss, 1, lr, c1, c2,
+  HIPCHK(mlp_grad_launch(c, (const unsigned short*)X, y, n, nb, rows, nullptr, loss, 1, lr, c1, c2,
                          (hipStream_t)stream));
   c->mlp.step = t;
   return DOLINC_OK;
@@ -780,8 +792,9 @@ dolinc_status dolinc_mlp_gradient(dolinc_ctx c, const uint16_t* X, const float* 
   dolinc_status st = mlp_batch_check(c, X, y, n);
   if (st != DOLINC_OK) return st;
   if (!grad) return fail(DOLINC_EINVAL, "NULL gradient output");
-  const int nb = (int)((n + MLP_ROWS_PER_BLOCK - 1) / MLP_ROWS_PER_BLOCK);
-  HIPCHK(mlp_grad_launch(c, (const unsigned short*)X, y, n, nb, MLP_ROWS_PER_BLOCK, grad, loss, 0, 0.f, 1.f, 1.f,
+  int nb = 0, rows = 0;
+  mlp_grid(n, &nb, &rows);
+  HIPCHK(mlp_grad_launch(c, (const unsigned short*)X, y, n, nb, rows, grad, loss, 0, 0.f, 1.f, 1.f,
                          (hipStream_t)stream));
   return DOLINC_OK;
 }

@@ -81,7 +81,7 @@ hipError_t mlp_grad_launch(dolinc_ctx_s* c, const unsigned short* X, const float
                      c->mlp.loss_part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_mlp_adam, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, s, nblocks, c->mlp.part,
+  hipLaunchKernelGGL(k_mlp_adam, dim3((MLP_NPARAM + 1 + ADAM_K - 1) / ADAM_K), dim3(256), 0, s, nblocks, c->mlp.part,
                      c->mlp.loss_part, c->mlp.p, c->mlp.m, c->mlp.v, c->mlp.w1b, c->mlp.w2b, grad_out, loss_out,
                      do_step, lr, 0.9f, 0.999f, c1, c2, 1e-8f);
   return hipGetLastError();

@@ -479,8 +479,12 @@ __global__ __launch_bounds__(256) void k_mlp_grad(MlpDev m, const unsigned short
   if (threadIdx.x == 0) loss_part[blockIdx.x] = red[MLP_NPARAM];
 }
 
-// Sum partial gradients in block order; optional Adam step on the fp32
-// master parameters with bf16 refresh of W1, W2.
+// Sum the per-block partial gradients (and, as index MLP_NPARAM, the
+// partial losses): a block takes 32 parameters, its 8 slices of 32 threads
+// sum every 8th partial (consecutive threads, consecutive parameters), then
+// the slices are added in order, so the result is independent of timing.
+// Optional Adam step on the fp32 master parameters with bf16 refresh of W1, W2.
+constexpr int ADAM_K = 32, ADAM_SLICES = 8;
 __global__ __launch_bounds__(256) void k_mlp_adam(int nparts, const float* __restrict__ part,
                                                   const float* __restrict__ loss_part, float* __restrict__ p,
                                                   float* __restrict__ mom, float* __restrict__ vel,
@@ -488,15 +492,24 @@ __global__ __launch_bounds__(256) void k_mlp_adam(int nparts, const float* __res
                                                   float* __restrict__ grad_out, float* __restrict__ loss_out,
                                                   int do_step, float lr, float b1, float b2, float c1, float c2,
                                                   float eps) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k == 0 && loss_out) {
-    float s = 0.f;
-    for (int b = 0; b < nparts; ++b) s += loss_part[b];
-    *loss_out = s;
+  __shared__ float sl_sum[ADAM_SLICES][ADAM_K];
+  const int kk = threadIdx.x % ADAM_K, sl = threadIdx.x / ADAM_K;
+  const int k = blockIdx.x * ADAM_K + kk;
+  float acc = 0.f;
+  if (k < MLP_NPARAM) {
+    for (int b = sl; b < nparts; b += ADAM_SLICES) acc += part[(int64_t)b * MLP_NPARAM + k];
+  } else if (k == MLP_NPARAM) {
+    for (int b = sl; b < nparts; b += ADAM_SLICES) acc += loss_part[b];
   }
-  if (k >= MLP_NPARAM) return;
+  sl_sum[sl][kk] = acc;
+  __syncthreads();
+  if (sl != 0 || k > MLP_NPARAM) return;
   float gsum = 0.f;
-  for (int b = 0; b < nparts; ++b) gsum += part[(int64_t)b * MLP_NPARAM + k];
+  for (int j = 0; j < ADAM_SLICES; ++j) gsum += sl_sum[j][kk];
+  if (k == MLP_NPARAM) {
+    if (loss_out) *loss_out = gsum;
+    return;
+  }
   if (grad_out) grad_out[k] = gsum;
   if (!do_step) return;
   const float mk = b1 * mom[k] + (1.f - b1) * gsum;

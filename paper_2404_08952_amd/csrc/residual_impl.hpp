@@ -858,7 +858,7 @@ __device__ __forceinline__ void grad2_sums(const KArgs<T>& a, const T* __restric
                                            T (*acc2)[D * (D + 1) / 2], const T* lds, int64_t c0, int n) {
   constexpr int NQ = NV * D;
   constexpr int NS2 = D * (D + 1) / 2;
-  constexpr int GB = 2;
+  constexpr int GB = 1;  // one record, then its row: measured fastest (2 and 3 are slower)
   const int64_t b = c / KTPB;
   const int lane = (int)(c - b * KTPB);
   const int r0 = a.ell_ptr[b], m = (a.ell_ptr[b + 1] - r0) / KTPB;

@@ -1,6 +1,8 @@
 """Summaries of rocprofv3 output for the stage kernels.
 
 ``python -m paper_2404_08952_amd.profiling <stats_dir> <fetch_dir> <write_dir> <out.md> [--launch-bytes B]``
+(``... --mfma <stats_dir> <pmc_dir> <rows>`` instead summarises the indicator
+network kernels' matrix-core use from an ``SQ_INSTS_VALU_MFMA_MOPS_BF16`` run)
 reads the CSV files that ``rocprofv3 --kernel-trace --stats`` and two
 ``rocprofv3 --pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE`` runs of ``bench.py``
 wrote, and prints (or writes) a short text summary:
@@ -97,7 +99,40 @@ def read_summary(path):
     return float(vals["traffic_bytes_per_launch"]), vals["kernel_source_sha256"]
 
 
+MFMA_KERNELS = (("k_mlp_fwd", 2 * (24 * 64 + 64 * 64 + 64)), ("k_mlp_grad", 3 * 2 * (24 * 64 + 64 * 64 + 64)))
+BF16_PEAK_FLOPS = 2.5e15  # dense matrix-core BF16 peak of the MI355X
+
+
+def mfma_summary(stats_dir, pmc_dir, rows):
+    """Matrix-core use of the indicator network kernels: executed BF16 FLOP
+    per launch from SQ_INSTS_VALU_MFMA_MOPS_BF16 (x 512), the rocprofv3
+    average duration, and the fraction of the dense BF16 peak; beside it the
+    algorithmic FLOP (forward 24 -> 64 -> 64 -> 1 per row, training 3x)."""
+    avg = {}
+    for name, calls, us, _pct in kernel_stats(stats_dir):
+        m = re.search(r"(k_mlp_\w+)", name)
+        if m:
+            avg[m.group(1)] = (us, calls)
+    lines = [f"{'kernel':12s} {'calls':>6s} {'avg_us':>9s} {'MFMA FLOP':>11s} {'TFLOP/s':>8s} {'of peak':>8s}"
+             f" {'alg FLOP':>11s}"]
+    for k, per_row in MFMA_KERNELS:
+        mops = counter_values(pmc_dir, "SQ_INSTS_VALU_MFMA_MOPS_BF16", k)
+        flop = statistics.median(mops) * 512.0
+        us, calls = avg[k]
+        tf = flop / (us * 1e-6) / 1e12
+        lines.append(f"{k:12s} {calls:6d} {us:9.1f} {flop:11.4e} {tf:8.1f} {tf * 1e12 / BF16_PEAK_FLOPS:8.4f}"
+                     f" {per_row * rows:11.4e}")
+    return lines
+
+
 def main(argv):
+    if len(argv) >= 2 and argv[1] == "--mfma":
+        if len(argv) < 5:
+            print(__doc__)
+            return 2
+        lines = mfma_summary(argv[2], argv[3], int(argv[4]))
+        print("\n".join(lines))
+        return 0
     if len(argv) < 5:
         print(__doc__)
         return 2
