@@ -193,7 +193,7 @@ hipError_t run_theta(dolinc_ctx_s* c, const void* U, const void* G1, float* thet
   a.U = (const T*)U;
   a.G1 = (const T*)G1;
   const dim3 grid(8 * a.cell_per_xcd), blk(KTPB);
-  const int dcs = dc_stride(c->params.scheme);
+  const int dcs = dc_stride(c->params.scheme, c->w.precision);
   if (c->dim == 2) {
     hipLaunchKernelGGL((k_theta<T, 2, 1>), grid, blk, 0, s, a, dcs, theta);
   } else if (c->w.nv == 1) {

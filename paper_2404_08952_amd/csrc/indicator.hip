@@ -6,7 +6,7 @@
 namespace dolinc {
 
 hipError_t features_launch(dolinc_ctx_s* c, const void* U, float* X32, unsigned short* Xb, hipStream_t s) {
-  const int dcs = dc_stride(c->params.scheme);
+  const int dcs = dc_stride(c->params.scheme, c->w.precision);
   if (c->w.precision == DOLINC_FP64) {
     KArgs<double> a = base_args<double>(c);
     a.U = (const double*)U;
@@ -28,7 +28,7 @@ static MlpDev mlp_dev(dolinc_ctx_s* c) {
 }
 
 hipError_t indicator_launch(dolinc_ctx_s* c, const void* U, float* theta, hipStream_t s) {
-  const int dcs = dc_stride(c->params.scheme);
+  const int dcs = dc_stride(c->params.scheme, c->w.precision);
   const MlpDev m = mlp_dev(c);
   if (c->w.precision == DOLINC_FP64) {
     KArgs<double> a = base_args<double>(c);
@@ -43,7 +43,7 @@ hipError_t indicator_launch(dolinc_ctx_s* c, const void* U, float* theta, hipStr
 }
 
 hipError_t grad_indicator_launch(dolinc_ctx_s* c, const void* U, void* G1, float* theta, hipStream_t s) {
-  const int dcs = dc_stride(c->params.scheme);
+  const int dcs = dc_stride(c->params.scheme, c->w.precision);
   const MlpDev m = mlp_dev(c);
   if (c->w.precision == DOLINC_FP64) {
     KArgs<double> a = base_args<double>(c);

@@ -13,8 +13,12 @@ namespace dolinc {
 
 // Per-face record layout (one record per partition entry).
 //   sw[e][4]  : S_x, S_y, S_z (0 in 2-D), omega (owner weight)
-//   dc[e][DC] : d_x, d_y, d_z, then the coefficients of the DOLINC
-//               representation of each side (see kernels for the meaning).
+//   dc[e][DC] : d_x, d_y, d_z, then (FP64 working type, linear schemes) the
+//               coefficients of the DOLINC representation of each side in
+//               the order of face_coefficients (coefficients.hpp), else the
+//               growth rate g alone (DC = 4): the FP32 flux kernel evaluates
+//               the coefficients from g in FP64 (fewer bytes per entry; the
+//               FP64 kernel, short of registers, reads them).
 // Per-cell face records in sliced ELL order: cells are taken in blocks of
 // ELL_BLOCK; block b holds m_b = (max faces of a cell in b) records per
 // cell, record j of cell lane l at ell_ptr[b] + j * ELL_BLOCK + l, so that
@@ -28,17 +32,17 @@ namespace dolinc {
 //                  sum_r (phi_o - phi_c) ell_sw[r][0..D).
 //   ell_d[r][4]  : sigma d_x, sigma d_y, sigma d_z, sigma (0 for padding).
 constexpr int ELL_BLOCK = 256;
-inline int coef_left(int scheme) {
-  return scheme <= 2 ? 1 : scheme == 3 ? 2 : scheme == 4 ? 3 : scheme == 8 ? 5 : 4;
-}
-inline int coef_right(int scheme) { return scheme <= 2 ? 1 : scheme == 3 ? 2 : (scheme == 4 || scheme == 8) ? 0 : 4; }
-// ENO3 / WENO5 records hold d and the growth rate g; their coefficients
-// are rational functions of g evaluated in the kernel.
 inline bool nonlinear_scheme(int scheme) { return scheme == 6 || scheme == 7; }
-inline int dc_stride(int scheme) {
-  if (nonlinear_scheme(scheme)) return 4;
-  int n = 3 + coef_left(scheme) + coef_right(scheme);
-  return (n + 3) & ~3;
+// coefficients per face of the linear schemes (both sides)
+inline int face_coef_count(int scheme) {
+  return scheme <= 2 ? 2 : scheme == 3 ? 4 : scheme == 4 ? 3 : scheme == 8 ? 5 : 8;
+}
+inline bool coefficients_stored(int scheme, int precision) {
+  return precision == DOLINC_FP64 && !nonlinear_scheme(scheme);
+}
+inline int dc_stride(int scheme, int precision) {
+  if (!coefficients_stored(scheme, precision)) return 4;
+  return (3 + face_coef_count(scheme) + 3) & ~3;
 }
 inline int scheme_order(int scheme) { return scheme <= 2 ? 0 : scheme <= 4 ? 1 : 2; }
 

@@ -9,14 +9,12 @@
 //           gives exact volume and centroid of the fan-bounded polyhedron.
 // Face scalars (Sec. 2.2): d = x_N - x_P, omega = |x_N - x_f| /
 // (|x_P - x_f| + |x_N - x_f|), growth rate g = omega / (1 - omega).
-// Coefficients (Sec. 2.3-2.4): reconstruction weights c_rj of eq:coeff in
-// closed form in g (USR3, CSR4 as printed; USR5 from the same formula),
-// G_n always summed as 1 + g + ... + g^(n-1); far cells folded in with the
-// inversion coefficients eq:lCoeffDLC1, eq:rCoeffDLC1, eq:lCoeffDLC2 into
-//   U_side = phi_other + w (phi_self - phi_other)
-//            + k0 phi_self^(1) + k1 phi_other^(1) + k2 phi_self^(2).
+// Per face entry: S and omega, d, and either the coefficients of the DOLINC
+// representation (FP64 working type) or g, from which the FP32 flux kernel
+// evaluates them in FP64 (coefficients.hpp).
 #include <hip/hip_runtime.h>
 
+#include "coefficients.hpp"
 #include "internal.hpp"
 
 namespace dolinc {
@@ -170,76 +168,6 @@ __global__ void k_face_scalars(int64_t nf, int dim, const int32_t* __restrict__ 
   if (!(om > 0.0 && om < 1.0)) atomicOr(flag, 4);
 }
 
-// DOLINC representation of one side (self = upwind cell of this frame,
-// growth rate g from self to other).  w, k0, k1, k2 as in the file comment.
-__device__ void side_coefficients(int scheme, double g, double* w, double* k0, double* k1, double* k2,
-                                  double* k3 = nullptr) {
-  *k0 = 0.0; *k1 = 0.0; *k2 = 0.0;
-  const double ig = 1.0 / g;
-  const double g2 = g * g, g3 = g2 * g, g4 = g3 * g, g5 = g4 * g;
-  const double G2 = 1.0 + g, G3 = 1.0 + g + g2, G4 = G3 + g3, G5 = G4 + g4;
-  switch (scheme) {
-    case DOLINC_FOU:
-      *w = 1.0;
-      return;
-    case DOLINC_CD2:
-      *w = g / G2;  // linear interpolation with the distance weight
-      return;
-    case DOLINC_USR3: {
-      const double den = G2 * G3;
-      const double c10 = -g3 / den, c11 = g * (1.0 + 2.0 * g + 2.0 * g2) / den;
-      // eq:lCoeffDLC1: a0 = 1 - 1/g, A = -phi_self^(1) / g
-      *w = c10 * (1.0 - ig) + c11;
-      *k0 = -c10 * ig;
-      return;
-    }
-    case DOLINC_CSR4: {
-      const double den = G3 * G4;
-      const double c10 = -g5 / den;
-      const double c11 = g2 * (1.0 + 2.0 * g + 2.0 * g2 + 2.0 * g3) / den;
-      const double c13 = -1.0 / den;
-      // eq:lCoeffDLC1 for the left far cell, eq:rCoeffDLC1 (a0 = g,
-      // A = g phi_other^(1)) for the right one
-      *w = c10 * (1.0 - ig) + c11 + c13 * g;
-      *k0 = -c10 * ig;
-      *k1 = c13 * g;
-      return;
-    }
-    case DOLINC_USR5: {
-      const double q = 1.0 + g2;
-      const double den = G2 * q * G3 * G5;
-      const double c0 = g4 * g5 / (q * G3 * G5);
-      const double c1 = -g5 * (g5 + 3.0 * g4 + 3.0 * g3 + 3.0 * g2 + 2.0 * g + 1.0) / den;
-      const double c2 = g2 * (3.0 * g5 * g2 + 6.0 * g3 * g3 + 9.0 * g5 + 10.0 * g4 + 9.0 * g3 + 6.0 * g2 +
-                              3.0 * g + 1.0) / den;
-      const double c4 = -1.0 / (G2 * q * G5);
-      const double ig2 = ig * ig, ig3 = ig2 * ig;
-      // eq:lCoeffDLC2 (phi_-2), eq:lCoeffDLC1 (phi_-1), eq:rCoeffDLC1 (phi_2)
-      *w = c0 * (1.0 - ig + ig2) + c1 * (1.0 - ig) + c2 + c4 * g;
-      *k0 = -c0 * ig * (1.0 - ig2) - c1 * ig;
-      *k1 = -c0 * ig3 + c4 * g;
-      *k2 = c0 * ig3;
-      return;
-    }
-    case DOLINC_CSR6: {
-      // eq:coeff on the six cells -2..3 with the far cells from eq:lCoeffDLC2
-      // (phi_-2), eq:lCoeffDLC1 (phi_-1), eq:rCoeffDLC1 (phi_2) and
-      // eq:rCoeffDLC2 (phi_3), collected on phi_0, phi_1 and the differentials
-      // (closed forms in g; 1/2, 3/20, -3/20, 1/60, 1/60 at g = 1)
-      const double gm = g2 - g + 1.0;
-      const double den = G2 * (1.0 + g2) * G5;
-      *w = g * (g5 * g + 5.0 * g5 + 4.0 * g4 + 2.0 * g3 + 2.0 * g2 - g - 3.0) / den;
-      *k0 = g2 * (2.0 * g5 * g + g3 - g + 1.0) / (den * gm);
-      *k1 = -g * (g5 * g - g5 + g3 + 2.0) / (den * gm);
-      *k2 = g4 * g5 / (den * gm * G3);
-      if (k3) *k3 = g2 / (den * gm * G3);
-      return;
-    }
-    default:
-      *w = 1.0;
-  }
-}
-
 template <class T>
 __global__ void k_entry_fill(int64_t ne, int dim, int scheme, int dcs, const int32_t* __restrict__ ent_face,
                              const double* __restrict__ S, const double* __restrict__ omega,
@@ -257,39 +185,15 @@ __global__ void k_entry_fill(int64_t ne, int dim, int scheme, int dcs, const int
   o[0] = (T)dvec[3 * f + 0];
   o[1] = (T)dvec[3 * f + 1];
   o[2] = (T)dvec[3 * f + 2];
-  const double gf = g[f];
-  if (scheme == DOLINC_ENO3 || scheme == DOLINC_WENO5) {  // the growth rate; coefficients follow in the kernel
-    o[3] = (T)gf;
+  if (sizeof(T) == 8 && scheme != DOLINC_ENO3 && scheme != DOLINC_WENO5) {
+    // FP64 working type: the coefficients of both sides, stored
+    double cf[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    face_coefficients(scheme, g[f], cf);
+    for (int k = 3; k < dcs; ++k) o[k] = (T)cf[k - 3];
     return;
   }
-  double w, k0, k1, k2, k3 = 0.0;
-  // left state: frame P -> N, growth g; factors 2 and 4 of the DOLINC
-  // differentials folded in (they multiply d.G1 and d.G2.d)
-  side_coefficients(scheme, gf, &w, &k0, &k1, &k2, &k3);
-  int k = 3;
-  if (scheme == DOLINC_CSR6) {  // symmetric template: one state per face
-    o[k++] = (T)w; o[k++] = (T)(2.0 * k0); o[k++] = (T)(2.0 * k1); o[k++] = (T)(4.0 * k2); o[k++] = (T)(4.0 * k3);
-    return;
-  }
-  if (scheme <= DOLINC_CD2) {
-    o[k++] = (T)w;
-  } else if (scheme == DOLINC_USR3) {
-    o[k++] = (T)w; o[k++] = (T)(2.0 * k0);
-  } else if (scheme == DOLINC_CSR4) {
-    o[k++] = (T)w; o[k++] = (T)(2.0 * k0); o[k++] = (T)(2.0 * k1);
-  } else {
-    o[k++] = (T)w; o[k++] = (T)(2.0 * k0); o[k++] = (T)(2.0 * k1); o[k++] = (T)(4.0 * k2);
-  }
-  if (scheme == DOLINC_CSR4) return;  // symmetric template: one state per face
-  // right state: mirrored frame N -> P, growth 1/g, d -> -d
-  side_coefficients(scheme, 1.0 / gf, &w, &k0, &k1, &k2);
-  if (scheme <= DOLINC_CD2) {
-    o[k++] = (T)w;
-  } else if (scheme == DOLINC_USR3) {
-    o[k++] = (T)w; o[k++] = (T)(-2.0 * k0);
-  } else {
-    o[k++] = (T)w; o[k++] = (T)(-2.0 * k0); o[k++] = (T)(-2.0 * k1); o[k++] = (T)(4.0 * k2);
-  }
+  // the growth rate: the kernels evaluate the coefficients from it in FP64
+  o[3] = (T)g[f];
 }
 
 // Auxiliary cells of boundary faces: the mirror image of the boundary cell
@@ -391,7 +295,7 @@ hipError_t launch_geometry(dolinc_ctx_s* c, hipStream_t s) {
 hipError_t launch_entry_fill(dolinc_ctx_s* c, hipStream_t s) {
   DevMesh& m = c->m;
   const int sch = c->params.scheme;
-  const int dcs = dc_stride(sch);
+  const int dcs = dc_stride(sch, c->w.precision);
   if (c->w.precision == DOLINC_FP64) {
     hipLaunchKernelGGL(k_entry_fill<double>, dim3(nblk(c->n_entries)), dim3(TPB), 0, s, c->n_entries, c->dim, sch,
                        dcs, m.ent_face, m.S, m.omega, m.g, m.dvec, (double*)c->w.sw, (double*)c->w.dc);

@@ -21,6 +21,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "coefficients.hpp"
 #include "internal.hpp"
 
 namespace dolinc {
@@ -79,10 +80,13 @@ struct NVars {
 template <int SCH>
 struct SchemeInfo {
   static constexpr int ORD = SCH <= 2 ? 0 : (SCH <= 4 ? 1 : 2);
-  static constexpr int NL = SCH <= 2 ? 1 : (SCH == 3 ? 2 : (SCH == 4 ? 3 : (SCH == 8 ? 5 : 4)));
-  static constexpr int NR = SCH <= 2 ? 1 : (SCH == 3 ? 2 : ((SCH == 4 || SCH == 8) ? 0 : 4));
-  static constexpr bool NONLIN = SCH == 6 || SCH == 7;  // ENO3, WENO5: d and g only
-  static constexpr int DCS = NONLIN ? 4 : (3 + NL + NR + 3) & ~3;
+  static constexpr bool NONLIN = SCH == 6 || SCH == 7;  // ENO3, WENO5
+  static constexpr int NC = SCH <= 2 ? 2 : (SCH == 3 ? 4 : (SCH == 4 ? 3 : (SCH == 8 ? 5 : 8)));
+  // values per face entry in dc: d and g, or (FP64, linear) d and the coefficients
+  template <class T>
+  static constexpr int dcs() {
+    return (NONLIN || sizeof(T) == 4) ? 4 : (3 + NC + 3) & ~3;
+  }
 };
 
 // A partition's cells are a contiguous index range, so their rows of a
@@ -537,7 +541,7 @@ __device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T
                                           const Stage<T>& st = Stage<T>()) {
   constexpr int NV = NVars<PK, D>::value;
   constexpr int ORD = SchemeInfo<SCH>::ORD;
-  constexpr int DCS = SchemeInfo<SCH>::DCS;
+  constexpr int DCS = SchemeInfo<SCH>::template dcs<T>();
   const int2 pn = a.ent_pn[e];
   const int64_t P = pn.x, N = pn.y;
   const T* swp = a.sw + 4 * e;
@@ -589,24 +593,36 @@ __device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T
 #pragma unroll
     for (int v = 0; v < NV; ++v)
       UR[v] = nonlin_side<T, SCH>(cf, uN[v], uP[v], T(-2) * gN[v], T(-2) * gP[v], T(4) * hN[v]);
-  } else
+  } else {
+    // coefficients of both sides: stored (FP64) or from g in FP64, rounded once to T
+    T c[8];
+    if constexpr (DCS > 4) {
 #pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    if constexpr (SCH <= 2) {
-      UL[v] = uN[v] + dc[3] * (uP[v] - uN[v]);
-      UR[v] = uP[v] + dc[4] * (uN[v] - uP[v]);
-    } else if constexpr (SCH == 3) {
-      UL[v] = uN[v] + dc[3] * (uP[v] - uN[v]) + dc[4] * gP[v];
-      UR[v] = uP[v] + dc[5] * (uN[v] - uP[v]) + dc[6] * gN[v];
-    } else if constexpr (SCH == 4) {
-      UL[v] = uN[v] + dc[3] * (uP[v] - uN[v]) + dc[4] * gP[v] + dc[5] * gN[v];
-      UR[v] = UL[v];
-    } else if constexpr (SCH == 8) {  // CSR6: symmetric template, both second differentials
-      UL[v] = uN[v] + dc[3] * (uP[v] - uN[v]) + dc[4] * gP[v] + dc[5] * gN[v] + dc[6] * hP[v] + dc[7] * hN[v];
-      UR[v] = UL[v];
+      for (int k = 0; k < 8; ++k) c[k] = 3 + k < DCS ? dc[3 + k] : T(0);
     } else {
-      UL[v] = uN[v] + dc[3] * (uP[v] - uN[v]) + dc[4] * gP[v] + dc[5] * gN[v] + dc[6] * hP[v];
-      UR[v] = uP[v] + dc[7] * (uN[v] - uP[v]) + dc[8] * gN[v] + dc[9] * gP[v] + dc[10] * hN[v];
+      double cd[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      face_coefficients(SCH, (double)dc[3], cd);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) c[k] = (T)cd[k];
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      if constexpr (SCH <= 2) {
+        UL[v] = uN[v] + c[0] * (uP[v] - uN[v]);
+        UR[v] = uP[v] + c[1] * (uN[v] - uP[v]);
+      } else if constexpr (SCH == 3) {
+        UL[v] = uN[v] + c[0] * (uP[v] - uN[v]) + c[1] * gP[v];
+        UR[v] = uP[v] + c[2] * (uN[v] - uP[v]) + c[3] * gN[v];
+      } else if constexpr (SCH == 4) {
+        UL[v] = uN[v] + c[0] * (uP[v] - uN[v]) + c[1] * gP[v] + c[2] * gN[v];
+        UR[v] = UL[v];
+      } else if constexpr (SCH == 8) {  // CSR6: symmetric template, both second differentials
+        UL[v] = uN[v] + c[0] * (uP[v] - uN[v]) + c[1] * gP[v] + c[2] * gN[v] + c[3] * hP[v] + c[4] * hN[v];
+        UR[v] = UL[v];
+      } else {
+        UL[v] = uN[v] + c[0] * (uP[v] - uN[v]) + c[1] * gP[v] + c[2] * gN[v] + c[3] * hP[v];
+        UR[v] = uP[v] + c[4] * (uN[v] - uP[v]) + c[5] * gN[v] + c[6] * gP[v] + c[7] * hN[v];
+      }
     }
   }
   if constexpr (BLEND) {
