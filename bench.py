@@ -159,6 +159,62 @@ def shock_tube_line(args):
     return out
 
 
+def tgv_kinetic_energy_line(args):
+    """Kinetic-energy history of the Taylor-Green vortex on the 2.0M-cell
+    subset mesh (126^3 jittered hexes, same recipe): the FP32 path with the
+    learned blend against the FP64 plain path (no blend), beside FP32 plain,
+    FP64 learned and FP32 with the classical sensor; 100 SSP-RK3 steps at
+    CFL 0.4, sampled every 10 steps."""
+    import torch
+    from paper_2404_08952_amd import Solver
+    from synth import configs
+    case = configs.taylor_green_3d(n=126)
+    nsteps, every = 100, 10
+    hist = {}
+    theta = {}
+    ref = dict(u_ref=configs.TGV_REF)
+    for label, prec, extra in (("fp64_plain", "fp64", dict(blend="none")),
+                               ("fp32_plain", "fp32", dict(blend="none", **ref)),
+                               ("fp64_learned", "fp64", dict(blend="learned")),
+                               ("fp32_learned", "fp32", dict(blend="learned", **ref)),
+                               ("fp32_classical", "fp32", dict(blend="classical", **ref))):
+        s = Solver(case.mesh, **case.params, precision=prec, **extra)
+        if extra["blend"] == "learned":
+            s.mlp_set(indicator_weights())
+        V = s.geometry()["V"][:case.mesh.n_cells]
+
+        def ke(U):
+            u = U[:case.mesh.n_cells].double()
+            return float(((0.5 * (u[:, 1:4] ** 2).sum(1) / u[:, 0]) * V).sum() / V.sum())
+        U = s.to_internal(case.U0)
+        h = [ke(U)]
+        for _ in range(nsteps // every):
+            s.advance(U, case.dt, every)
+            h.append(ke(U))
+        hist[label] = h
+        if extra["blend"] != "none":  # blend weights of the final state
+            if extra["blend"] == "learned":
+                th = s.mlp_forward(s.features(U, fp32=False)[1])[:case.mesh.n_cells]
+            else:
+                th = s.classical_theta(U)[:case.mesh.n_cells]
+            theta[label] = dict(mean=float(th.mean()), frac_below_0_9=float((th < 0.9).double().mean()))
+        s.close()
+        del U
+        torch.cuda.empty_cache()
+    a64 = hist["fp64_plain"]
+    out = dict(workload=f"Taylor-Green 126^3 ({case.mesh.n_cells:,} cells), {nsteps} steps, dt {case.dt:.4e}",
+               t=[case.dt * every * k for k in range(len(a64))], kinetic_energy=hist, theta_final=theta,
+               decay={k: h[0] - h[-1] for k, h in hist.items()},
+               max_rel_difference_vs_fp64_plain={k: max(abs(x - y) / y for x, y in zip(h, a64))
+                                                  for k, h in hist.items() if k != "fp64_plain"})
+    log(f"[bench] TGV 126^3 kinetic energy decay over {nsteps} steps: " +
+        ", ".join(f"{k} {v:.3e}" for k, v in out["decay"].items()) +
+        "; max relative difference to FP64 plain: " +
+        ", ".join(f"{k} {v:.2e}" for k, v in out["max_rel_difference_vs_fp64_plain"].items()) +
+        f"; learned theta: {theta}")
+    return out
+
+
 MLP_FWD_FLOP = 2 * (24 * 64 + 64 * 64 + 64 * 1)   # multiply-adds of 24 -> 64 -> 64 -> 1, per cell
 BF16_PEAK_TFLOPS = 2500.0
 
@@ -305,6 +361,7 @@ def main():
     ap.add_argument("--cpu-baseline-only", action="store_true")
     ap.add_argument("--indicator-only", action="store_true",
                     help="only the indicator network's inference / training throughput (for counter runs)")
+    ap.add_argument("--ke-only", action="store_true", help="only the Taylor-Green kinetic-energy comparison")
     args = ap.parse_args()
 
     if args.cpu_baseline_only:
@@ -320,6 +377,9 @@ def main():
         raise SystemExit("bench.py needs a GPU")
     if args.indicator_only:
         print(json.dumps(indicator_line(args)))
+        return
+    if args.ke_only:
+        print(json.dumps(tgv_kinetic_energy_line(args)))
         return
     dev = torch.cuda.get_device_name(0)
     t0 = time.time()
@@ -354,6 +414,7 @@ def main():
     del solver
     tube = shock_tube_line(args) if args.workload == "tgv3d" else None
     mlp = indicator_line(args) if args.workload == "tgv3d" else None
+    ke = tgv_kinetic_energy_line(args) if args.workload == "tgv3d" else None
     gbps_copy = copy_bandwidth()
     log(f"[bench] streaming y = -x: {gbps_copy:.0f} GB/s")
 
@@ -413,6 +474,7 @@ def main():
                                for k, v in nonlin.items()},
         "bounded_fp32": tube,
         "indicator_network": mlp,
+        "tgv_kinetic_energy": ke,
         "device": dev,
         "copy_gbps": gbps_copy,
     }
