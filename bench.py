@@ -362,6 +362,8 @@ def main():
     ap.add_argument("--indicator-only", action="store_true",
                     help="only the indicator network's inference / training throughput (for counter runs)")
     ap.add_argument("--ke-only", action="store_true", help="only the Taylor-Green kinetic-energy comparison")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the FP32 / FP64 headline paths (for profiler runs: per-kernel averages of one mesh)")
     args = ap.parse_args()
 
     if args.cpu_baseline_only:
@@ -399,7 +401,8 @@ def main():
         log(f"[bench] {prec}: {res[prec]['ms_per_step']:.3f} ms/step, kernels ms {res[prec]['kernel_ms']}")
     # the non-oscillatory DOLINC schemes and CSR6 on the same mesh (FP32, no blend)
     nonlin = {}
-    if args.workload == "tgv3d":
+    extras = args.workload == "tgv3d" and not args.headline_only
+    if extras:
         for sch in ("WENO5", "ENO3", "CSR6"):
             r = time_path(solver, case, "fp32", dict(fp32_extra, blend="none"), max(1, min(args.steps, 5)), 1,
                           params=dict(case.params, scheme=sch))
@@ -412,9 +415,9 @@ def main():
             log(f"[bench] fp32 {sch}: {r['ms_per_step']:.3f} ms/step, kernels ms {r['kernel_ms']}")
     solver.close()
     del solver
-    tube = shock_tube_line(args) if args.workload == "tgv3d" else None
-    mlp = indicator_line(args) if args.workload == "tgv3d" else None
-    ke = tgv_kinetic_energy_line(args) if args.workload == "tgv3d" else None
+    tube = shock_tube_line(args) if extras else None
+    mlp = indicator_line(args) if extras else None
+    ke = tgv_kinetic_energy_line(args) if extras else None
     gbps_copy = copy_bandwidth()
     log(f"[bench] streaming y = -x: {gbps_copy:.0f} GB/s")
 

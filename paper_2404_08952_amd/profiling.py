@@ -58,18 +58,24 @@ def kernel_stats(stats_dir):
     return sorted(out, key=lambda x: -x[3])
 
 
-def counter_values(pmc_dir, counter, kernel_regex):
+def counter_values(pmc_dir, counter, kernel_regex, largest_grid=False):
+    """Counter values of the matching dispatches (with largest_grid, only
+    those of the largest grid: the full-size mesh when smaller runs of the
+    same kernel share the file)."""
     rows = _csv(pmc_dir, "*counter_collection.csv")
     rx = re.compile(kernel_regex)
-    vals = [float(r["Counter_Value"]) for r in rows
-            if r["Counter_Name"] == counter and rx.search(r["Kernel_Name"])]
-    return vals
+    sel = [(int(r["Grid_Size"]), float(r["Counter_Value"])) for r in rows
+           if r["Counter_Name"] == counter and rx.search(r["Kernel_Name"])]
+    if largest_grid and sel:
+        g = max(x[0] for x in sel)
+        sel = [x for x in sel if x[0] == g]
+    return [v for _g, v in sel]
 
 
 def traffic(fetch_dir, write_dir, kernel_regex=re.escape(FLUX_KERNEL), calib_regex=CALIB_KERNEL):
     """HBM bytes per launch of the kernel, calibrated on the streaming kernel."""
-    f_k = counter_values(fetch_dir, "FETCH_SIZE", kernel_regex)
-    w_k = counter_values(write_dir, "WRITE_SIZE", kernel_regex)
+    f_k = counter_values(fetch_dir, "FETCH_SIZE", kernel_regex, largest_grid=True)
+    w_k = counter_values(write_dir, "WRITE_SIZE", kernel_regex, largest_grid=True)
     f_c = counter_values(fetch_dir, "FETCH_SIZE", calib_regex)
     w_c = counter_values(write_dir, "WRITE_SIZE", calib_regex)
     if not (f_k and w_k and f_c and w_c):
