@@ -592,7 +592,7 @@ __global__ __launch_bounds__(KTPB) void k_grad_indicator(KArgs<T> a, int dcs, Ml
   T g[NV * D];
   if (c < a.nc) {
     T acc[NV][D];
-    grad_sums<T, D, NV>(a, a.U, c, acc, ul, c0, ncl);
+    grad_sums<T, D, NV, 6>(a, a.U, c, acc, ul, c0, ncl);
     const T rv = a.rV[c];
     for (int k = 0; k < NV; ++k)
       for (int x = 0; x < D; ++x) g[k * D + x] = acc[k][x] * rv;

@@ -823,10 +823,13 @@ __device__ __forceinline__ int64_t rec_cell(double v) { return (int64_t)__double
 // cell waits on two memory latencies per batch.  Padding records name the
 // cell itself with zero weight (phi_c - phi_c = 0), leaving the sums as
 // they are.  c must be cell lane of the ELL block c / KTPB.
-template <class T, int D, int NQ>
+// GB0: records per batch (0: 3 for rows of at most 5 values, else 2; the
+// measured optimum of the gradient kernel; the fused indicator kernel
+// prefers 6).
+template <class T, int D, int NQ, int GB0 = 0>
 __device__ __forceinline__ void grad_sums(const KArgs<T>& a, const T* __restrict__ phi, int64_t c, T (*acc)[D],
                                           const T* lds = nullptr, int64_t c0 = 0, int n = 0) {
-  constexpr int GB = NQ <= 5 ? 4 : 2;
+  constexpr int GB = GB0 > 0 ? GB0 : (NQ <= 5 ? 3 : 2);
   const int64_t b = c / KTPB;
   const int lane = (int)(c - b * KTPB);
   const int r0 = a.ell_ptr[b], m = (a.ell_ptr[b + 1] - r0) / KTPB;
