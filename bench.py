@@ -230,19 +230,9 @@ def vortex_line(args):
     t0 = time.time()
     case = configs.vortex_3d(scheme="USR3", quad_pts=1)
     steps, cfl = 200, 0.4
-    # CFL on the cells' own geometry: dt = cfl min_c 2 V_c / (lambda sum_f |S_f|)
-    # (h / dim on a cube; the lattice rule of the recipe overestimates it
-    # about twofold on Kuhn tetrahedra, where every scheme then blows up)
-    g = Solver(case.mesh, **case.params, precision="fp64")
-    geo = g.geometry()
-    n = case.mesh.n_cells
-    area = torch.linalg.norm(geo["S"], dim=1).cpu().numpy()
-    ssum = np.bincount(case.mesh.owner, weights=area, minlength=n) + \
-        np.bincount(case.mesh.neighbour, weights=area, minlength=n)
-    V = geo["V"].cpu().numpy()[g.perm]
-    g.close()
-    lam = fields.max_wave_speed("euler", case.U0)
-    dt = cfl * float(np.min(2.0 * V / ssum)) / lam
+    # CFL on the cells' own geometry (the lattice rule of the recipe is ten
+    # times larger on the jittered Kuhn slivers, where every scheme blows up)
+    dt = geometric_dt(case, cfl, "euler")
     exact = fields.cell_averages(case.mesh, case.exact(steps * dt), n_pts=1)
     log(f"[bench] vortex 64^3 x 6 tets: set-up {time.time() - t0:.1f} s")
     out = dict(workload=f"isentropic vortex, {case.mesh.n_cells:,} jittered Kuhn tetrahedra, USR3, Rusanov, "
@@ -271,6 +261,88 @@ def vortex_line(args):
         del U
         torch.cuda.empty_cache()
     out["rho_fp32_vs_fp64_rel_l2"] = float(np.linalg.norm(rho["fp32"] - rho["fp64"]) / np.linalg.norm(rho["fp64"]))
+    return out
+
+
+def geometric_dt(case, cfl, pde, t_end=None):
+    """CFL time step on the cells' own geometry, dt = cfl min_c 2 V_c /
+    (lambda sum_f |S_f|) (h / dim on a square or cube); with t_end, the
+    step count to reach it and the step that lands on it."""
+    import math
+    import numpy as np
+    import torch
+    from paper_2404_08952_amd import Solver
+    from synth import fields
+    g = Solver(case.mesh, **case.params, precision="fp64")
+    geo = g.geometry()
+    n = case.mesh.n_cells
+    area = torch.linalg.norm(geo["S"], dim=1).cpu().numpy()
+    two = case.mesh.neighbour >= 0
+    ssum = np.bincount(case.mesh.owner, weights=area, minlength=n) + \
+        np.bincount(case.mesh.neighbour[two], weights=area[two], minlength=n)
+    V = geo["V"].cpu().numpy()[g.perm]
+    g.close()
+    dt = cfl * float(np.min(2.0 * V / ssum)) / fields.max_wave_speed(pde, case.U0)
+    if t_end is None:
+        return dt
+    steps = int(math.ceil(t_end / dt - 1e-12))
+    return t_end / steps, steps
+
+
+def burgers_sweep_line(args):
+    """2-D inviscid Burgers along (1, 1) on the mixed tri / quad / pentagon
+    meshes of the recipe (half the quads split, 5 % pentagons, +-0.25 h
+    jitter; the same meshes unjittered; regular all-triangle and all-quad
+    meshes to 256^2), u0 = 0.5 + 0.25 sin 2 pi (x + y) to t = 0.05 (before the shock),
+    USR3 and CSR4 with the Godunov flux at CFL 0.5 on the cell geometry
+    (geometric_dt), FP64 and FP32: error
+    against the exact solution's cell averages at 64^2 .. 512^2 and the
+    observed orders, and the throughput at 256^2."""
+    import numpy as np
+    import torch
+    from paper_2404_08952_amd import Solver
+    from synth import configs, fields
+    from synth import mesh as M
+    kinds = ("jittered", "unjittered", "triangles", "quads")
+    combos = [(k, sch, prec) for k in kinds for sch in ("USR3", "CSR4") for prec in ("fp64", "fp32")]
+    res = {c: dict(cells=[], l2_error=[], finite=[], cell_updates_per_s_256=None) for c in combos}
+    runs = [(k, n) for k in kinds for n in ((64, 128, 256, 512) if k in kinds[:2] else (64, 128, 256))]
+    for kind, n in runs:
+        case = configs.burgers_2d(n=n, jitter=0.25 if kind == "jittered" else 0.0)
+        if kind in ("triangles", "quads"):  # the same problem on regular meshes of one cell type
+            case.mesh = M.periodic_2d(n, n, split=1.0 if kind == "triangles" else 0.0, diagonal="main")
+            case.U0 = fields.cell_averages(case.mesh, fields.burgers_diag(0.0), n_pts=4)
+        dt, steps = geometric_dt(case, 0.5, "burgers", t_end=0.05)
+        case.dt, case.steps = dt, steps
+        ex = fields.cell_averages(case.mesh, case.exact(case.steps * case.dt), n_pts=4)[:, 0]
+        for _k, scheme, prec in [c for c in combos if c[0] == kind]:
+            s = Solver(case.mesh, **dict(case.params, scheme=scheme), precision=prec)
+            U = s.to_internal(case.U0)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            s.advance(U, case.dt, case.steps)
+            e1.record()
+            torch.cuda.synchronize()
+            r = res[(kind, scheme, prec)]
+            if n == 256:
+                r["cell_updates_per_s_256"] = case.mesh.n_cells * 3 * case.steps / (e0.elapsed_time(e1) * 1e-3)
+            u = s.to_external(U)[:, 0].astype(np.float64)
+            V = s.geometry()["V"].cpu().numpy()[s.perm]
+            s.close()
+            ok = bool(np.isfinite(u).all())
+            r["l2_error"].append(float(np.sqrt(np.sum(V * (u - ex) ** 2) / np.sum(V))) if ok else float("nan"))
+            r["cells"].append(case.mesh.n_cells)
+            r["finite"].append(ok)
+    out = {}
+    for (kind, scheme, prec), r in res.items():
+        e = np.array(r["l2_error"])
+        r["observed_order"] = [float(x) for x in np.log2(e[:-1] / e[1:])]
+        key = f"{kind}_{scheme}_{prec}"
+        out[key] = r
+        log(f"[bench] Burgers 2-D {key}: L2 errors {['%.3e' % x for x in r['l2_error']]}, orders "
+            f"{['%.2f' % x for x in r['observed_order']]}")
     return out
 
 
@@ -422,6 +494,7 @@ def main():
                     help="only the indicator network's inference / training throughput (for counter runs)")
     ap.add_argument("--ke-only", action="store_true", help="only the Taylor-Green kinetic-energy comparison")
     ap.add_argument("--vortex-only", action="store_true", help="only the isentropic-vortex line")
+    ap.add_argument("--burgers-only", action="store_true", help="only the 2-D Burgers refinement sweep")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the FP32 / FP64 headline paths (for profiler runs: per-kernel averages of one mesh)")
     args = ap.parse_args()
@@ -445,6 +518,9 @@ def main():
         return
     if args.vortex_only:
         print(json.dumps(vortex_line(args)))
+        return
+    if args.burgers_only:
+        print(json.dumps(burgers_sweep_line(args)))
         return
     dev = torch.cuda.get_device_name(0)
     t0 = time.time()
@@ -482,6 +558,7 @@ def main():
     mlp = indicator_line(args) if extras else None
     ke = tgv_kinetic_energy_line(args) if extras else None
     vtx = vortex_line(args) if extras else None
+    brg = burgers_sweep_line(args) if extras else None
     gbps_copy = copy_bandwidth()
     log(f"[bench] streaming y = -x: {gbps_copy:.0f} GB/s")
 
@@ -543,6 +620,7 @@ def main():
         "indicator_network": mlp,
         "tgv_kinetic_energy": ke,
         "vortex_closed_form": vtx,
+        "burgers_2d_sweep": brg,
         "device": dev,
         "copy_gbps": gbps_copy,
     }
