@@ -264,6 +264,66 @@ def vortex_line(args):
     return out
 
 
+def shocks_line(args):
+    """The Sod slab of the shock workload at an eighth of its size (100^3
+    jittered hexes, 30 % split into tetrahedra and prisms: about 1.9M cells),
+    USR3 + Rusanov to t = 0.1 (time step on the cell geometry): the FP32 path with the learned blend, the FP32
+    path with the classical sensor and the FP64 classical-sensor run, each
+    against the exact Riemann solution (density L1, position of the right
+    shock) and the learned run against the FP64 classical one."""
+    import numpy as np
+    import torch
+    from paper_2404_08952_amd import Solver
+    from synth import configs, fields
+    t0 = time.time()
+    case = configs.shocks_3d(n=100, problem="sod")
+    # CFL 0.4 on the cell geometry with the recipe's margin of 2 on the
+    # initial wave speed (the lattice rule blows up on the jittered slivers)
+    t_end = case.dt * case.steps
+    case.dt, case.steps = geometric_dt(case, 0.2, "euler", t_end=t_end)
+    x = fields.cell_points(case.mesh)[:, 0]
+    t_end = case.dt * case.steps
+    rho_ex = fields.sod_slab_exact(x, t_end)[0]
+    rho_post = fields.riemann_exact((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), np.array([1.7]))[0][0]
+    band = (x > 0.86) & (x < 1.0)
+    log(f"[bench] shock slab {case.mesh.n_cells:,} cells: set-up {time.time() - t0:.1f} s")
+    out = dict(workload=f"Sod slab, {case.mesh.n_cells:,} mixed cells (100^3 hexes, 30 % split), USR3, Rusanov, "
+                        f"{case.steps} steps to t = {t_end:.3f}")
+    rho = {}
+    for label, prec, blend in (("fp64_classical", "fp64", "classical"), ("fp32_classical", "fp32", "classical"),
+                               ("fp32_learned", "fp32", "learned")):
+        s = Solver(case.mesh, **case.params, precision=prec, blend=blend)
+        if blend == "learned":
+            s.mlp_set(indicator_weights())
+        U = s.to_internal(case.U0)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s.advance(U, case.dt, case.steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / case.steps
+        d = s.diagnostics(U)
+        th = (s.mlp_forward(s.features(U, fp32=False)[1]) if blend == "learned" else s.classical_theta(U))
+        frac = float((th[:case.mesh.n_cells] < 0.5).double().mean())
+        u = s.to_external(U)
+        V = s.geometry()["V"].cpu().numpy()[s.perm]
+        s.close()
+        r = u[:, 0].astype(np.float64)
+        rho[label] = (r, V)
+        l1 = float(np.sum(V * np.abs(r - rho_ex)) / V.sum())
+        xs = float(np.sum(V[band] * (r[band] - rho_ex[band])) / (rho_post - 0.125) / V.sum())
+        out[label] = dict(ms_per_step=ms, value=case.mesh.n_cells * 3 / (ms * 1e-3), unit="cell-updates/s",
+                          rho_l1_vs_exact=l1, shock_position_error=xs, frac_theta_below_half=frac,
+                          min_rho=float(d[5]), min_p=float(d[6]), nonfinite=int(d[-1]))
+        log(f"[bench] shock slab {label}: {ms:.3f} ms/step, rho L1 {l1:.4e}, shock position error {xs:+.2e}, "
+            f"theta < 0.5 in {100 * frac:.0f} % of cells")
+    r64, V = rho["fp64_classical"]
+    out["learned_vs_fp64_classical_l1"] = float(np.sum(V * np.abs(rho["fp32_learned"][0] - r64)) / V.sum())
+    return out
+
+
 def geometric_dt(case, cfl, pde, t_end=None):
     """CFL time step on the cells' own geometry, dt = cfl min_c 2 V_c /
     (lambda sum_f |S_f|) (h / dim on a square or cube); with t_end, the
@@ -495,6 +555,7 @@ def main():
     ap.add_argument("--ke-only", action="store_true", help="only the Taylor-Green kinetic-energy comparison")
     ap.add_argument("--vortex-only", action="store_true", help="only the isentropic-vortex line")
     ap.add_argument("--burgers-only", action="store_true", help="only the 2-D Burgers refinement sweep")
+    ap.add_argument("--shocks-only", action="store_true", help="only the shock-slab line")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the FP32 / FP64 headline paths (for profiler runs: per-kernel averages of one mesh)")
     args = ap.parse_args()
@@ -521,6 +582,9 @@ def main():
         return
     if args.burgers_only:
         print(json.dumps(burgers_sweep_line(args)))
+        return
+    if args.shocks_only:
+        print(json.dumps(shocks_line(args)))
         return
     dev = torch.cuda.get_device_name(0)
     t0 = time.time()
@@ -559,6 +623,7 @@ def main():
     ke = tgv_kinetic_energy_line(args) if extras else None
     vtx = vortex_line(args) if extras else None
     brg = burgers_sweep_line(args) if extras else None
+    shk = shocks_line(args) if extras else None
     gbps_copy = copy_bandwidth()
     log(f"[bench] streaming y = -x: {gbps_copy:.0f} GB/s")
 
@@ -621,6 +686,7 @@ def main():
         "tgv_kinetic_energy": ke,
         "vortex_closed_form": vtx,
         "burgers_2d_sweep": brg,
+        "shock_slab": shk,
         "device": dev,
         "copy_gbps": gbps_copy,
     }
