@@ -20,6 +20,9 @@ ARCH = "gfx950"
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          # matrix-core results in ordinary VGPRs: the network's activations
+          # then read them without a v_accvgpr_read per value
+          "-mllvm", "-amdgpu-mfma-vgpr-form=1",
           "-I", os.path.join(os.path.dirname(HERE), "include")]
 SOURCES = ["mesh_prep.cpp", "api.cpp", "precompute.hip", "kernels_f64.hip", "kernels_f32.hip", "indicator.hip",
            "boundary.hip"]

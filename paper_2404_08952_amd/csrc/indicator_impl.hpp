@@ -45,12 +45,18 @@ struct MlpDev {
 
 // ---------------------------------------------------------------- features
 
-// tanh through one exponential: tanh x = 1 - 2 / (exp(2x) + 1), |x| clamped
+// tanh x = 2 / (1 + exp(-2x)) - 1 with the hardware base-2 exponential and
+// reciprocal (five instructions).  No clamp is needed: for large negative x
+// the exponential overflows to +inf and the reciprocal to 0 (tanh = -1), for
+// large positive x it underflows to 0 (tanh = 1).
 __device__ __forceinline__ float fast_tanh(float x) {
-  const float y = fminf(fmaxf(x, -15.f), 15.f);
-  const float e = __expf(2.f * y);
-  return 1.f - 2.f * __builtin_amdgcn_rcpf(e + 1.f);
+  const float e = __builtin_amdgcn_exp2f(x * -2.8853900817779268f);  // -2 log2(e)
+  return fmaf(__builtin_amdgcn_rcpf(1.f + e), 2.f, -1.f);
 }
+
+// x clamped to [lo, hi] (one v_med3 for fp32)
+__device__ __forceinline__ float clampv(float x, float lo, float hi) { return __builtin_amdgcn_fmed3f(x, lo, hi); }
+__device__ __forceinline__ double clampv(double x, double lo, double hi) { return fmin(fmax(x, lo), hi); }
 
 template <class T, int D>
 __device__ __forceinline__ void cell_channels(const T* U, const T* G, T gamma, T* q, T (*gq)[D]) {
@@ -150,7 +156,7 @@ __device__ void cell_features_from(const KArgs<T>& a, int dcs, int64_t c, const 
         // ratio is then 0 (as in exact arithmetic, where Delta = 0 gives 0)
         const T den = delta * delta + eps * eps;
         T r = den > T(0) ? fdiv(sd * delta, den) : T(0);
-        r = r < T(-2) ? T(-2) : (r > T(2) ? T(2) : r);
+        r = clampv(r, T(-2), T(2));
         mx_g0[k] = fmax(mx_g0[k], fabs(g0));
         mx_dl[k] = fmax(mx_dl[k], fabs(delta));
         mx_b[k] = fmax(mx_b[k], beta);
@@ -165,10 +171,7 @@ __device__ void cell_features_from(const KArgs<T>& a, int dcs, int64_t c, const 
   for (int k = 0; k < 4; ++k) {
     const T rs = fdiv(T(1), fabs(qc[k]) + sm_dl[k] * inv + T(1e-8));
     T f[6] = {mx_g0[k] * rs, mx_dl[k] * rs, mx_b[k], sm_b[k] * inv, mn_r[k], mx_sd[k] * rs};
-    for (int j = 0; j < 6; ++j) {
-      T v = f[j] < T(-8) ? T(-8) : (f[j] > T(8) ? T(8) : f[j]);
-      feat[6 * k + j] = (float)v;
-    }
+    for (int j = 0; j < 6; ++j) feat[6 * k + j] = (float)clampv(f[j], T(-8), T(8));
   }
 }
 
@@ -312,7 +315,7 @@ __device__ __forceinline__ float mlp_tile_fwd(const MlpVec<P>& m, const MlpRegs&
   part += __shfl_xor(part, 32, 64);
   const float z3 = part + m.b3;
   *z3out = z3;
-  return __builtin_amdgcn_rcpf(1.f + __expf(-z3));
+  return __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(z3 * -1.4426950408889634f));
 }
 
 __global__ __launch_bounds__(256) void k_mlp_fwd(MlpDev m, const unsigned short* __restrict__ X, int64_t n,
