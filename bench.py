@@ -324,6 +324,67 @@ def shocks_line(args):
     return out
 
 
+def blast_line(args):
+    """The spherical blast of the shock workload (rho 1 at rest, p 10 inside
+    r < 0.2 about the centre, 0.1 outside) on 60^3 jittered hexes with 30 %
+    split (about 0.41M cells), USR3 + Rusanov to t = 0.05 (time step on the
+    cell geometry): the FP32 path with the learned blend against the FP64
+    classical-sensor run and the FP64 run limited everywhere, each against a
+    fine 1-D radial solution (4000 shells; the flow stays spherical inside the
+    unit cube until t = 0.05).  On 100^3 every path, the one limited
+    everywhere included, drives the pressure of a sliver cell next to the
+    initial sphere to zero within a few steps (the limited face values are not
+    positivity-preserving), so the line stops at 60^3."""
+    import numpy as np
+    import torch
+    from paper_2404_08952_amd import Solver
+    from synth import configs, fields
+    t0 = time.time()
+    case = configs.shocks_3d(n=60, problem="blast")
+    t_end = case.dt * case.steps
+    case.dt, case.steps = geometric_dt(case, 0.2, "euler", t_end=t_end)
+    t_end = case.dt * case.steps
+    r = np.linalg.norm(fields.cell_points(case.mesh) - 0.5, axis=1)
+    rho_ref = fields.blast_reference(t_end, n=4000)(r)[0]
+    log(f"[bench] blast {case.mesh.n_cells:,} cells: set-up and radial reference {time.time() - t0:.1f} s")
+    out = dict(workload=f"spherical blast, {case.mesh.n_cells:,} mixed cells (60^3 hexes, 30 % split), USR3, "
+                        f"Rusanov, {case.steps} steps to t = {t_end:.3f}; reference: 1-D radial Euler, 4000 shells")
+    rho = {}
+    for label, prec, blend in (("fp64_limited", "fp64", "theta"), ("fp64_classical", "fp64", "classical"),
+                               ("fp32_learned", "fp32", "learned")):
+        s = Solver(case.mesh, **case.params, precision=prec, blend=blend)
+        if blend == "learned":
+            s.mlp_set(indicator_weights())
+        if blend == "theta":
+            s.set_theta(torch.zeros(case.mesh.n_cells, dtype=torch.float32, device=s.device))
+        U = s.to_internal(case.U0)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s.advance(U, case.dt, case.steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / case.steps
+        d = s.diagnostics(U)
+        frac = 1.0
+        if blend != "theta":
+            th = (s.mlp_forward(s.features(U, fp32=False)[1]) if blend == "learned" else s.classical_theta(U))
+            frac = float((th[:case.mesh.n_cells] < 0.5).double().mean())
+        u = s.to_external(U)
+        V = s.geometry()["V"].cpu().numpy()[s.perm]
+        s.close()
+        rr = u[:, 0].astype(np.float64)
+        rho[label] = (rr, V)
+        l1 = float(np.sum(V * np.abs(rr - rho_ref)) / V.sum())
+        out[label] = dict(ms_per_step=ms, rho_l1_vs_radial=l1, frac_theta_below_half=frac,
+                          min_rho=float(d[5]), min_p=float(d[6]), nonfinite=int(d[-1]))
+        log(f"[bench] blast {label}: {ms:.3f} ms/step, rho L1 {l1:.4e}, theta < 0.5 in {100 * frac:.0f} % of cells")
+    r64, V = rho["fp64_classical"]
+    out["learned_vs_fp64_classical_l1"] = float(np.sum(V * np.abs(rho["fp32_learned"][0] - r64)) / V.sum())
+    return out
+
+
 def geometric_dt(case, cfl, pde, t_end=None):
     """CFL time step on the cells' own geometry, dt = cfl min_c 2 V_c /
     (lambda sum_f |S_f|) (h / dim on a square or cube); with t_end, the
@@ -555,7 +616,7 @@ def main():
     ap.add_argument("--ke-only", action="store_true", help="only the Taylor-Green kinetic-energy comparison")
     ap.add_argument("--vortex-only", action="store_true", help="only the isentropic-vortex line")
     ap.add_argument("--burgers-only", action="store_true", help="only the 2-D Burgers refinement sweep")
-    ap.add_argument("--shocks-only", action="store_true", help="only the shock-slab line")
+    ap.add_argument("--shocks-only", action="store_true", help="only the shock-slab and spherical-blast lines")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the FP32 / FP64 headline paths (for profiler runs: per-kernel averages of one mesh)")
     args = ap.parse_args()
@@ -584,7 +645,7 @@ def main():
         print(json.dumps(burgers_sweep_line(args)))
         return
     if args.shocks_only:
-        print(json.dumps(shocks_line(args)))
+        print(json.dumps(dict(shock_slab=shocks_line(args), spherical_blast=blast_line(args))))
         return
     dev = torch.cuda.get_device_name(0)
     t0 = time.time()
@@ -624,6 +685,7 @@ def main():
     vtx = vortex_line(args) if extras else None
     brg = burgers_sweep_line(args) if extras else None
     shk = shocks_line(args) if extras else None
+    blast = blast_line(args) if extras else None
     gbps_copy = copy_bandwidth()
     log(f"[bench] streaming y = -x: {gbps_copy:.0f} GB/s")
 
@@ -687,6 +749,7 @@ def main():
         "vortex_closed_form": vtx,
         "burgers_2d_sweep": brg,
         "shock_slab": shk,
+        "spherical_blast": blast,
         "device": dev,
         "copy_gbps": gbps_copy,
     }

@@ -385,3 +385,88 @@ def sod_slab_exact(x, t, gamma=GAMMA):
         out[k][right] = r[k]
         out[k][~right] = -q[k] if k == 1 else q[k]
     return tuple(out)
+
+
+# --------------------------------------------------------------------------
+# reference solution of the spherical blast: 1-D radial Euler on a fine grid
+# --------------------------------------------------------------------------
+
+def radial_euler(init, r_max, n, t_end, alpha=2, gamma=GAMMA, cfl=0.4):
+    """Symmetric Euler flow in r (alpha = 0 planar, 2 spherical) to t_end.
+
+    Finite volumes on n shells of [0, r_max]: MUSCL with minmod slopes of
+    (rho, u, p), HLL flux with Davis speeds, SSP-RK3, time step from the CFL
+    number.  Shell volumes (r+^(a+1) - r-^(a+1)) / (a+1), face areas r^a; the
+    pressure force on the shell's curved sides is p (A+ - A-), so a gas at
+    rest and uniform pressure stays at rest exactly.  Mirror condition at
+    r = 0, zero-gradient state at r_max.  init(r) -> (rho, u, p) at the
+    shell centres.  Returns (centres, rho, u, p)."""
+    h = r_max / n
+    rf = np.arange(n + 1) * h
+    rc = 0.5 * (rf[:-1] + rf[1:])
+    A = rf ** alpha
+    V = (rf[1:] ** (alpha + 1) - rf[:-1] ** (alpha + 1)) / (alpha + 1)
+    dA = A[1:] - A[:-1]
+    rho, u, p = (np.asarray(q, dtype=np.float64).copy() for q in init(rc))
+    U = np.stack([rho, rho * u, p / (gamma - 1.0) + 0.5 * rho * u * u])
+
+    def prim(U):
+        r = U[0]
+        v = U[1] / r
+        return r, v, (gamma - 1.0) * (U[2] - 0.5 * r * v * v)
+
+    def minmod(a, b):
+        return np.where(a * b > 0, np.sign(a) * np.minimum(np.abs(a), np.abs(b)), 0.0)
+
+    def rhs(U):
+        r, v, pr = prim(U)
+        W = np.stack([r, v, pr])
+        # two ghost shells each side: mirror at r = 0, copies at r_max
+        Wg = np.concatenate([W[:, 1::-1], W, W[:, -1:], W[:, -1:]], axis=1)
+        Wg[1, :2] *= -1.0
+        s = minmod(Wg[:, 1:-1] - Wg[:, :-2], Wg[:, 2:] - Wg[:, 1:-1])   # slopes of shells -1 .. n
+        WL = Wg[:, 1:-2] + 0.5 * s[:, :-1]                              # faces 0 .. n
+        WR = Wg[:, 2:-1] - 0.5 * s[:, 1:]
+
+        def flux(W):
+            r, v, pr = W
+            E = pr / (gamma - 1.0) + 0.5 * r * v * v
+            return np.stack([r * v, r * v * v + pr, (E + pr) * v]), np.stack([r, r * v, E])
+
+        FL, UL = flux(WL)
+        FR, UR = flux(WR)
+        cL = np.sqrt(gamma * WL[2] / WL[0])
+        cR = np.sqrt(gamma * WR[2] / WR[0])
+        sL = np.minimum(WL[1] - cL, WR[1] - cR)
+        sR = np.maximum(WL[1] + cL, WR[1] + cR)
+        Fh = (sR * FL - sL * FR + sL * sR * (UR - UL)) / (sR - sL)
+        F = np.where(sL >= 0, FL, np.where(sR <= 0, FR, Fh))
+        R = -(A[1:] * F[:, 1:] - A[:-1] * F[:, :-1]) / V
+        R[1] += pr * dA / V
+        return R, float(np.max(np.abs(v) + np.sqrt(gamma * pr / r)))
+
+    t = 0.0
+    while t < t_end:
+        R1, smax = rhs(U)
+        dt = min(cfl * h / smax, t_end - t)
+        U1 = U + dt * R1
+        U2 = 0.75 * U + 0.25 * (U1 + dt * rhs(U1)[0])
+        U = U / 3.0 + 2.0 / 3.0 * (U2 + dt * rhs(U2)[0])
+        t += dt
+    r, v, pr = prim(U)
+    return rc, r, v, pr
+
+
+def blast_reference(t, n=8000, r_max=0.5, gamma=GAMMA, radius=0.2):
+    """Radial profile of the spherical blast (rho 1 at rest, p 10 inside
+    radius, 0.1 outside) at time t, valid in the sphere r < r_max while its
+    outgoing shock stays inside (t <= 0.05: the shock is near r = 0.3).
+    Returns a function of r -> (rho, u, p) by linear interpolation."""
+    def init(r):
+        return np.ones_like(r), np.zeros_like(r), np.where(r < radius, 10.0, 0.1)
+    rc, rho, u, p = radial_euler(init, r_max, n, t, alpha=2, gamma=gamma)
+
+    def at(r):
+        r = np.asarray(r, dtype=np.float64)
+        return tuple(np.interp(r, rc, q) for q in (rho, u, p))
+    return at
