@@ -84,6 +84,7 @@ void free_work(dolinc_ctx c) {
   Work& w = c->w;
   dfree(w.sw); dfree(w.ell_sw); dfree(w.ell_d); dfree(w.dc); dfree(w.rV); dfree(w.G1); dfree(w.Hf); dfree(w.W1); dfree(w.W2);
   dfree_t(w.theta);
+  dfree_t(w.Xf);
   w.scheme = w.precision = -1;
   w.nv = 0;
 }
@@ -208,16 +209,24 @@ hipError_t prepare_stage(dolinc_ctx c, const void* U, hipStream_t s) {
   const int ord = scheme_order(c->params.scheme);
   const bool bl = c->params.blend != DOLINC_BLEND_NONE;
   if (c->params.blend == DOLINC_BLEND_LEARNED && c->dim == 3) {
-    // first gradient fused with the indicator (timed as the indicator)
+    // first gradient fused with the indicator's features (timed as the
+    // indicator); the network then runs on the context's second stream
+    // while the second derivatives run on the caller's, which waits for it
+    // before the blend weights of the auxiliary cells and the flux kernel
     {
       TimedLaunch t(c, s, 2);
-      hipError_t e = grad_indicator_launch(c, U, c->w.G1, c->w.theta, s);
+      hipError_t e = grad_features_launch(c, U, c->w.G1, c->w.Xf, s);
       if (e != hipSuccess) return e;
     }
-    hipError_t e = launch_ghost(c, GHOST_G1, c->w.G1, s);
+    hipError_t e = hipEventRecord(c->ev_fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->s_net, c->ev_fork, 0);
+    if (e == hipSuccess) e = mlp_forward_launch(c, c->w.Xf, c->n_interior, c->w.theta, c->s_net, DOLINC_N_FEATURES);
+    if (e == hipSuccess) e = hipEventRecord(c->ev_join, c->s_net);
+    if (e == hipSuccess) e = launch_ghost(c, GHOST_G1, c->w.G1, s);
+    if (e == hipSuccess && ord >= 2) e = hface_launch(c, c->w.G1, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, c->ev_join, 0);
     if (e == hipSuccess) e = launch_ghost(c, GHOST_THETA, c->w.theta, s);
-    if (e != hipSuccess || ord < 2) return e;
-    return hface_launch(c, c->w.G1, s);
+    return e;
   }
   if (ord >= 1 || bl) {
     hipError_t e = grad_dispatch(c, U, c->w.G1, nullptr, s);
@@ -543,6 +552,7 @@ dolinc_status dolinc_precompute(dolinc_ctx c, const dolinc_params* p, dolinc_str
   if ((size_t)c->max_entries * nv * el > 65536)
     return fail(DOLINC_EUNSUPPORTED, "partition face fluxes exceed 64 KiB of LDS; use a smaller part_cells");
   if (c->w.precision != p->precision || c->w.scheme != p->scheme || c->w.nv != nv || c->w.blend != p->blend) {
+    if (c->s_net) HIPCHK(hipStreamSynchronize(c->s_net));  // the network may still read the old buffers
     free_work(c);
     const size_t nc = (size_t)c->n_cells, ne = (size_t)c->n_entries;
     hipError_t e = hipSuccess;
@@ -559,6 +569,7 @@ dolinc_status dolinc_precompute(dolinc_ctx c, const dolinc_params* p, dolinc_str
     al(&c->w.W1, nc * nv * el);
     al(&c->w.W2, nc * nv * el);
     if (bl) al((void**)&c->w.theta, nc * sizeof(float));
+    if (p->blend == DOLINC_BLEND_LEARNED && c->dim == 3) al((void**)&c->w.Xf, nc * DOLINC_N_FEATURES * sizeof(unsigned short));
     if (e != hipSuccess) {
       free_work(c);
       return fail(DOLINC_ENOMEM, std::string("workspace allocation failed: ") + hipGetErrorString(e));
@@ -568,6 +579,14 @@ dolinc_status dolinc_precompute(dolinc_ctx c, const dolinc_params* p, dolinc_str
     c->w.nv = nv;
     c->w.blend = p->blend;
     c->w.elem = el;
+  }
+  if (p->blend == DOLINC_BLEND_LEARNED && c->dim == 3 && !c->s_net) {
+    // the network's stream and the two events that fork it from, and join
+    // it back to, the caller's stream in every stage
+    hipError_t e = hipStreamCreateWithFlags(&c->s_net, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
+    if (e != hipSuccess) return fail(DOLINC_EHIP, std::string("stream set-up failed: ") + hipGetErrorString(e));
   }
   c->params = *p;
   HIPCHK(launch_entry_fill(c, s));
@@ -767,7 +786,7 @@ dolinc_status dolinc_mlp_forward(dolinc_ctx c, const uint16_t* X, int64_t n, flo
   if (!X || !theta) return fail(DOLINC_EINVAL, "NULL argument");
   if (n < 0) return fail(DOLINC_EINVAL, "n must be >= 0");
   if (n == 0) return DOLINC_OK;
-  HIPCHK(mlp_forward_launch(c, (const unsigned short*)X, n, theta, (hipStream_t)stream));
+  HIPCHK(mlp_forward_launch(c, (const unsigned short*)X, n, theta, (hipStream_t)stream, DOLINC_FEATURE_STRIDE));
   return DOLINC_OK;
 }
 
@@ -829,8 +848,12 @@ void dolinc_destroy(dolinc_ctx c) {
     std::lock_guard<std::mutex> lk(g_live_mu);
     if (!c || !g_live.erase((const void*)c)) return;
   }
+  if (c->s_net) (void)hipStreamSynchronize(c->s_net);
   free_all(c);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+  if (c->s_net) (void)hipStreamDestroy(c->s_net);
   delete c;
 }
 

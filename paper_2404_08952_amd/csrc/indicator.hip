@@ -1,9 +1,12 @@
 // Launchers of the learned-indicator kernels (features, MLP forward,
-// gradients, Adam) and the fused per-stage indicator.
+// gradients, Adam) and of the per-stage gradient + features kernel.
 #include "dispatch_impl.hpp"
 #include "indicator_impl.hpp"
 
 namespace dolinc {
+
+static_assert(MLP_IN == DOLINC_N_FEATURES && MLP_INP == DOLINC_FEATURE_STRIDE && MLP_NPARAM == DOLINC_MLP_PARAMS,
+              "network sizes of the kernels and of the C interface differ");
 
 hipError_t features_launch(dolinc_ctx_s* c, const void* U, float* X32, unsigned short* Xb, hipStream_t s) {
   const int dcs = dc_stride(c->params.scheme, c->w.precision);
@@ -42,19 +45,18 @@ hipError_t indicator_launch(dolinc_ctx_s* c, const void* U, float* theta, hipStr
   return hipGetLastError();
 }
 
-hipError_t grad_indicator_launch(dolinc_ctx_s* c, const void* U, void* G1, float* theta, hipStream_t s) {
+hipError_t grad_features_launch(dolinc_ctx_s* c, const void* U, void* G1, unsigned short* Xf, hipStream_t s) {
   const int dcs = dc_stride(c->params.scheme, c->w.precision);
-  const MlpDev m = mlp_dev(c);
   if (c->w.precision == DOLINC_FP64) {
     KArgs<double> a = base_args<double>(c);
     a.U = (const double*)U;
-    hipLaunchKernelGGL((k_grad_indicator<double, 3>), dim3(8 * a.cell_per_xcd), dim3(KTPB), 0, s, a, dcs, m,
-                       (double*)G1, theta);
+    hipLaunchKernelGGL((k_grad_features<double, 3>), dim3(8 * a.cell_per_xcd), dim3(KTPB), 0, s, a, dcs,
+                       (double*)G1, Xf);
   } else {
     KArgs<float> a = base_args<float>(c);
     a.U = (const float*)U;
-    hipLaunchKernelGGL((k_grad_indicator<float, 3>), dim3(8 * a.cell_per_xcd), dim3(KTPB), 0, s, a, dcs, m,
-                       (float*)G1, theta);
+    hipLaunchKernelGGL((k_grad_features<float, 3>), dim3(8 * a.cell_per_xcd), dim3(KTPB), 0, s, a, dcs,
+                       (float*)G1, Xf);
   }
   return hipGetLastError();
 }
@@ -65,12 +67,13 @@ hipError_t mlp_pack_launch(dolinc_ctx_s* c, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t mlp_forward_launch(dolinc_ctx_s* c, const unsigned short* X, int64_t n, float* theta, hipStream_t s) {
+hipError_t mlp_forward_launch(dolinc_ctx_s* c, const unsigned short* X, int64_t n, float* theta, hipStream_t s,
+                              int xstride) {
   const int64_t tiles = (n + 15) / 16;
   int64_t blocks = (tiles + 3) / 4;
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_mlp_fwd, dim3((unsigned)blocks), dim3(256), 0, s, mlp_dev(c), X, n, theta);
+  hipLaunchKernelGGL(k_mlp_fwd, dim3((unsigned)blocks), dim3(256), 0, s, mlp_dev(c), X, n, theta, xstride);
   return hipGetLastError();
 }
 

@@ -283,8 +283,10 @@ __device__ __forceinline__ float mlp_tile_fwd(const MlpVec<P>& m, const MlpRegs&
   const int l = threadIdx.x & 63;
   const int r = l & 15, g = l >> 4;
   v4s xb[2];
+  // K columns 24..31 (lanes g = 2, 3 of the second K block) are the zero
+  // padding of W1: they are not read, so rows may be packed 24 wide
   for (int kk = 0; kk < 2; ++kk) {
-    if (r < nrow)
+    if (r < nrow && 16 * kk + 4 * g < MLP_IN)
       xb[kk] = load4(X + r * xstride + 16 * kk + 4 * g);
     else
       xb[kk] = v4s{0, 0, 0, 0};
@@ -319,7 +321,7 @@ __device__ __forceinline__ float mlp_tile_fwd(const MlpVec<P>& m, const MlpRegs&
 }
 
 __global__ __launch_bounds__(256) void k_mlp_fwd(MlpDev m, const unsigned short* __restrict__ X, int64_t n,
-                                                 float* __restrict__ theta) {
+                                                 float* __restrict__ theta, int xstride) {
   MlpRegs R;
   load_weights(m, R);
   const auto mv = mlp_vec(m);
@@ -332,7 +334,7 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(MlpDev m, const unsigned short*
     const int nrow = (int)((n - row0) < 16 ? (n - row0) : 16);
     v4f H1[4], H2[4];
     float z3;
-    const float th = mlp_tile_fwd(mv, R, X + row0 * MLP_INP, nrow, H1, H2, &z3);
+    const float th = mlp_tile_fwd(mv, R, X + row0 * xstride, nrow, H1, H2, &z3, xstride);
     if (l < nrow) theta[row0 + l] = th;
   }
 }
@@ -572,16 +574,15 @@ __global__ __launch_bounds__(KTPB) void k_indicator(KArgs<T> a, int dcs, MlpDev 
   }
 }
 
-// First gradient fused with the learned indicator: the cell's Gauss-linear
-// gradient is stored and, still in registers, feeds the features; the
-// network then runs on the block's cells from LDS.  Same arithmetic as
-// k_grad + k_features + k_mlp_fwd, so theta is identical.
+// First gradient and the indicator's features of a stage: the cell's
+// Gauss-linear gradient is stored and, still in registers, feeds the 24
+// features, written as bf16 rows 24 wide (48 bytes, coalesced) for the
+// network's forward kernel.  Same arithmetic as k_grad + k_features.
 template <class T, int D>
-__global__ __launch_bounds__(KTPB) void k_grad_indicator(KArgs<T> a, int dcs, MlpDev m, T* __restrict__ G1out,
-                                                          float* __restrict__ theta) {
+__global__ __launch_bounds__(KTPB) void k_grad_features(KArgs<T> a, int dcs, T* __restrict__ G1out,
+                                                         unsigned short* __restrict__ Xf) {
   constexpr int NV = D + 2;
-  constexpr int XS = MLP_INP + 2;  // padded row stride (shorts) against LDS bank conflicts
-  __shared__ unsigned short xs[KTPB * XS];
+  static_assert(MLP_IN % 8 == 0, "feature rows are stored in 16-byte pieces");
   __shared__ T ul[KTPB * NV];
   __shared__ T g1buf[KTPB * NV * D];
   const int b = xcd_remap(blockIdx.x, a.cell_per_xcd, a.n_cell_blocks);
@@ -591,7 +592,6 @@ __global__ __launch_bounds__(KTPB) void k_grad_indicator(KArgs<T> a, int dcs, Ml
   stage_rows(ul, a.U, c0, ncl, NV);
   __syncthreads();
   const int64_t c = c0 + threadIdx.x;
-  unsigned short* row = xs + threadIdx.x * XS;
   T g[NV * D];
   if (c < a.nc) {
     T acc[NV][D];
@@ -601,30 +601,12 @@ __global__ __launch_bounds__(KTPB) void k_grad_indicator(KArgs<T> a, int dcs, Ml
       for (int x = 0; x < D; ++x) g[k * D + x] = acc[k][x] * rv;
     float f[MLP_IN];
     cell_features_from<T, D>(a, dcs, c, g, f, ul, c0, ncl);
-    for (int j = 0; j < MLP_IN; ++j) row[j] = f2bf(f[j]);
-  } else {
-    for (int j = 0; j < MLP_IN; ++j) row[j] = 0;
+    unsigned int w[MLP_IN / 2];
+    for (int j = 0; j < MLP_IN / 2; ++j) w[j] = (unsigned)f2bf(f[2 * j]) | ((unsigned)f2bf(f[2 * j + 1]) << 16);
+    uint4* dst = reinterpret_cast<uint4*>(Xf + c * MLP_IN);
+    for (int q = 0; q < MLP_IN / 8; ++q) dst[q] = uint4{w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]};
   }
-  for (int j = MLP_IN; j < MLP_INP; ++j) row[j] = 0;
-  store_rows_coalesced<T, NV * D>(G1out, c0, ncl, g, g1buf);  // also orders the xs writes
-  static_assert(sizeof(MlpLds) <= sizeof(g1buf), "network parameters must fit the G1 staging buffer");
-  MlpLds* ml = reinterpret_cast<MlpLds*>(g1buf);
-  __syncthreads();  // the G1 rows have left g1buf
-  mlp_to_lds(m, ml);
-  __syncthreads();
-  MlpRegs R;
-  load_weights_lds(ml, R);
-  const auto mv = mlp_vec(ml);
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  for (int t = 0; t < 4; ++t) {
-    const int64_t row0 = c0 + 64 * w + 16 * t;
-    if (row0 >= a.nc) break;
-    const int nrow = (int)((a.nc - row0) < 16 ? (a.nc - row0) : 16);
-    v4f H1[4], H2[4];
-    float z3;
-    const float th = mlp_tile_fwd(mv, R, xs + (64 * w + 16 * t) * XS, nrow, H1, H2, &z3, XS);
-    if (l < nrow) theta[row0 + l] = th;
-  }
+  store_rows_coalesced<T, NV * D>(G1out, c0, ncl, g, g1buf);
 }
 
 }  // namespace dolinc

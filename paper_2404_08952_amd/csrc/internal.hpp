@@ -108,6 +108,7 @@ struct Work {
   void* W1 = nullptr;
   void* W2 = nullptr;
   float* theta = nullptr;
+  unsigned short* Xf = nullptr;  // learned blend: the stage's bf16 features [n_cells][24]
   double* diag = nullptr;  // partial sums for diagnostics
   int* flag = nullptr;     // device error flag
   size_t elem = 0;         // sizeof working type
@@ -130,6 +131,10 @@ struct dolinc_ctx_s {
   dolinc_params params{};
   bool geometry_done = false;
   bool precomputed = false;
+  // learned blend: the network runs on a second stream of the context
+  // (default priority) while the second derivatives run on the caller's
+  hipStream_t s_net = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // kernel timing (dolinc_timing)
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
@@ -158,9 +163,11 @@ hipError_t launch_diagnostics(dolinc_ctx_s* c, const void* U, double* out_host, 
 bool flux_supported(const dolinc_params& p, int dim);
 hipError_t features_launch(dolinc_ctx_s* c, const void* U, float* X32, unsigned short* Xb, hipStream_t s);
 hipError_t indicator_launch(dolinc_ctx_s* c, const void* U, float* theta, hipStream_t s);
-hipError_t grad_indicator_launch(dolinc_ctx_s* c, const void* U, void* G1, float* theta, hipStream_t s);
 hipError_t mlp_pack_launch(dolinc_ctx_s* c, hipStream_t s);
-hipError_t mlp_forward_launch(dolinc_ctx_s* c, const unsigned short* X, int64_t n, float* theta, hipStream_t s);
+hipError_t grad_features_launch(dolinc_ctx_s* c, const void* U, void* G1, unsigned short* Xf, hipStream_t s);
+// X rows xstride bf16 wide (24: packed stage features, 32: the API's rows)
+hipError_t mlp_forward_launch(dolinc_ctx_s* c, const unsigned short* X, int64_t n, float* theta, hipStream_t s,
+                              int xstride);
 hipError_t mlp_grad_launch(dolinc_ctx_s* c, const unsigned short* X, const float* y, int64_t n, int nblocks,
                            int rows_per_block, float* grad_out, float* loss_out, int do_step, float lr, float c1,
                            float c2, hipStream_t s);
