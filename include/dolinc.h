@@ -31,6 +31,13 @@
  *     enqueued; on error nothing is enqueued.
  *   - One context may be used by one host thread / one stream at a time.
  *     Calls on one context that overlap on different streams race.
+ *   - With DOLINC_BLEND_LEARNED in 3-D, each stage of dolinc_residual /
+ *     dolinc_rk_step / dolinc_advance runs the network on a second stream
+ *     that the context owns (created by dolinc_precompute, default
+ *     priority), forked from the given stream by an event after the
+ *     features and joined back before the flux: all of a call's work is
+ *     still ordered on the given stream, so synchronising or recording an
+ *     event on it covers the network too.
  */
 #ifndef DOLINC_H
 #define DOLINC_H

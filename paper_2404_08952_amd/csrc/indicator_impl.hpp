@@ -577,7 +577,9 @@ __global__ __launch_bounds__(KTPB) void k_indicator(KArgs<T> a, int dcs, MlpDev 
 // First gradient and the indicator's features of a stage: the cell's
 // Gauss-linear gradient is stored and, still in registers, feeds the 24
 // features, written as bf16 rows 24 wide (48 bytes, coalesced) for the
-// network's forward kernel.  Same arithmetic as k_grad + k_features.
+// network's forward kernel.  The formulas of k_grad + k_features; compiled
+// apart from them, so in FP32 a few features may round differently (FP64:
+// the same bf16 rows).
 template <class T, int D>
 __global__ __launch_bounds__(KTPB) void k_grad_features(KArgs<T> a, int dcs, T* __restrict__ G1out,
                                                          unsigned short* __restrict__ Xf) {
