@@ -320,10 +320,81 @@ __device__ __forceinline__ float mlp_tile_fwd(const MlpVec<P>& m, const MlpRegs&
   return __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(z3 * -1.4426950408889634f));
 }
 
+// Inference with the K = 32 bf16 matrix instruction of gfx950
+// (v_mfma_f32_16x16x32_bf16, half as many instructions as K = 16): lane
+// group g = l / 16 holds 8 K slots of each operand.  Layer 1: slots 8g..8g+7
+// are features 8g..8g+7 (g = 3: W1's zero padding, not read).  Layer 2 takes
+// two accumulator tiles t = 2b, 2b + 1 as one K block b: slot 8g + i is
+// hidden unit 32b + 4g + i and slot 8g + 4 + i unit 32b + 16 + 4g + i, the
+// values lane l already holds; W2 is loaded in the same slot order, so the
+// contraction pairs every unit with its own weight whatever order the
+// instruction sums its K slots in.
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ v4f mfma32(v8s a, v8s b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a), __builtin_bit_cast(v8bf, b), c, 0, 0,
+                                                 0);
+}
+
+struct MlpRegs32 {
+  v8s w1[4];     // output tile t: W1 rows 16t + l % 16, columns 8g..8g+7
+  v8s w2[4][2];  // output tile t, K block b
+};
+
+__device__ __forceinline__ v8s load8(const unsigned short* p) {
+  return __builtin_bit_cast(v8s, *reinterpret_cast<const uint4*>(p));
+}
+
+__device__ __forceinline__ void load_weights32(const MlpDev& m, MlpRegs32& R) {
+  const int l = threadIdx.x & 63;
+  const int r = l & 15, g = l >> 4;
+  for (int t = 0; t < 4; ++t) {
+    R.w1[t] = load8(m.w1b + (16 * t + r) * MLP_INP + 8 * g);
+    for (int b = 0; b < 2; ++b) {
+      const unsigned short* w = m.w2b + (16 * t + r) * MLP_H + 32 * b + 4 * g;
+      v8s v;
+      for (int i = 0; i < 4; ++i) {
+        v[i] = (short)w[i];
+        v[4 + i] = (short)w[16 + i];
+      }
+      R.w2[t][b] = v;
+    }
+  }
+}
+
+// theta of the 16 cells whose bf16 features are at X (row stride xstride,
+// a multiple of 8; rows beyond nrow read as zero), for lane l's cell l % 16
+template <class P>
+__device__ __forceinline__ float mlp_tile_fwd32(const MlpVec<P>& m, const MlpRegs32& R, const unsigned short* X,
+                                                int nrow, int xstride) {
+  const int l = threadIdx.x & 63;
+  const int r = l & 15, g = l >> 4;
+  const v8s xb = (r < nrow && 8 * g < MLP_IN) ? load8(X + r * xstride + 8 * g) : v8s{0, 0, 0, 0, 0, 0, 0, 0};
+  v8s h1[2];
+  for (int t = 0; t < 4; ++t) {
+    v4f acc;
+    for (int i = 0; i < 4; ++i) acc[i] = m.b1[16 * t + 4 * g + i];
+    acc = mfma32(R.w1[t], xb, acc);
+    for (int i = 0; i < 4; ++i) h1[t >> 1][4 * (t & 1) + i] = (short)f2bf(fast_tanh(acc[i]));
+  }
+  float part = 0.f;
+  for (int t = 0; t < 4; ++t) {
+    v4f acc;
+    for (int i = 0; i < 4; ++i) acc[i] = m.b2[16 * t + 4 * g + i];
+    for (int b = 0; b < 2; ++b) acc = mfma32(R.w2[t][b], h1[b], acc);
+    for (int i = 0; i < 4; ++i) part += m.w3[16 * t + 4 * g + i] * fast_tanh(acc[i]);
+  }
+  part += __shfl_xor(part, 16, 64);
+  part += __shfl_xor(part, 32, 64);
+  const float z3 = part + m.b3;
+  return __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(z3 * -1.4426950408889634f));
+}
+
 __global__ __launch_bounds__(256) void k_mlp_fwd(MlpDev m, const unsigned short* __restrict__ X, int64_t n,
                                                  float* __restrict__ theta, int xstride) {
-  MlpRegs R;
-  load_weights(m, R);
+  MlpRegs32 R;
+  load_weights32(m, R);
   const auto mv = mlp_vec(m);
   const int l = threadIdx.x & 63;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -332,9 +403,7 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(MlpDev m, const unsigned short*
   for (int64_t t = wave; t < ntile; t += nwaves) {
     const int64_t row0 = t * 16;
     const int nrow = (int)((n - row0) < 16 ? (n - row0) : 16);
-    v4f H1[4], H2[4];
-    float z3;
-    const float th = mlp_tile_fwd(mv, R, X + row0 * xstride, nrow, H1, H2, &z3, xstride);
+    const float th = mlp_tile_fwd32(mv, R, X + row0 * xstride, nrow, xstride);
     if (l < nrow) theta[row0 + l] = th;
   }
 }
