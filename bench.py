@@ -385,6 +385,48 @@ def blast_line(args):
     return out
 
 
+def ordering_line(args):
+    """Cell-ordering ablation on the Taylor-Green workload at 160^3 (4.1M
+    jittered hexes, the input order a seeded shuffle): FP32 USR5 + HLLC +
+    learned-blend SSP-RK3 steps with the library's Hilbert renumbering, with
+    reverse Cuthill-McKee, and with the input order kept; face entries per
+    face (seam duplicates) and ms per step."""
+    import torch
+    from paper_2404_08952_amd import Solver
+    from synth import configs
+    t0 = time.time()
+    case = configs.taylor_green_3d(n=160)
+    nc, nf = case.mesh.n_cells, case.mesh.n_faces
+    log(f"[bench] ordering ablation {nc:,} cells: set-up {time.time() - t0:.1f} s")
+    out = dict(workload=f"Taylor-Green 160^3 ({nc:,} jittered hexes, input order shuffled), USR5, HLLC, learned "
+                        "blend, FP32, SSP-RK3")
+    for label, ren in (("hilbert", 2), ("rcm", 1), ("input_order", 0)):
+        t1 = time.time()
+        s = Solver(case.mesh, **case.params, precision="fp32", blend="learned", u_ref=configs.TGV_REF, renumber=ren)
+        setup = time.time() - t1
+        s.mlp_set(indicator_weights())
+        U = s.to_internal(case.U0)
+        s.rk_step(U, case.dt)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        steps = 3
+        e0.record()
+        for _ in range(steps):
+            s.rk_step(U, case.dt)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        st = s.stats()
+        s.close()
+        out[label] = dict(ms_per_step=ms, value=nc * 3 / (ms * 1e-3), unit="cell-updates/s",
+                          entries_per_face=st["n_entries"] / nf, partitions=st["n_parts"],
+                          max_partition_entries=st["max_entries"], create_s=setup)
+        log(f"[bench] ordering {label}: {ms:.3f} ms/step, {st['n_entries'] / nf:.3f} entries per face, "
+            f"create {setup:.1f} s")
+    return out
+
+
 def geometric_dt(case, cfl, pde, t_end=None):
     """CFL time step on the cells' own geometry, dt = cfl min_c 2 V_c /
     (lambda sum_f |S_f|) (h / dim on a square or cube); with t_end, the
@@ -618,6 +660,7 @@ def main():
     ap.add_argument("--vortex-only", action="store_true", help="only the isentropic-vortex line")
     ap.add_argument("--burgers-only", action="store_true", help="only the 2-D Burgers refinement sweep")
     ap.add_argument("--shocks-only", action="store_true", help="only the shock-slab and spherical-blast lines")
+    ap.add_argument("--ordering-only", action="store_true", help="only the cell-ordering ablation")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the FP32 / FP64 headline paths (for profiler runs: per-kernel averages of one mesh)")
     args = ap.parse_args()
@@ -644,6 +687,9 @@ def main():
         return
     if args.burgers_only:
         print(json.dumps(burgers_sweep_line(args)))
+        return
+    if args.ordering_only:
+        print(json.dumps(ordering_line(args)))
         return
     if args.shocks_only:
         print(json.dumps(dict(shock_slab=shocks_line(args), spherical_blast=blast_line(args))))
@@ -687,6 +733,7 @@ def main():
     brg = burgers_sweep_line(args) if extras else None
     shk = shocks_line(args) if extras else None
     blast = blast_line(args) if extras else None
+    order = ordering_line(args) if extras else None
     gbps_copy = copy_bandwidth()
     log(f"[bench] streaming y = -x: {gbps_copy:.0f} GB/s")
 
@@ -752,6 +799,7 @@ def main():
         "burgers_2d_sweep": brg,
         "shock_slab": shk,
         "spherical_blast": blast,
+        "cell_ordering": order,
         "device": dev,
         "copy_gbps": gbps_copy,
     }
