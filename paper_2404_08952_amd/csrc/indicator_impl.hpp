@@ -223,44 +223,8 @@ __device__ __forceinline__ void load_weights(const MlpDev& m, MlpRegs& R) {
   }
 }
 
-// The network's parameters copied into LDS once per workgroup (bf16 weights
-// as 32-bit words), so the waves of a block read them from LDS instead of
-// each fetching 12 KiB through the vector memory path.
-struct MlpLds {
-  unsigned int w1[MLP_H * MLP_INP / 2];
-  unsigned int w2[MLP_H * MLP_H / 2];
-  float b1[MLP_H], b2[MLP_H], w3[MLP_H], b3[4];
-};
-
-__device__ __forceinline__ void mlp_to_lds(const MlpDev& m, MlpLds* L) {
-  const unsigned int* w1 = reinterpret_cast<const unsigned int*>(m.w1b);
-  const unsigned int* w2 = reinterpret_cast<const unsigned int*>(m.w2b);
-  for (int i = threadIdx.x; i < MLP_H * MLP_INP / 2; i += blockDim.x) L->w1[i] = w1[i];
-  for (int i = threadIdx.x; i < MLP_H * MLP_H / 2; i += blockDim.x) L->w2[i] = w2[i];
-  for (int i = threadIdx.x; i < MLP_H; i += blockDim.x) {
-    L->b1[i] = m.p[OFF_B1 + i];
-    L->b2[i] = m.p[OFF_B2 + i];
-    L->w3[i] = m.p[OFF_W3 + i];
-  }
-  if (threadIdx.x == 0) L->b3[0] = m.p[OFF_B3];
-}
-
-__device__ __forceinline__ v4s lds4(LdsPtr<unsigned int> p) {
-  const unsigned int a = p[0], b = p[1];
-  return v4s{(short)(a & 0xffffu), (short)(a >> 16), (short)(b & 0xffffu), (short)(b >> 16)};
-}
-
-__device__ __forceinline__ void load_weights_lds(const MlpLds* L, MlpRegs& R) {
-  const int l = threadIdx.x & 63;
-  const int r = l & 15, g = l >> 4;
-  for (int t = 0; t < 4; ++t) {
-    for (int kk = 0; kk < 2; ++kk) R.w1[t][kk] = lds4(as_lds(L->w1 + ((16 * t + r) * MLP_INP + 16 * kk + 4 * g) / 2));
-    for (int kk = 0; kk < 4; ++kk) R.w2[t][kk] = lds4(as_lds(L->w2 + ((16 * t + r) * MLP_H + 16 * kk + 4 * g) / 2));
-  }
-}
-
-// Biases and output weights of the network, from HBM (P = const float*)
-// or from LDS (P = LdsPtr<float>).
+// Biases and output weights of the network (P: pointer type they are read
+// through).
 template <class P>
 struct MlpVec {
   P b1, b2, w3;
@@ -269,9 +233,6 @@ struct MlpVec {
 
 __device__ __forceinline__ MlpVec<const float*> mlp_vec(const MlpDev& m) {
   return {m.p + OFF_B1, m.p + OFF_B2, m.p + OFF_W3, m.p[OFF_B3]};
-}
-__device__ __forceinline__ MlpVec<LdsPtr<float>> mlp_vec(const MlpLds* L) {
-  return {as_lds(L->b1), as_lds(L->b2), as_lds(L->w3), L->b3[0]};
 }
 
 // Forward of 16 cells whose bf16 features are at X (row stride 32; rows
