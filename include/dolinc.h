@@ -247,8 +247,9 @@ dolinc_status dolinc_features(dolinc_ctx ctx, const void* U, float* X32, uint16_
 dolinc_status dolinc_mlp_set(dolinc_ctx ctx, const float* params);
 dolinc_status dolinc_mlp_get(dolinc_ctx ctx, float* params);
 
-/* theta = network(X) for n rows of bf16 features X (device [n][32]);
- * theta device float [n]. */
+/* theta = network(X) for n rows of bf16 features X (device [n][32], 16-byte
+ * aligned: each lane reads 8 features at once; the 8 padding columns are not
+ * read); theta device float [n].  EINVAL for a NULL or misaligned X. */
 dolinc_status dolinc_mlp_forward(dolinc_ctx ctx, const uint16_t* X, int64_t n, float* theta, dolinc_stream s);
 
 /* One Adam step (lr, beta1 0.9, beta2 0.999, eps 1e-8) on the mean binary

@@ -785,6 +785,7 @@ dolinc_status dolinc_mlp_forward(dolinc_ctx c, const uint16_t* X, int64_t n, flo
   if (!c->mlp.p) return fail(DOLINC_ESTATE, "dolinc_mlp_set has not been called");
   if (!X || !theta) return fail(DOLINC_EINVAL, "NULL argument");
   if (n < 0) return fail(DOLINC_EINVAL, "n must be >= 0");
+  if (reinterpret_cast<uintptr_t>(X) % 16 != 0) return fail(DOLINC_EINVAL, "X must be 16-byte aligned");
   if (n == 0) return DOLINC_OK;
   HIPCHK(mlp_forward_launch(c, (const unsigned short*)X, n, theta, (hipStream_t)stream, DOLINC_FEATURE_STRIDE));
   return DOLINC_OK;

@@ -135,3 +135,22 @@ def test_mlp_forward_large_ragged_batch():
     _rl, rg = OI.loss_and_grad(p.astype(np.float64), Xh.astype(np.float64), y.cpu().numpy().astype(np.float64),
                                bf16=True)
     assert np.linalg.norm(g.cpu().numpy() - rg) <= 1e-3 * np.linalg.norm(rg)
+
+
+def test_mlp_forward_rejects_misaligned_rows():
+    """Rows are read 16 bytes at a time: a feature array that does not start
+    on a 16-byte boundary is refused before anything is enqueued."""
+    import torch
+
+    from paper_2404_08952_amd import Solver
+    from paper_2404_08952_amd import binding as B
+    mesh, _geo, _U = _setup()
+    s = Solver(mesh, pde="euler", scheme="USR3", flux="rusanov", blend="learned")
+    s.mlp_set(OI.xavier_init(3).astype(np.float32))
+    buf = torch.zeros(33 * 16, dtype=torch.int16, device="cuda")
+    with pytest.raises(B.DolincError) as e:
+        s.mlp_forward(buf[1:1 + 16 * 32].view(16, 32))
+    assert e.value.status == B.EINVAL
+    th = s.mlp_forward(buf[:16 * 32].view(16, 32))
+    assert torch.isfinite(th).all()
+    s.close()
