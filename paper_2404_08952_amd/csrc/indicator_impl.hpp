@@ -89,6 +89,73 @@ __device__ __forceinline__ void cell_channels(const T* U, const T* G, T gamma, T
   }
 }
 
+// Running statistics of the features over a cell's faces
+template <class T>
+struct FeatAcc {
+  T mx_g0[4], mx_dl[4], mx_b[4], sm_b[4], mn_r[4], mx_sd[4], sm_dl[4];
+  int nface;
+  __device__ __forceinline__ void init() {
+    for (int k = 0; k < 4; ++k) {
+      mx_g0[k] = mx_dl[k] = mx_b[k] = sm_b[k] = mx_sd[k] = sm_dl[k] = T(0);
+      mn_r[k] = T(2);
+    }
+    nface = 0;
+  }
+};
+
+// One face of the cell: dv = sigma d (the cell's upwind frame), Uo the
+// other cell's state, qc / gqc the cell's channels and their gradients.
+template <class T, int D>
+__device__ __forceinline__ void feat_face(const T* dv, const T* Uo, T gamma, const T* qc, const T (*gqc)[D],
+                                          FeatAcc<T>& A) {
+  ++A.nface;
+  // neighbour channel values
+  T qo[4];
+  {
+    const T rho = Uo[0];
+    T ke = T(0), m2 = T(0);
+    for (int x = 0; x < D; ++x) {
+      ke += fdiv(Uo[1 + x] * Uo[1 + x], rho);
+      m2 += Uo[1 + x] * Uo[1 + x];
+    }
+    qo[0] = rho;
+    qo[1] = (gamma - T(1)) * (Uo[D + 1] - T(0.5) * ke);
+    qo[2] = Uo[D + 1];
+    qo[3] = fsqrt(m2);
+  }
+  for (int k = 0; k < 4; ++k) {
+    T g0 = T(0);
+    for (int x = 0; x < D; ++x) g0 += dv[x] * gqc[k][x];
+    g0 *= T(2);
+    const T delta = qo[k] - qc[k];
+    const T sd = g0 - delta;
+    const T eps = T(1e-8) * (fabs(qc[k]) + fabs(qo[k])) + T(1e-30);
+    const T beta = fdiv(fabs(sd - delta), fabs(sd) + fabs(delta) + eps);
+    // eps^2 underflows in FP32 when both channel values are 0; the
+    // ratio is then 0 (as in exact arithmetic, where Delta = 0 gives 0)
+    const T den = delta * delta + eps * eps;
+    T r = den > T(0) ? fdiv(sd * delta, den) : T(0);
+    r = clampv(r, T(-2), T(2));
+    A.mx_g0[k] = fmax(A.mx_g0[k], fabs(g0));
+    A.mx_dl[k] = fmax(A.mx_dl[k], fabs(delta));
+    A.mx_b[k] = fmax(A.mx_b[k], beta);
+    A.sm_b[k] += beta;
+    A.mn_r[k] = fmin(A.mn_r[k], r);
+    A.mx_sd[k] = fmax(A.mx_sd[k], fabs(sd - delta));
+    A.sm_dl[k] += fabs(delta);
+  }
+}
+
+template <class T>
+__device__ __forceinline__ void feat_finish(const T* qc, const FeatAcc<T>& A, float* feat) {
+  const T inv = T(1) / (T)A.nface;
+  for (int k = 0; k < 4; ++k) {
+    const T rs = fdiv(T(1), fabs(qc[k]) + A.sm_dl[k] * inv + T(1e-8));
+    T f[6] = {A.mx_g0[k] * rs, A.mx_dl[k] * rs, A.mx_b[k], A.sm_b[k] * inv, A.mn_r[k], A.mx_sd[k] * rs};
+    for (int j = 0; j < 6; ++j) feat[6 * k + j] = (float)clampv(f[j], T(-8), T(8));
+  }
+}
+
 // Gc: the cell's gradient [NV][D] (from memory or registers)
 template <class T, int D>
 __device__ void cell_features_from(const KArgs<T>& a, int dcs, int64_t c, const T* Gc, float* feat,
@@ -101,15 +168,11 @@ __device__ void cell_features_from(const KArgs<T>& a, int dcs, int64_t c, const 
   T Uc[NV];
   load_row<T, NV>(Uc, Ulds, a.U, c0, n, c);
   cell_channels<T, D>(Uc, Gc, a.gamma, qc, gqc);
-  T mx_g0[4], mx_dl[4], mx_b[4], sm_b[4], mn_r[4], mx_sd[4], sm_dl[4];
-  for (int k = 0; k < 4; ++k) {
-    mx_g0[k] = mx_dl[k] = mx_b[k] = sm_b[k] = mx_sd[k] = sm_dl[k] = T(0);
-    mn_r[k] = T(2);
-  }
+  FeatAcc<T> A;
+  A.init();
   // face records (sliced ELL) in batches of 4, then the batch's neighbour
   // rows; padding records (sigma = 0) are skipped
   constexpr int GB = 4;
-  int nface = 0;
   for (int j = 0; j < m; j += GB) {
     int64_t o[GB];
     T dv[GB][D], sg[GB];
@@ -129,50 +192,10 @@ __device__ void cell_features_from(const KArgs<T>& a, int dcs, int64_t c, const 
 #pragma unroll
     for (int jj = 0; jj < GB; ++jj) {
       if (sg[jj] == T(0)) continue;
-      ++nface;
-      // neighbour channel values
-      T qo[4];
-      {
-        const T rho = Uo[jj][0];
-        T ke = T(0), m2 = T(0);
-        for (int x = 0; x < D; ++x) {
-          ke += fdiv(Uo[jj][1 + x] * Uo[jj][1 + x], rho);
-          m2 += Uo[jj][1 + x] * Uo[jj][1 + x];
-        }
-        qo[0] = rho;
-        qo[1] = (a.gamma - T(1)) * (Uo[jj][D + 1] - T(0.5) * ke);
-        qo[2] = Uo[jj][D + 1];
-        qo[3] = fsqrt(m2);
-      }
-      for (int k = 0; k < 4; ++k) {
-        T g0 = T(0);
-        for (int x = 0; x < D; ++x) g0 += dv[jj][x] * gqc[k][x];
-        g0 *= T(2);
-        const T delta = qo[k] - qc[k];
-        const T sd = g0 - delta;
-        const T eps = T(1e-8) * (fabs(qc[k]) + fabs(qo[k])) + T(1e-30);
-        const T beta = fdiv(fabs(sd - delta), fabs(sd) + fabs(delta) + eps);
-        // eps^2 underflows in FP32 when both channel values are 0; the
-        // ratio is then 0 (as in exact arithmetic, where Delta = 0 gives 0)
-        const T den = delta * delta + eps * eps;
-        T r = den > T(0) ? fdiv(sd * delta, den) : T(0);
-        r = clampv(r, T(-2), T(2));
-        mx_g0[k] = fmax(mx_g0[k], fabs(g0));
-        mx_dl[k] = fmax(mx_dl[k], fabs(delta));
-        mx_b[k] = fmax(mx_b[k], beta);
-        sm_b[k] += beta;
-        mn_r[k] = fmin(mn_r[k], r);
-        mx_sd[k] = fmax(mx_sd[k], fabs(sd - delta));
-        sm_dl[k] += fabs(delta);
-      }
+      feat_face<T, D>(dv[jj], Uo[jj], a.gamma, qc, gqc, A);
     }
   }
-  const T inv = T(1) / (T)nface;
-  for (int k = 0; k < 4; ++k) {
-    const T rs = fdiv(T(1), fabs(qc[k]) + sm_dl[k] * inv + T(1e-8));
-    T f[6] = {mx_g0[k] * rs, mx_dl[k] * rs, mx_b[k], sm_b[k] * inv, mn_r[k], mx_sd[k] * rs};
-    for (int j = 0; j < 6; ++j) feat[6 * k + j] = (float)clampv(f[j], T(-8), T(8));
-  }
+  feat_finish<T>(qc, A, feat);
 }
 
 template <class T, int D>
@@ -626,13 +649,70 @@ __global__ __launch_bounds__(KTPB) void k_grad_features(KArgs<T> a, int dcs, T* 
   const int64_t c = c0 + threadIdx.x;
   T g[NV * D];
   if (c < a.nc) {
-    T acc[NV][D];
-    grad_sums<T, D, NV, 6>(a, a.U, c, acc, ul, c0, ncl);
+    const int r0 = a.ell_ptr[b], m = (a.ell_ptr[b + 1] - r0) / KTPB;  // faces per cell in this block
     const T rv = a.rV[c];
-    for (int k = 0; k < NV; ++k)
-      for (int x = 0; x < D; ++x) g[k * D + x] = acc[k][x] * rv;
     float f[MLP_IN];
-    cell_features_from<T, D>(a, dcs, c, g, f, ul, c0, ncl);
+    constexpr int FB = 6;
+    if (m <= FB) {
+      // one pass: the records (both kinds) and neighbour rows of all the
+      // cell's faces are loaded once and serve the gradient, then the
+      // features; the same operations in the same order as grad_sums and
+      // cell_features_from
+      const int lane = threadIdx.x;
+      T q[NV];
+      load_row<T, NV>(q, ul, a.U, c0, ncl, c);
+      int64_t o[FB];
+      T Sw[FB][D], dv[FB][D], sg[FB];
+#pragma unroll
+      for (int jj = 0; jj < FB; ++jj) {
+        const bool ok = jj < m;
+        const int64_t r = (int64_t)r0 + (int64_t)(ok ? jj : 0) * KTPB + lane;
+        GlbPtr<T> rec = as_glb(a.ell_sw + 4 * r);
+        GlbPtr<T> rd = as_glb(a.ell_d + 4 * r);
+        T v[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) v[x] = rec[x];
+        o[jj] = ok ? rec_cell(v[3]) : c;
+#pragma unroll
+        for (int x = 0; x < D; ++x) {
+          Sw[jj][x] = ok ? v[x] : T(0);
+          dv[jj][x] = rd[x];
+        }
+        sg[jj] = ok ? rd[3] : T(0);
+      }
+      T Uo[FB][NV];
+#pragma unroll
+      for (int jj = 0; jj < FB; ++jj) load_row<T, NV>(Uo[jj], ul, a.U, c0, ncl, o[jj]);
+      T acc[NV][D];
+#pragma unroll
+      for (int k = 0; k < NV; ++k)
+#pragma unroll
+        for (int x = 0; x < D; ++x) acc[k][x] = T(0);
+#pragma unroll
+      for (int jj = 0; jj < FB; ++jj)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+          const T dq = Uo[jj][k] - q[k];
+#pragma unroll
+          for (int x = 0; x < D; ++x) acc[k][x] += dq * Sw[jj][x];
+        }
+      for (int k = 0; k < NV; ++k)
+        for (int x = 0; x < D; ++x) g[k * D + x] = acc[k][x] * rv;
+      T qc[4], gqc[4][D];
+      cell_channels<T, D>(q, g, a.gamma, qc, gqc);
+      FeatAcc<T> A;
+      A.init();
+#pragma unroll
+      for (int jj = 0; jj < FB; ++jj)
+        if (sg[jj] != T(0)) feat_face<T, D>(dv[jj], Uo[jj], a.gamma, qc, gqc, A);
+      feat_finish<T>(qc, A, f);
+    } else {
+      T acc[NV][D];
+      grad_sums<T, D, NV, 6>(a, a.U, c, acc, ul, c0, ncl);
+      for (int k = 0; k < NV; ++k)
+        for (int x = 0; x < D; ++x) g[k * D + x] = acc[k][x] * rv;
+      cell_features_from<T, D>(a, dcs, c, g, f, ul, c0, ncl);
+    }
     unsigned int w[MLP_IN / 2];
     for (int j = 0; j < MLP_IN / 2; ++j) w[j] = (unsigned)f2bf(f[2 * j]) | ((unsigned)f2bf(f[2 * j + 1]) << 16);
     uint4* dst = reinterpret_cast<uint4*>(Xf + c * MLP_IN);
