@@ -322,10 +322,11 @@ def test_full_size_vortex_sampled(precision):
     """The 3-D Euler vortex workload at full size (64^3 x 6 tetrahedra, CSR4,
     Rusanov) in the benchmark's launch configuration: sampled cells against
     the oracle on their neighbourhood, conservation over one step."""
+    from bench import PART_CELLS
     case = configs.vortex_3d(point_ic=True)
     mesh = case.mesh
     extra = dict(u_ref=configs.VORTEX_REF) if precision == "fp32" else {}
-    s = _solver(mesh, **case.params, precision=precision, **extra)
+    s = _solver(mesh, **case.params, precision=precision, part_cells=PART_CELLS[precision], **extra)
     U0 = case.U0.astype(np.float32).astype(np.float64) if precision == "fp32" else case.U0
     Ud = s.to_internal(U0)
     R = s.to_external(s.residual(Ud))
@@ -362,14 +363,14 @@ def test_full_size_taylor_green_sampled():
     mesh = case.mesh
     w = np.load(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
                              "paper_2404_08952_amd", "data", "indicator_weights.npy"))
+    from bench import PART_CELLS
     from oracle import indicator as OI
-    s = _solver(mesh, **case.params, blend="learned", precision="fp64")
     seeds = np.random.default_rng(10).choice(mesh.n_cells, 24, replace=False)
     sub, cells, _f = submesh(mesh, seeds, 5)
     loc = np.searchsorted(cells, seeds)
     for prec in ("fp64", "fp32"):
         extra = dict(u_ref=configs.TGV_REF) if prec == "fp32" else {}
-        s.configure(**case.params, blend="learned", precision=prec, **extra)
+        s = _solver(mesh, **case.params, blend="learned", precision=prec, part_cells=PART_CELLS[prec], **extra)
         s.mlp_set(w)
         U0 = case.U0.astype(np.float32).astype(np.float64) if prec == "fp32" else case.U0
         Ud = s.to_internal(U0)
@@ -393,3 +394,4 @@ def test_full_size_taylor_green_sampled():
             # 2.5e-5 here, the 1e-5 target holds on the coarser workloads
             assert max(errs) <= 5e-5, errs
         del Ud
+        s.close()
