@@ -549,8 +549,16 @@ dolinc_status dolinc_precompute(dolinc_ctx c, const dolinc_params* p, dolinc_str
   const size_t el = p->precision == DOLINC_FP64 ? sizeof(double) : sizeof(float);
   const int ord = scheme_order(p->scheme);
   const bool bl = p->blend != DOLINC_BLEND_NONE;
-  if ((size_t)c->max_entries * nv * el > 65536)
-    return fail(DOLINC_EUNSUPPORTED, "partition face fluxes exceed 64 KiB of LDS; use a smaller part_cells");
+  {
+    // the flux kernel accumulates a partition's face fluxes in LDS
+    int dev = 0, lim = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || lim <= 0)
+      lim = 64 * 1024;
+    if ((size_t)c->max_entries * nv * el > (size_t)lim)
+      return fail(DOLINC_EUNSUPPORTED, "partition face fluxes exceed the LDS of one workgroup (" +
+                                           std::to_string(lim / 1024) + " KiB); use a smaller part_cells");
+  }
   if (c->w.precision != p->precision || c->w.scheme != p->scheme || c->w.nv != nv || c->w.blend != p->blend) {
     if (c->s_net) HIPCHK(hipStreamSynchronize(c->s_net));  // the network may still read the old buffers
     free_work(c);
