@@ -79,3 +79,23 @@ def test_features_uniform_and_linear_fields():
     U2[c0, 4] += 0.0
     F2 = OI.features(mesh, geo, U2, OS.gauss_linear(mesh, geo, U2))
     assert F2[c0, 2] > 0.99
+
+
+def test_ratio_feature_clip():
+    """On a uniform lattice the Gauss gradient is the central difference, so
+    a cell with neighbours a, c along x and value b has, on its +x face,
+    r = s Delta / Delta^2 = (b - a) / (c - b) (s = 2 d.grad - Delta); its
+    -x face gives (b - c) / (a - b) and its y and z faces (Delta = 0) give 0.
+    (a, b, c) = (1.0, 1.1, 1.0 + 0.1 / 3): r = -1.5, the minimum feature.
+    (a, b, c) = (1.0, 1.1, 1.075): r = -4, clipped to -2."""
+    n = 6
+    mesh = M.periodic_3d(n)
+    geo = OG.geometry(mesh)
+    i = np.floor(geo.xc[:, 0] * n + 1e-9).astype(int)
+    for c_val, want in ((1.0 + 0.1 / 3.0, -1.5), (1.075, -2.0)):
+        row = {1: 1.0, 2: 1.1, 3: c_val}
+        rho = np.array([row.get(k, 1.0) for k in i])
+        U = fields.prim_to_cons(rho, np.zeros((mesh.n_cells, 3)), np.full(mesh.n_cells, 1.0))
+        F = OI.features(mesh, geo, U, OS.gauss_linear(mesh, geo, U))
+        sel = i == 2
+        np.testing.assert_allclose(F[sel, 4], want, atol=1e-9)   # min r of the density channel
