@@ -76,7 +76,7 @@ def grad_kernel_bytes(nc, nf, nq, dim, el, out_per_cell):
     return nc * (nq * el + out_per_cell * el + el + 4) + nf * (8 + 4 * el + 4)
 
 
-def time_path(s, case, precision, extra, steps, warmup, params=None):
+def time_path(s, case, precision, extra, steps, warmup, params=None, windows=0, window_steps=34):
     import torch
     t0 = time.time()
     s.configure(**(params or case.params), precision=precision, **extra)
@@ -99,9 +99,22 @@ def time_path(s, case, precision, extra, steps, warmup, params=None):
     torch.cuda.synchronize()
     ms_k, n_k = s.timing(False)
     ms = e0.elapsed_time(e1)
+    # further windows of >= 100 stages without per-kernel events (their
+    # median backs the single timed window above)
+    win = []
+    for _ in range(windows):
+        e0.record(stream)
+        for _ in range(window_steps):
+            s.rk_step(U, case.dt)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        win.append(e0.elapsed_time(e1) / window_steps)
     diag = s.diagnostics(U)
     out = dict(ms_total=ms, ms_per_step=ms / steps, kernel_ms=ms_k.tolist(), kernel_n=n_k.tolist(),
                stats=s.stats(), finite=bool(diag[-1] == 0), min_rho=float(diag[s.nv]), min_p=float(diag[s.nv + 1]))
+    if win:
+        out["windows"] = dict(steps_each=window_steps, stages_each=3 * window_steps, ms_per_step=win,
+                              median_ms_per_step=float(sorted(win)[len(win) // 2]))
     del U
     torch.cuda.empty_cache()
     return out
@@ -719,7 +732,8 @@ def main():
         log(f"[bench] create (renumber, {PART_CELLS[prec]}-cell partitions, upload, FP64 geometry) "
             f"{time.time() - t0:.1f} s")
         ex = dict(extra, **(fp32_extra if prec == "fp32" else {}))
-        res[prec] = time_path(solver, case, prec, ex, args.steps, args.warmup)
+        res[prec] = time_path(solver, case, prec, ex, args.steps, args.warmup,
+                              windows=0 if args.headline_only else 5)
         log(f"[bench] {prec}: {res[prec]['ms_per_step']:.3f} ms/step, kernels ms {res[prec]['kernel_ms']}")
         if prec == "fp32" and extras:
             for sch in ("WENO5", "ENO3", "CSR6"):
@@ -769,7 +783,8 @@ def main():
                     grad_kernel=grad,
                     grad2_kernel_ms=per(1), indicator_kernel_ms=per(2),
                     stage_kernel_ms=sum(per(k) for k in range(4) if r["kernel_n"][k]),
-                    finite=r["finite"], min_rho=r["min_rho"], min_p=r["min_p"], partitions=r["stats"])
+                    finite=r["finite"], min_rho=r["min_rho"], min_p=r["min_p"], partitions=r["stats"],
+                    windows=r.get("windows"))
 
     s32, s64 = summarize("fp32"), summarize("fp64")
     fk = s32["flux_kernel"]
