@@ -238,9 +238,6 @@ hipError_t prepare_stage(dolinc_ctx c, const void* U, hipStream_t s) {
     TimedLaunch t(c, s, 2);
     e = c->w.precision == DOLINC_FP64 ? theta_f64(c, U, c->w.G1, c->w.theta, s)
                                       : theta_f32(c, U, c->w.G1, c->w.theta, s);
-  } else if (c->params.blend == DOLINC_BLEND_LEARNED) {
-    TimedLaunch t(c, s, 2);
-    e = indicator_launch(c, U, c->w.theta, s);
   }
   if (e != hipSuccess || !bl) return e;
   return launch_ghost(c, GHOST_THETA, c->w.theta, s);

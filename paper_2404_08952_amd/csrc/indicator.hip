@@ -30,21 +30,6 @@ static MlpDev mlp_dev(dolinc_ctx_s* c) {
   return m;
 }
 
-hipError_t indicator_launch(dolinc_ctx_s* c, const void* U, float* theta, hipStream_t s) {
-  const int dcs = dc_stride(c->params.scheme, c->w.precision);
-  const MlpDev m = mlp_dev(c);
-  if (c->w.precision == DOLINC_FP64) {
-    KArgs<double> a = base_args<double>(c);
-    a.U = (const double*)U;
-    hipLaunchKernelGGL((k_indicator<double, 3>), dim3(8 * a.cell_per_xcd), dim3(KTPB), 0, s, a, dcs, m, theta);
-  } else {
-    KArgs<float> a = base_args<float>(c);
-    a.U = (const float*)U;
-    hipLaunchKernelGGL((k_indicator<float, 3>), dim3(8 * a.cell_per_xcd), dim3(KTPB), 0, s, a, dcs, m, theta);
-  }
-  return hipGetLastError();
-}
-
 hipError_t grad_features_launch(dolinc_ctx_s* c, const void* U, void* G1, unsigned short* Xf, hipStream_t s) {
   const int dcs = dc_stride(c->params.scheme, c->w.precision);
   if (c->w.precision == DOLINC_FP64) {

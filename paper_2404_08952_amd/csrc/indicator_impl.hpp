@@ -10,11 +10,12 @@
 // each clipped to [-8, 8].  grad p and grad|rho u| by the chain rule.
 //
 // Network: theta = sigmoid(W3 . tanh(W2 tanh(W1 x + b1) + b2) + b3).
-// Matrix-core formulation (v_mfma_f32_16x16x16_bf16, wave64): each wave
-// carries 16 cells as the N dimension of Z^T = W X^T, so the accumulator
-// tile of one layer (lane l holds units 4(l/16)..4(l/16)+3 of cell l%16) is
-// exactly the B operand of the next layer.  bf16 operands (round to nearest
-// even), fp32 accumulation, fp32 biases, last layer on the vector ALU.
+// Matrix-core formulation (wave64): each wave carries 16 cells as the N
+// dimension of Z^T = W X^T, so the accumulator tiles of one layer (lane l
+// holds units 4(l/16)..4(l/16)+3 of cell l%16) are the B operand of the next
+// layer: the forward uses v_mfma_f32_16x16x32_bf16, the backward's products
+// v_mfma_f32_16x16x16_bf16.  bf16 operands (round to nearest even), fp32
+// accumulation, fp32 biases, last layer on the vector ALU.
 #pragma once
 #include "residual_impl.hpp"
 
@@ -221,31 +222,6 @@ __global__ __launch_bounds__(KTPB) void k_features(KArgs<T> a, int dcs, float* _
 }
 
 // ---------------------------------------------------------------- forward
-// Weights in A-operand layout: lane l holds rows (units) 16 t + l % 16,
-// K columns 16 kk + 4 (l / 16) .. + 3.
-struct MlpRegs {
-  v4s w1[4][2];
-  v4s w2[4][4];
-};
-
-__device__ __forceinline__ v4s load4(const unsigned short* p) {
-  v4s r;
-  r.x = (short)p[0];
-  r.y = (short)p[1];
-  r.z = (short)p[2];
-  r.w = (short)p[3];
-  return r;
-}
-
-__device__ __forceinline__ void load_weights(const MlpDev& m, MlpRegs& R) {
-  const int l = threadIdx.x & 63;
-  const int r = l & 15, g = l >> 4;
-  for (int t = 0; t < 4; ++t) {
-    for (int kk = 0; kk < 2; ++kk) R.w1[t][kk] = load4(m.w1b + (16 * t + r) * MLP_INP + 16 * kk + 4 * g);
-    for (int kk = 0; kk < 4; ++kk) R.w2[t][kk] = load4(m.w2b + (16 * t + r) * MLP_H + 16 * kk + 4 * g);
-  }
-}
-
 // Biases and output weights of the network (P: pointer type they are read
 // through).
 template <class P>
@@ -258,53 +234,7 @@ __device__ __forceinline__ MlpVec<const float*> mlp_vec(const MlpDev& m) {
   return {m.p + OFF_B1, m.p + OFF_B2, m.p + OFF_W3, m.p[OFF_B3]};
 }
 
-// Forward of 16 cells whose bf16 features are at X (row stride 32; rows
-// beyond nrow read as zero).  Outputs in D layout (lane: units 16t+4g+i of
-// cell l%16): H1 (fp32), H2 (fp32); returns theta of cell l % 16.
-template <class P>
-__device__ __forceinline__ float mlp_tile_fwd(const MlpVec<P>& m, const MlpRegs& R, const unsigned short* X, int nrow,
-                                              v4f* H1, v4f* H2, float* z3out, int xstride = MLP_INP) {
-  const int l = threadIdx.x & 63;
-  const int r = l & 15, g = l >> 4;
-  v4s xb[2];
-  // K columns 24..31 (lanes g = 2, 3 of the second K block) are the zero
-  // padding of W1: they are not read, so rows may be packed 24 wide
-  for (int kk = 0; kk < 2; ++kk) {
-    if (r < nrow && 16 * kk + 4 * g < MLP_IN)
-      xb[kk] = load4(X + r * xstride + 16 * kk + 4 * g);
-    else
-      xb[kk] = v4s{0, 0, 0, 0};
-  }
-  v4s h1b[4];
-  for (int t = 0; t < 4; ++t) {
-    v4f acc;
-    for (int i = 0; i < 4; ++i) acc[i] = m.b1[16 * t + 4 * g + i];
-    for (int kk = 0; kk < 2; ++kk) acc = mfma16(R.w1[t][kk], xb[kk], acc);
-    v4f h;
-    for (int i = 0; i < 4; ++i) h[i] = fast_tanh(acc[i]);
-    H1[t] = h;
-    h1b[t] = v4s{(short)f2bf(h[0]), (short)f2bf(h[1]), (short)f2bf(h[2]), (short)f2bf(h[3])};
-  }
-  float part = 0.f;
-  for (int t = 0; t < 4; ++t) {
-    v4f acc;
-    for (int i = 0; i < 4; ++i) acc[i] = m.b2[16 * t + 4 * g + i];
-    for (int kk = 0; kk < 4; ++kk) acc = mfma16(R.w2[t][kk], h1b[kk], acc);
-    v4f h;
-    for (int i = 0; i < 4; ++i) {
-      h[i] = fast_tanh(acc[i]);
-      part += m.w3[16 * t + 4 * g + i] * h[i];
-    }
-    H2[t] = h;
-  }
-  part += __shfl_xor(part, 16, 64);
-  part += __shfl_xor(part, 32, 64);
-  const float z3 = part + m.b3;
-  *z3out = z3;
-  return __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(z3 * -1.4426950408889634f));
-}
-
-// Inference with the K = 32 bf16 matrix instruction of gfx950
+// Forward of 16 cells with the K = 32 bf16 matrix instruction of gfx950
 // (v_mfma_f32_16x16x32_bf16, half as many instructions as K = 16): lane
 // group g = l / 16 holds 8 K slots of each operand.  Layer 1: slots 8g..8g+7
 // are features 8g..8g+7 (g = 3: W1's zero padding, not read).  Layer 2 takes
@@ -348,10 +278,14 @@ __device__ __forceinline__ void load_weights32(const MlpDev& m, MlpRegs32& R) {
 }
 
 // theta of the 16 cells whose bf16 features are at X (row stride xstride,
-// a multiple of 8; rows beyond nrow read as zero), for lane l's cell l % 16
+// a multiple of 8, X 16-byte aligned; rows beyond nrow read as zero), for
+// lane l's cell l % 16; optionally the hidden activations in accumulator
+// layout (H1, H2: lane l holds units 16t + 4g + i of cell l % 16) and the
+// logit z3, which the training kernel's backward uses.
 template <class P>
 __device__ __forceinline__ float mlp_tile_fwd32(const MlpVec<P>& m, const MlpRegs32& R, const unsigned short* X,
-                                                int nrow, int xstride) {
+                                                int nrow, int xstride, v4f* H1 = nullptr, v4f* H2 = nullptr,
+                                                float* z3out = nullptr) {
   const int l = threadIdx.x & 63;
   const int r = l & 15, g = l >> 4;
   const v8s xb = (r < nrow && 8 * g < MLP_IN) ? load8(X + r * xstride + 8 * g) : v8s{0, 0, 0, 0, 0, 0, 0, 0};
@@ -360,18 +294,29 @@ __device__ __forceinline__ float mlp_tile_fwd32(const MlpVec<P>& m, const MlpReg
     v4f acc;
     for (int i = 0; i < 4; ++i) acc[i] = m.b1[16 * t + 4 * g + i];
     acc = mfma32(R.w1[t], xb, acc);
-    for (int i = 0; i < 4; ++i) h1[t >> 1][4 * (t & 1) + i] = (short)f2bf(fast_tanh(acc[i]));
+    v4f h;
+    for (int i = 0; i < 4; ++i) {
+      h[i] = fast_tanh(acc[i]);
+      h1[t >> 1][4 * (t & 1) + i] = (short)f2bf(h[i]);
+    }
+    if (H1) H1[t] = h;
   }
   float part = 0.f;
   for (int t = 0; t < 4; ++t) {
     v4f acc;
     for (int i = 0; i < 4; ++i) acc[i] = m.b2[16 * t + 4 * g + i];
     for (int b = 0; b < 2; ++b) acc = mfma32(R.w2[t][b], h1[b], acc);
-    for (int i = 0; i < 4; ++i) part += m.w3[16 * t + 4 * g + i] * fast_tanh(acc[i]);
+    v4f h;
+    for (int i = 0; i < 4; ++i) {
+      h[i] = fast_tanh(acc[i]);
+      part += m.w3[16 * t + 4 * g + i] * h[i];
+    }
+    if (H2) H2[t] = h;
   }
   part += __shfl_xor(part, 16, 64);
   part += __shfl_xor(part, 32, 64);
   const float z3 = part + m.b3;
+  if (z3out) *z3out = z3;
   return __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(z3 * -1.4426950408889634f));
 }
 
@@ -402,8 +347,8 @@ __global__ __launch_bounds__(256) void k_mlp_grad(MlpDev m, const unsigned short
   __shared__ unsigned short sh1[4][16 * MLP_H];   // H1 [row][u1], bf16
   __shared__ unsigned short sd1[4][16 * MLP_H];   // delta1 [row][u1], bf16
   __shared__ float red[MLP_NPARAM + 1];
-  MlpRegs R;
-  load_weights(m, R);
+  MlpRegs32 R;
+  load_weights32(m, R);
   const auto mv = mlp_vec(m);
   const int l = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
@@ -430,7 +375,7 @@ __global__ __launch_bounds__(256) void k_mlp_grad(MlpDev m, const unsigned short
     const int nrow = (int)((r1 - row0) < 16 ? (r1 - row0) : 16);
     v4f H1[4], H2[4];
     float z3;
-    const float th = mlp_tile_fwd(mv, R, X + row0 * MLP_INP, nrow, H1, H2, &z3);
+    const float th = mlp_tile_fwd32(mv, R, X + row0 * MLP_INP, nrow, MLP_INP, H1, H2, &z3);
     const bool valid = r < nrow;
     const float yy = valid ? y[row0 + r] : 0.f;
     const float g3 = valid ? (th - yy) * invn : 0.f;
@@ -592,39 +537,6 @@ __global__ void k_mlp_pack(const float* __restrict__ p, unsigned short* __restri
     w1b[k] = j < MLP_IN ? f2bf(p[OFF_W1 + u * MLP_IN + j]) : (unsigned short)0;
   }
   if (k < MLP_H * MLP_H) w2b[k] = f2bf(p[OFF_W2 + k]);
-}
-
-// Learned blend weights: features of the block's cells into LDS, then the
-// MLP on 16-cell tiles by each wave.
-template <class T, int D>
-__global__ __launch_bounds__(KTPB) void k_indicator(KArgs<T> a, int dcs, MlpDev m, float* __restrict__ theta) {
-  __shared__ unsigned short xs[KTPB * MLP_INP];
-  const int b = xcd_remap(blockIdx.x, a.cell_per_xcd, a.n_cell_blocks);
-  if (b < 0) return;
-  const int64_t c0 = (int64_t)b * KTPB;
-  const int64_t c = c0 + threadIdx.x;
-  if (c < a.nc) {
-    float f[MLP_IN];
-    cell_features<T, D>(a, dcs, c, f);
-    for (int j = 0; j < MLP_IN; ++j) xs[threadIdx.x * MLP_INP + j] = f2bf(f[j]);
-  } else {
-    for (int j = 0; j < MLP_IN; ++j) xs[threadIdx.x * MLP_INP + j] = 0;
-  }
-  for (int j = MLP_IN; j < MLP_INP; ++j) xs[threadIdx.x * MLP_INP + j] = 0;
-  __syncthreads();
-  MlpRegs R;
-  load_weights(m, R);
-  const auto mv = mlp_vec(m);
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  for (int t = 0; t < 4; ++t) {
-    const int64_t row0 = c0 + 64 * w + 16 * t;
-    if (row0 >= a.nc) break;
-    const int nrow = (int)((a.nc - row0) < 16 ? (a.nc - row0) : 16);
-    v4f H1[4], H2[4];
-    float z3;
-    const float th = mlp_tile_fwd(mv, R, xs + (64 * w + 16 * t) * MLP_INP, nrow, H1, H2, &z3);
-    if (l < nrow) theta[row0 + l] = th;
-  }
 }
 
 // First gradient and the indicator's features of a stage: the cell's

@@ -162,7 +162,6 @@ hipError_t launch_face_export(dolinc_ctx_s* c, const void* U, void* UL, void* UR
 hipError_t launch_diagnostics(dolinc_ctx_s* c, const void* U, double* out_host, hipStream_t s);
 bool flux_supported(const dolinc_params& p, int dim);
 hipError_t features_launch(dolinc_ctx_s* c, const void* U, float* X32, unsigned short* Xb, hipStream_t s);
-hipError_t indicator_launch(dolinc_ctx_s* c, const void* U, float* theta, hipStream_t s);
 hipError_t mlp_pack_launch(dolinc_ctx_s* c, hipStream_t s);
 hipError_t grad_features_launch(dolinc_ctx_s* c, const void* U, void* G1, unsigned short* Xf, hipStream_t s);
 // X rows xstride bf16 wide (24: packed stage features, 32: the API's rows)
