@@ -16,6 +16,9 @@ import sys
 import tempfile
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+# what the CPU suite needs
+COPY = ["oracle", "synth", "tests", "paper_2404_08952_amd", "include", "pytest.ini", "bench.py",
+        "__graft_entry__.py"]
 
 MUTATIONS = [
     ('oracle/scheme.py',
@@ -119,8 +122,14 @@ def check(item):
     tmp = tempfile.mkdtemp(prefix=f"oracle_mut{i}_")
     try:
         dst = os.path.join(tmp, "repo")
-        shutil.copytree(ROOT, dst, ignore=shutil.ignore_patterns(".git", "_work", "__pycache__", "gpurun_out",
-                                                                  "_build", "*.so"))
+        os.makedirs(dst)
+        skip = shutil.ignore_patterns("__pycache__", "*.so", "*.o")
+        for name in COPY:
+            src_path = os.path.join(ROOT, name)
+            if os.path.isdir(src_path):
+                shutil.copytree(src_path, os.path.join(dst, name), ignore=skip)
+            else:
+                shutil.copy2(src_path, os.path.join(dst, name))
         p = os.path.join(dst, path)
         with open(p) as fh:
             src = fh.read()
@@ -140,6 +149,12 @@ def check(item):
 
 def main():
     workers = int(sys.argv[1]) if len(sys.argv) > 1 else 4
+    # control: the copy without a planted mistake must pass
+    path, old, _new = MUTATIONS[0]
+    control = check((len(MUTATIONS), (path, old, old)))
+    print("control (no mistake):", "passes" if control.startswith("MISSED") else "FAILS", flush=True)
+    if not control.startswith("MISSED"):
+        sys.exit(2)
     missed = 0
     with cf.ThreadPoolExecutor(workers) as ex:
         for line in ex.map(check, enumerate(MUTATIONS)):
