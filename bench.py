@@ -802,7 +802,9 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": desc, "cells": nc, "faces": nf, "stages_per_step": 3,
-                   "precision": "FP32 bulk (reference-state flux form), coefficients precomputed in FP64"},
+                   "precision": ("FP32 bulk (reference-state flux form); geometry and growth rates precomputed "
+                                 "in FP64, the DOLINC coefficients evaluated from them in FP64 in the flux kernel"),
+                   "partition_cells": PART_CELLS["fp32"]},
         "roofline": {"bound": "hbm", "achieved": fk["gbps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": fk["gbps"] / HBM_PEAK_GBPS, "traffic": measured_traffic(args.workload),
                      "kernel": "k_flux (reconstruction + blend + Riemann flux + segmented accumulation + RK update)",
