@@ -322,9 +322,20 @@ __device__ __forceinline__ float mlp_tile_fwd32(const MlpVec<P>& m, const MlpReg
 
 __global__ __launch_bounds__(256) void k_mlp_fwd(MlpDev m, const unsigned short* __restrict__ X, int64_t n,
                                                  float* __restrict__ theta, int xstride) {
+  // biases and output weights in LDS, re-read at every tile (compiler
+  // barrier below), the weight matrices in registers: fewer VGPRs, so the
+  // kernel leaves room on each SIMD for the kernel it runs beside
+  __shared__ float vb[3 * MLP_H + 4];
+  for (int i = threadIdx.x; i < MLP_H; i += blockDim.x) {
+    vb[i] = m.p[OFF_B1 + i];
+    vb[MLP_H + i] = m.p[OFF_B2 + i];
+    vb[2 * MLP_H + i] = m.p[OFF_W3 + i];
+  }
+  if (threadIdx.x == 0) vb[3 * MLP_H] = m.p[OFF_B3];
+  __syncthreads();
   MlpRegs32 R;
   load_weights32(m, R);
-  const auto mv = mlp_vec(m);
+  const MlpVec<LdsPtr<float>> mv = {as_lds(vb), as_lds(vb + MLP_H), as_lds(vb + 2 * MLP_H), vb[3 * MLP_H]};
   const int l = threadIdx.x & 63;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -332,6 +343,7 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(MlpDev m, const unsigned short*
   for (int64_t t = wave; t < ntile; t += nwaves) {
     const int64_t row0 = t * 16;
     const int nrow = (int)((n - row0) < 16 ? (n - row0) : 16);
+    __asm__ volatile("" ::: "memory");
     const float th = mlp_tile_fwd32(mv, R, X + row0 * xstride, nrow, xstride);
     if (l < nrow) theta[row0 + l] = th;
   }
