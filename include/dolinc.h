@@ -120,7 +120,10 @@ typedef struct {
   const double* neigh_shift;     /* host [n_faces][dim]: moves the neighbour's       */
                                  /* geometry into the owner's frame (periodic)       */
   int32_t renumber;              /* 0 keep, 1 reverse Cuthill-McKee, 2 Hilbert curve */
-  int32_t part_cells;            /* cells per partition (0 = default 256; <= 1024)   */
+  int32_t part_cells;            /* cells per partition (0 = default 256; <= 1024);  */
+                                 /* dolinc_precompute returns EUNSUPPORTED when a    */
+                                 /* partition's face fluxes exceed the LDS of one    */
+                                 /* workgroup on the device (160 KB on gfx950)       */
   /* Non-coupled boundaries (Sec. 2.6).  NULL: every face has two cells.
    * Otherwise host [n_faces]: -1 for a two-cell face; for a boundary face
    * (neighbour[f] == -1, owner[f] the cell, normal pointing out of the
