@@ -5,10 +5,15 @@ Test infrastructure only.
   where cell 0 is upwind and cell 1 downwind, Delta = phi_1 - phi_0 and the
   upwind difference s = phi_0^(1) - Delta (= g (phi_0 - phi_-1) by the
   first inversion formula, Sec. 2.3, and the ENO3 divided difference,
-  Sec. 2.4).  The limited state is phi_0 + (1 - omega_0) psi Delta with
-  psi Delta = 2 s Delta / (s + Delta) when s Delta > 0, else 0 (Van Leer's
-  limiter in the gradient-ratio form r = s / Delta; symmetric,
-  psi(1/r) = psi(r) / r).
+  Sec. 2.4).  The limited state is phi_0 + L with the increment
+  L = (1 - omega_0) psi Delta, psi Delta = 2 s Delta / (s + Delta) when
+  s Delta > 0, else 0 (Van Leer's limiter in the gradient-ratio form
+  r = s / Delta; symmetric, psi(1/r) = psi(r) / r), and |L| capped at |Delta|
+  so that the face state stays between the two cell values.  On a face with
+  omega_0 >= 1/2 (uniform cells, or the face nearer the upwind cell) Van
+  Leer's psi < 2 keeps it there by itself; where the downwind cell is the
+  nearer one, (1 - omega_0) psi can reach 2 (1 - omega_0) > 1 and the
+  uncapped state would overshoot the downwind value.
 * Sensor: beta = |s - Delta| / (|s| + |Delta| + eps) per face side and
   sensed variable; a cell takes the largest beta over the faces on which it
   is the upwind cell.  theta = clip((beta_hi - beta) / (beta_hi - beta_lo)).
@@ -34,16 +39,23 @@ def vanleer_increment(s, delta):
     return np.where(prod > 0.0, 2.0 * prod / safe, 0.0)
 
 
+def limited_increment(s, delta, w_down):
+    """(1 - omega_0) psi Delta with w_down = 1 - omega_0 (the downwind cell's
+    interpolation weight), its magnitude capped at |Delta|."""
+    inc = w_down * vanleer_increment(s, delta)
+    return np.where(np.abs(inc) > np.abs(delta), delta, inc)
+
+
 def limited_states(mesh, geo, U, G1):
     """Van Leer limited (U_L, U_R) per face."""
     P, N = mesh.owner, mesh.neighbour
     w = geo.omega[:, None]
     dL = U[N] - U[P]
     sL = 2.0 * np.einsum("fva,fa->fv", G1[P], geo.d) - dL
-    UL = U[P] + (1.0 - w) * vanleer_increment(sL, dL)
+    UL = U[P] + limited_increment(sL, dL, 1.0 - w)
     dR = U[P] - U[N]
     sR = 2.0 * np.einsum("fva,fa->fv", G1[N], -geo.d) - dR
-    UR = U[N] + w * vanleer_increment(sR, dR)
+    UR = U[N] + limited_increment(sR, dR, w)
     return UL, UR
 
 

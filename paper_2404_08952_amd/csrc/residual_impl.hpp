@@ -56,7 +56,6 @@ struct KArgs {
   T bdir[3];
   int use_ref;
   T uref[5];
-  int stage_mask;  // k_flux rows staged in LDS: 1 G1, 4 U and theta
   const int32_t* face_ent;
   int64_t nf;
   T* eUL;
@@ -163,20 +162,6 @@ __device__ __forceinline__ void contract2(P src, const T* d, T* out) {
   }
 }
 
-template <class T, int NV, int D, int ORD>
-__device__ __forceinline__ void contract_cell(const T* lds, const T* __restrict__ g, int64_t c0, int n, int64_t row,
-                                              const T* d, T* out) {
-  constexpr int W = ORD == 1 ? NV * D : NV * D * (D + 1) / 2;
-  const int64_t r = row - c0;
-  if (r >= 0 && r < n) {
-    if constexpr (ORD == 1) contract1<T, NV, D>(as_lds(lds + r * W), d, out);
-    else contract2<T, NV, D>(as_lds(lds + r * W), d, out);
-  } else {
-    if constexpr (ORD == 1) contract1<T, NV, D>(as_glb(g + row * W), d, out);
-    else contract2<T, NV, D>(as_glb(g + row * W), d, out);
-  }
-}
-
 // FP32 quotient and square root on the hardware reciprocal / square-root
 // units (about 1 ulp, no correction sequence); FP64 stays correctly rounded.
 __device__ __forceinline__ float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
@@ -188,6 +173,17 @@ template <class T>
 __device__ __forceinline__ T vanleer_inc(T s, T delta) {
   const T prod = s * delta;
   return prod > T(0) ? fdiv(T(2) * prod, s + delta) : T(0);
+}
+
+// Limited increment w_down * psi Delta (w_down = 1 - omega_0, the downwind
+// cell's interpolation weight) with its magnitude capped at |Delta|: the
+// limited face state stays between the two cell values also where the
+// downwind cell is the nearer one (w_down > 1/2), where Van Leer's psi up to
+// 2 would otherwise carry it past the downwind value.
+template <class T>
+__device__ __forceinline__ T limited_inc(T s, T delta, T w_down) {
+  const T inc = w_down * vanleer_inc(s, delta);
+  return fabs(inc) > fabs(delta) ? delta : inc;
 }
 
 // ---------------------------------------------------------------- Euler fluxes
@@ -522,23 +518,11 @@ __device__ __forceinline__ T nonlin_side(const NonlinCoef<T>& c, T a0, T a1, T D
 
 // ---------------------------------------------------------------- face evaluation
 // Loads one face entry, reconstructs (U_L, U_R) and returns the
-// face-integrated flux F.S (owner -> neighbour).
-// Optional LDS copies of the current partition's cell rows (k_flux).
-template <class T>
-struct Stage {
-  // Rows c0 .. c0+n* of each array held in LDS (n* = 0: read it from HBM).
-  // The pointers always point into LDS (never null) so that loads through
-  // them stay LDS loads.
-  const T* U = nullptr;
-  const T* G1 = nullptr;
-  const float* th = nullptr;
-  int64_t c0 = 0;
-  int nU = 0, nG1 = 0, nth = 0;
-};
-
+// face-integrated flux F.S (owner -> neighbour).  Cell rows are gathered
+// straight from HBM/L2: staging the partition's own rows in LDS cost more in
+// occupancy and barriers than it saved.
 template <class T, int D, int PK, int SCH, bool BLEND>
-__device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T* UR, T* F,
-                                          const Stage<T>& st = Stage<T>()) {
+__device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T* UR, T* F) {
   constexpr int NV = NVars<PK, D>::value;
   constexpr int ORD = SchemeInfo<SCH>::ORD;
   constexpr int DCS = SchemeInfo<SCH>::template dcs<T>();
@@ -554,8 +538,15 @@ __device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T
   T uP[NV], uN[NV];
   // Euler with a reference state: reconstruct perturbations U - U_ref
   const bool pert = PK >= 2 && a.use_ref;
-  load_row<T, NV>(uP, st.U, a.U, st.c0, st.nU, P);
-  load_row<T, NV>(uN, st.U, a.U, st.c0, st.nU, N);
+  {
+    GlbPtr<T> up = as_glb(a.U + P * NV);
+    GlbPtr<T> un = as_glb(a.U + N * NV);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      uP[v] = up[v];
+      uN[v] = un[v];
+    }
+  }
   if (pert) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -567,8 +558,8 @@ __device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T
 #pragma unroll
   for (int v = 0; v < NV; ++v) gP[v] = gN[v] = hP[v] = hN[v] = T(0);
   if constexpr (ORD >= 1 || BLEND) {
-    contract_cell<T, NV, D, 1>(st.G1, a.G1, st.c0, st.nG1, P, dc, gP);
-    contract_cell<T, NV, D, 1>(st.G1, a.G1, st.c0, st.nG1, N, dc, gN);
+    contract1<T, NV, D>(as_glb(a.G1 + P * NV * D), dc, gP);
+    contract1<T, NV, D>(as_glb(a.G1 + N * NV * D), dc, gN);
   }
   if constexpr (ORD >= 2) {  // d.H.d of both cells, written per face record by the second-derivative kernel
     const int2 rc = a.ent_rec[e];
@@ -626,16 +617,14 @@ __device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T
     }
   }
   if constexpr (BLEND) {
-    float thP, thN;
-    load_row<float, 1>(&thP, st.th, a.theta, st.c0, st.nth, P);
-    load_row<float, 1>(&thN, st.th, a.theta, st.c0, st.nth, N);
+    const float thP = as_glb(a.theta)[P], thN = as_glb(a.theta)[N];
     const T tf = (T)fminf(thP, thN);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       const T dL = uN[v] - uP[v];
-      const T VL = uP[v] + (T(1) - om) * vanleer_inc(T(2) * gP[v] - dL, dL);
+      const T VL = uP[v] + limited_inc(T(2) * gP[v] - dL, dL, T(1) - om);
       const T dR = uP[v] - uN[v];
-      const T VR = uN[v] + om * vanleer_inc(T(-2) * gN[v] - dR, dR);
+      const T VR = uN[v] + limited_inc(T(-2) * gN[v] - dR, dR, om);
       UL[v] = tf * UL[v] + (T(1) - tf) * VL;
       UR[v] = tf * UR[v] + (T(1) - tf) * VR;
     }
@@ -700,61 +689,20 @@ __device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T
 }
 
 // ---------------------------------------------------------------- kernels
-// Rows of one cell staged by k_flux: U, G1 (if used), theta.
-template <class T, int D, int PK, int SCH, bool BLEND>
-struct FluxStage {
-  static constexpr int NV = NVars<PK, D>::value;
-  static constexpr bool G1 = SchemeInfo<SCH>::ORD >= 1 || BLEND;
-  // bytes of LDS for the staged rows of B cells (theta as T-sized slots)
-  static constexpr size_t bytes(int B, int mask) {
-    return (size_t)B * ((mask & 4 ? NV + (BLEND ? 1 : 0) : 0) + ((mask & 1) && G1 ? NV * D : 0)) * sizeof(T);
-  }
-};
-
 template <class T, int D, int PK, int SCH, bool BLEND>
 __global__ __launch_bounds__(KTPB) void k_flux(KArgs<T> a) {
   constexpr int NV = NVars<PK, D>::value;
-  using FS = FluxStage<T, D, PK, SCH, BLEND>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int p = xcd_remap(blockIdx.x, a.per_xcd, a.np);
   if (p < 0) return;
   const int64_t c0 = (int64_t)p * a.B;
   const int ncl = (int)(a.nc - c0 < a.B ? a.nc - c0 : a.B);
-  // LDS: staged cell rows, then the face fluxes
-  T* lds = reinterpret_cast<T*>(smem_raw);
-  Stage<T> st;
-  st.c0 = c0;
-  st.U = st.G1 = lds;
-  st.th = reinterpret_cast<const float*>(lds);
-  size_t off = 0;
-  if (a.stage_mask & 4) {
-    stage_rows(lds + off, a.U, c0, ncl, NV);
-    st.nU = ncl;
-    off += (size_t)a.B * NV;
-  }
-  if constexpr (FS::G1) {
-    if (a.stage_mask & 1) {
-      stage_rows(lds + off, a.G1, c0, ncl, NV * D);
-      st.G1 = lds + off;
-      st.nG1 = ncl;
-      off += (size_t)a.B * NV * D;
-    }
-  }
-  if constexpr (BLEND) {
-    if (a.stage_mask & 4) {
-      float* thl = reinterpret_cast<float*>(lds + off);
-      stage_rows(thl, a.theta, c0, ncl, 1);
-      st.th = thl;
-      st.nth = ncl;
-      off += (size_t)a.B;
-    }
-  }
-  T* Fs = lds + off;
-  __syncthreads();
+  // LDS: the partition's face fluxes
+  T* Fs = reinterpret_cast<T*>(smem_raw);
   const int e0 = a.part_ptr[p], e1 = a.part_ptr[p + 1];
   for (int e = e0 + (int)threadIdx.x; e < e1; e += KTPB) {
     T UL[NV], UR[NV], F[NV];
-    eval_face<T, D, PK, SCH, BLEND>(a, e, UL, UR, F, st);
+    eval_face<T, D, PK, SCH, BLEND>(a, e, UL, UR, F);
 #pragma unroll
     for (int v = 0; v < NV; ++v) Fs[(e - e0) * NV + v] = F[v];
   }

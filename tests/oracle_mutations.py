@@ -114,6 +114,40 @@ MUTATIONS = [
     ('oracle/scheme.py',
      'UR = side(GN, GP, -geo.d, 1.0 / geo.g, scheme)',
      'UR = side(GN, GP, geo.d, 1.0 / geo.g, scheme)'),
+    # blend, sensor, positivity and indicator channels
+    ('oracle/limiter.py',
+     'return np.clip((BETA_HI - beta) / (BETA_HI - BETA_LO), 0.0, 1.0), beta',
+     'return np.clip((BETA_HI - beta) / (BETA_HI + BETA_LO), 0.0, 1.0), beta'),
+    ('oracle/limiter.py',
+     'np.maximum.at(beta, N, bN)',
+     'np.maximum.at(beta, P, bN)'),
+    ('oracle/limiter.py',
+     'tf = np.minimum(theta[mesh.owner], theta[mesh.neighbour])[:, None]',
+     'tf = np.maximum(theta[mesh.owner], theta[mesh.neighbour])[:, None]'),
+    ('oracle/limiter.py',
+     'UR = U[N] + limited_increment(sR, dR, w)',
+     'UR = U[N] + limited_increment(sR, dR, 1.0 - w)'),
+    ('oracle/limiter.py',
+     'return np.where(np.abs(inc) > np.abs(delta), delta, inc)',
+     'return inc'),
+    ('oracle/solver.py',
+     'UR = np.where(badR[:, None], U[mesh.neighbour], UR)',
+     'UR = np.where(badR[:, None], U[mesh.owner], UR)'),
+    ('oracle/indicator.py',
+     'g_p = (gamma - 1.0) * (g_E - u_dot_gm',
+     'g_p = (gamma - 1.0) * (g_E + u_dot_gm'),
+    ('oracle/indicator.py',
+     'np.einsum("ca,cad->cd", m / safe[:, None], g_m)',
+     'np.einsum("ca,cda->cd", m / safe[:, None], g_m)'),
+    ('oracle/indicator.py',
+     'f = np.stack([acc_max[0] / scale,',
+     'f = np.stack([acc_max[0] / scale ** 2,'),
+    ('oracle/indicator.py',
+     'acc_max[2], sum_beta / cnt, acc_min,',
+     'acc_max[2], sum_beta, acc_min,'),
+    ('oracle/indicator.py',
+     'acc_max[3] / scale], 1)',
+     'acc_max[3]], 1)'),
 ]
 
 
