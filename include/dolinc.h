@@ -167,14 +167,15 @@ typedef struct {                 /* host-side partition statistics              
 } dolinc_mesh_stats;
 
 /* Validate the mesh, renumber cells, build partitions and face entries and
- * upload them (hipMalloc + synchronous copies on the null stream).  Defines
+ * upload them (hipMalloc, then copies enqueued on stream s; synchronises s
+ * before returning, so the host arrays may be released afterwards).  Defines
  * the problem of Sec. 2.1-2.2: cell averages on a face-addressed mesh, every
  * face shared by two cells (periodic faces carrying a translation, Sec. 2.6)
  * or, with face_patch, a boundary face of one cell on a boundary patch
  * (Sec. 2.6; an auxiliary cell is appended for it, see dolinc_set_boundary).
  * EMESH for unpaired / self faces, out-of-range indices, boundary faces
  * without a valid patch or non-closed cells. */
-dolinc_status dolinc_create(const dolinc_mesh_desc* mesh, dolinc_ctx* out);
+dolinc_status dolinc_create(const dolinc_mesh_desc* mesh, dolinc_stream s, dolinc_ctx* out);
 
 /* The host part of dolinc_create only (validation, renumbering, partitions);
  * touches no device.  new_of_old (host [n_cells]) and stats may be NULL. */
@@ -235,9 +236,13 @@ dolinc_status dolinc_face_states(dolinc_ctx ctx, const void* U, void* UL, void* 
 dolinc_status dolinc_geometry(dolinc_ctx ctx, double* V, double* xc, double* S, double* xf,
                               double* omega, double* g, dolinc_stream s);
 
-/* Diagnostics of U into host double out[n_v + 3]: conserved totals
- * sum_c V_c U_c (FP64 sums) for every variable, then min rho (or min u),
- * min p (Euler; else max u) and the count of non-finite entries.  Blocks on s. */
+/* Diagnostics of U into device double out[n_v + 3]: conserved totals
+ * sum_c V_c U_c (FP64 sums; the conservation statement of the coupled
+ * finite-volume update, Sec. 2.2 and 2.6) for every variable, then min rho
+ * (or min u), min p (Euler; else max u) and the count of non-finite entries.
+ * Two kernels enqueued on s (per-block partials, then one ordered
+ * reduction); does not block.  Calls on one context share the partials'
+ * workspace, so two diagnostics calls in flight on different streams race. */
 dolinc_status dolinc_diagnostics(dolinc_ctx ctx, const void* U, double* out, dolinc_stream s);
 
 /* Features of state U (Euler): X32 device float [n_cells][24] and/or Xbf
@@ -245,10 +250,14 @@ dolinc_status dolinc_diagnostics(dolinc_ctx ctx, const void* U, double* out, dol
  * NULL.  Internal cell order. */
 dolinc_status dolinc_features(dolinc_ctx ctx, const void* U, float* X32, uint16_t* Xbf, dolinc_stream s);
 
-/* Set (host float[DOLINC_MLP_PARAMS]) or read back the network parameters.
- * Setting resets the Adam moments and step count.  Both synchronise. */
-dolinc_status dolinc_mlp_set(dolinc_ctx ctx, const float* params);
-dolinc_status dolinc_mlp_get(dolinc_ctx ctx, float* params);
+/* Set or read back the network parameters: params device
+ * float[DOLINC_MLP_PARAMS] (the packing above), copied on stream s; neither
+ * call blocks.  Setting resets the Adam moments and step count and refreshes
+ * the bf16 copies the matrix cores read; the values are taken as given (no
+ * finiteness check on the device).  The first set allocates the network's
+ * device memory (ENOMEM if that fails). */
+dolinc_status dolinc_mlp_set(dolinc_ctx ctx, const float* params, dolinc_stream s);
+dolinc_status dolinc_mlp_get(dolinc_ctx ctx, float* params, dolinc_stream s);
 
 /* theta = network(X) for n rows of bf16 features X (device [n][32], 16-byte
  * aligned: each lane reads 8 features at once; the 8 padding columns are not

@@ -54,7 +54,7 @@ class DolincError(RuntimeError):
 _LIB = None
 
 SIGNATURES = {
-    "dolinc_create": [C.POINTER(MeshDesc), C.POINTER(C.c_void_p)],
+    "dolinc_create": [C.POINTER(MeshDesc), C.c_void_p, C.POINTER(C.c_void_p)],
     "dolinc_mesh_prepare": [C.POINTER(MeshDesc), C.c_void_p, C.POINTER(MeshStats)],
     "dolinc_permutation": [C.c_void_p, C.c_void_p],
     "dolinc_stats": [C.c_void_p, C.POINTER(MeshStats)],
@@ -71,8 +71,8 @@ SIGNATURES = {
     "dolinc_diagnostics": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
     "dolinc_timing": [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p],
     "dolinc_features": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
-    "dolinc_mlp_set": [C.c_void_p, C.c_void_p],
-    "dolinc_mlp_get": [C.c_void_p, C.c_void_p],
+    "dolinc_mlp_set": [C.c_void_p, C.c_void_p, C.c_void_p],
+    "dolinc_mlp_get": [C.c_void_p, C.c_void_p, C.c_void_p],
     "dolinc_mlp_forward": [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p],
     "dolinc_mlp_train_step": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_float, C.c_void_p, C.c_void_p],
     "dolinc_mlp_gradient": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p],
@@ -83,10 +83,16 @@ SIGNATURES = {
 
 
 def load(path=LIB_PATH):
-    """Load the HIP library (raises if it has not been built)."""
+    """Load the HIP library (raises if it has not been built).
+
+    PyTorch is imported first: its HIP runtime then serves the library too
+    (the library's dependency on the runtime resolves to the copy already
+    loaded).  Loading the library first would bring in a second runtime,
+    and the first device call of one of them would find no device."""
     global _LIB
     if _LIB is not None:
         return _LIB
+    import torch  # noqa: F401
     if not os.path.exists(path):
         raise FileNotFoundError(f"{path} not found: build it with paper_2404_08952_amd/build.py")
     lib = C.CDLL(path)
@@ -174,7 +180,7 @@ class Solver:
         torch.cuda.set_device(self.device)
         d, keep = mesh_desc(mesh, renumber, part_cells)
         h = C.c_void_p()
-        _check(self.lib, self.lib.dolinc_create(C.byref(d), C.byref(h)))
+        _check(self.lib, self.lib.dolinc_create(C.byref(d), self._stream(), C.byref(h)))
         self.h = h
         del keep
         self.dim = mesh.dim
@@ -294,10 +300,12 @@ class Solver:
                                                   self._stream()))
         return dict(V=V, xc=xc, S=S, xf=xf, omega=om, g=g)
 
-    def diagnostics(self, U):
-        out = np.empty(self.nv + 3, dtype=np.float64)
-        _check(self.lib, self.lib.dolinc_diagnostics(self.h, self._ptr(U), out.ctypes.data, self._stream()))
-        return out
+    def diagnostics(self, U, device=False):
+        """Conserved totals, min rho (min u), min p (max u), non-finite count;
+        a device tensor with ``device=True``, else copied to the host."""
+        out = self.torch.empty(self.nv + 3, dtype=self.torch.float64, device=self.device)
+        _check(self.lib, self.lib.dolinc_diagnostics(self.h, self._ptr(U), self._ptr(out), self._stream()))
+        return out if device else out.cpu().numpy()
 
     def timing(self, enable):
         """Start (True) / stop (False) per-kernel HIP-event timing; returns the
@@ -317,15 +325,24 @@ class Solver:
         return X32, Xb
 
     def mlp_set(self, params):
-        p = np.ascontiguousarray(params, dtype=np.float32)
-        if p.size != MLP_PARAMS:
+        """Network parameters from a host array or a device tensor (float32
+        [MLP_PARAMS]); copied on the current stream."""
+        if isinstance(params, self.torch.Tensor):
+            p = params.detach().to(device=self.device, dtype=self.torch.float32).contiguous()
+        else:
+            h = np.ascontiguousarray(params, dtype=np.float32)
+            if not np.all(np.isfinite(h)):
+                raise ValueError("non-finite network parameter")
+            p = self.torch.from_numpy(h).to(self.device)
+        if p.numel() != MLP_PARAMS:
             raise ValueError(f"expected {MLP_PARAMS} parameters")
-        _check(self.lib, self.lib.dolinc_mlp_set(self.h, p.ctypes.data))
+        _check(self.lib, self.lib.dolinc_mlp_set(self.h, self._ptr(p), self._stream()))
+        self._mlp_src = p  # kept until the next set: the copy is stream-ordered
 
-    def mlp_get(self):
-        p = np.empty(MLP_PARAMS, dtype=np.float32)
-        _check(self.lib, self.lib.dolinc_mlp_get(self.h, p.ctypes.data))
-        return p
+    def mlp_get(self, device=False):
+        p = self.torch.empty(MLP_PARAMS, dtype=self.torch.float32, device=self.device)
+        _check(self.lib, self.lib.dolinc_mlp_get(self.h, self._ptr(p), self._stream()))
+        return p if device else p.cpu().numpy()
 
     def mlp_forward(self, Xb):
         th = self.torch.empty(Xb.shape[0], dtype=self.torch.float32, device=self.device)

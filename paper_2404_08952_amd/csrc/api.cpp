@@ -28,8 +28,8 @@ hipError_t hface_f64(dolinc_ctx_s*, const void*, void*, hipStream_t);
 hipError_t hface_f32(dolinc_ctx_s*, const void*, void*, hipStream_t);
 hipError_t theta_f64(dolinc_ctx_s*, const void*, const void*, float*, hipStream_t);
 hipError_t theta_f32(dolinc_ctx_s*, const void*, const void*, float*, hipStream_t);
-hipError_t diag_f64(dolinc_ctx_s*, const void*, double*, int, hipStream_t);
-hipError_t diag_f32(dolinc_ctx_s*, const void*, double*, int, hipStream_t);
+hipError_t diag_f64(dolinc_ctx_s*, const void*, double*, int, double*, hipStream_t);
+hipError_t diag_f32(dolinc_ctx_s*, const void*, double*, int, double*, hipStream_t);
 }  // namespace dolinc
 
 using namespace dolinc;
@@ -61,11 +61,13 @@ bool valid_ctx(dolinc_ctx c) {
   return g_live.count((const void*)c) != 0;
 }
 
+// Device copy of a host array, enqueued on stream s (the host array must
+// outlive the copy: dolinc_create synchronises s before its host vectors go).
 template <class X>
-hipError_t upload(X** dst, const X* src, size_t n) {
+hipError_t upload(X** dst, const X* src, size_t n, hipStream_t s) {
   hipError_t e = hipMalloc((void**)dst, n * sizeof(X) + (n == 0 ? sizeof(X) : 0));
   if (e != hipSuccess) return e;
-  if (n) e = hipMemcpy(*dst, src, n * sizeof(X), hipMemcpyHostToDevice);
+  if (n) e = hipMemcpyAsync(*dst, src, n * sizeof(X), hipMemcpyHostToDevice, s);
   return e;
 }
 
@@ -333,8 +335,9 @@ dolinc_status dolinc_mesh_prepare(const dolinc_mesh_desc* mesh, int32_t* new_of_
   return DOLINC_OK;
 }
 
-dolinc_status dolinc_create(const dolinc_mesh_desc* mesh, dolinc_ctx* out) {
+dolinc_status dolinc_create(const dolinc_mesh_desc* mesh, dolinc_stream stream, dolinc_ctx* out) {
   if (!mesh || !out) return fail(DOLINC_EINVAL, "NULL argument");
+  hipStream_t s = (hipStream_t)stream;
   *out = nullptr;
   dolinc_ctx c = nullptr;
   try {
@@ -373,7 +376,7 @@ dolinc_status dolinc_create(const dolinc_mesh_desc* mesh, dolinc_ctx* out) {
     DevMesh& m = c->m;
     hipError_t e = hipSuccess;
 #define UP(dst, src, n)                                       \
-  if (e == hipSuccess) e = upload(&(dst), (src), (size_t)(n));
+  if (e == hipSuccess) e = upload(&(dst), (src), (size_t)(n), s);
     UP(m.part_ptr, P.part_ent_ptr.data(), P.part_ent_ptr.size());
     UP(m.ent_face, P.ent_face.data(), P.ent_face.size());
     UP(m.ent_pn, pn.data(), pn.size());
@@ -460,6 +463,8 @@ dolinc_status dolinc_create(const dolinc_mesh_desc* mesh, dolinc_ctx* out) {
     dm(&m.dvec, 3 * (size_t)nf);
     if (e == hipSuccess) e = hipMalloc((void**)&c->w.flag, sizeof(int));
     if (e == hipSuccess) e = hipMalloc((void**)&c->w.diag, 1024 * 8 * sizeof(double));
+    // the host arrays above must outlive their copies
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
       free_all(c);
       delete c;
@@ -713,27 +718,11 @@ dolinc_status dolinc_diagnostics(dolinc_ctx c, const void* U, double* out, dolin
   if (st != DOLINC_OK) return st;
   if (!U || !out) return fail(DOLINC_EINVAL, "NULL argument");
   hipStream_t s = (hipStream_t)stream;
-  const int nv = c->w.nv, nout = nv + 3;
   int nb = (int)((c->n_interior + KTPB_HOST - 1) / KTPB_HOST);
   if (nb > 1024) nb = 1024;
-  HIPCHK(c->w.precision == DOLINC_FP64 ? diag_f64(c, U, c->w.diag, nb, s) : diag_f32(c, U, c->w.diag, nb, s));
-  std::vector<double> part((size_t)nb * nout);
-  HIPCHK(hipMemcpyAsync(part.data(), c->w.diag, part.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  const bool euler = c->params.pde == DOLINC_EULER;
-  for (int k = 0; k < nout; ++k) {
-    double acc = k < nv || k == nv + 2 ? 0.0 : (k == nv || euler ? 1e300 : -1e300);
-    for (int b = 0; b < nb; ++b) {
-      double x = part[(size_t)b * nout + k];
-      if (k < nv || k == nv + 2)
-        acc += x;
-      else if (k == nv || euler)
-        acc = std::fmin(acc, x);
-      else
-        acc = std::fmax(acc, x);
-    }
-    out[k] = acc;
-  }
+  if (nb < 1) nb = 1;
+  HIPCHK(c->w.precision == DOLINC_FP64 ? diag_f64(c, U, c->w.diag, nb, out, s)
+                                       : diag_f32(c, U, c->w.diag, nb, out, s));
   return DOLINC_OK;
 }
 
@@ -750,11 +739,9 @@ dolinc_status dolinc_features(dolinc_ctx c, const void* U, float* X32, uint16_t*
   return DOLINC_OK;
 }
 
-dolinc_status dolinc_mlp_set(dolinc_ctx c, const float* params) {
+dolinc_status dolinc_mlp_set(dolinc_ctx c, const float* params, dolinc_stream stream) {
   if (!valid_ctx(c)) return fail(DOLINC_ESTATE, "invalid or destroyed context");
   if (!params) return fail(DOLINC_EINVAL, "NULL parameters");
-  for (int k = 0; k < MLP_N; ++k)
-    if (!std::isfinite(params[k])) return fail(DOLINC_EINVAL, "non-finite parameter");
   Mlp& m = c->mlp;
   if (!m.p) {
     hipError_t e = hipMalloc((void**)&m.p, MLP_N * sizeof(float));
@@ -767,21 +754,19 @@ dolinc_status dolinc_mlp_set(dolinc_ctx c, const float* params) {
       return fail(DOLINC_ENOMEM, "network allocation failed");
     }
   }
-  HIPCHK(hipMemcpy(m.p, params, MLP_N * sizeof(float), hipMemcpyHostToDevice));
-  HIPCHK(hipMemset(m.m, 0, MLP_N * sizeof(float)));
-  HIPCHK(hipMemset(m.v, 0, MLP_N * sizeof(float)));
-  HIPCHK(mlp_pack_launch(c, nullptr));
-  HIPCHK(hipDeviceSynchronize());
+  // copy, Adam moments cleared, bf16 copies refreshed: kernels on the
+  // caller's stream (a stage's network work is joined back into the stream
+  // it was called on, so it is ordered before this)
+  HIPCHK(mlp_set_launch(c, params, (hipStream_t)stream));
   m.step = 0;
   return DOLINC_OK;
 }
 
-dolinc_status dolinc_mlp_get(dolinc_ctx c, float* params) {
+dolinc_status dolinc_mlp_get(dolinc_ctx c, float* params, dolinc_stream stream) {
   if (!valid_ctx(c)) return fail(DOLINC_ESTATE, "invalid or destroyed context");
   if (!c->mlp.p) return fail(DOLINC_ESTATE, "dolinc_mlp_set has not been called");
   if (!params) return fail(DOLINC_EINVAL, "NULL output");
-  HIPCHK(hipDeviceSynchronize());
-  HIPCHK(hipMemcpy(params, c->mlp.p, MLP_N * sizeof(float), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpyAsync(params, c->mlp.p, MLP_N * sizeof(float), hipMemcpyDeviceToDevice, (hipStream_t)stream));
   return DOLINC_OK;
 }
 

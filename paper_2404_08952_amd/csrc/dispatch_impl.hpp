@@ -1,8 +1,6 @@
 // Launch-side dispatch from runtime parameters to kernel instantiations.
 // Included once per working type (kernels_f64.hip, kernels_f32.hip).
 #pragma once
-#include <cstdlib>
-
 #include "residual_impl.hpp"
 
 namespace dolinc {
@@ -62,27 +60,15 @@ inline int pde_kind(const dolinc_params& p) {
 }
 
 template <class T, int D, int PK, int SCH, bool BL>
-hipError_t go_flux(const KArgs<T>& a0, size_t lds, hipStream_t s, bool exporting) {
+hipError_t go_flux(const KArgs<T>& a, size_t lds, hipStream_t s, bool exporting) {
   if (exporting) {
-    const unsigned nb = (unsigned)((a0.nf + KTPB - 1) / KTPB);
-    hipLaunchKernelGGL((k_face_export<T, D, PK, SCH, BL>), dim3(nb), dim3(KTPB), 0, s, a0);
+    const unsigned nb = (unsigned)((a.nf + KTPB - 1) / KTPB);
+    hipLaunchKernelGGL((k_face_export<T, D, PK, SCH, BL>), dim3(nb), dim3(KTPB), 0, s, a);
     return hipGetLastError();
   }
-  using FS = FluxStage<T, D, PK, SCH, BL>;
-  KArgs<T> a = a0;
-  const size_t limit = flux_lds_limit();
-  // Rows are gathered straight from HBM/L2 by default: staging the
-  // partition's own rows in LDS (mask bits 1 G1, 4 U and theta) cost more
-  // in occupancy and the extra barrier than it saved on this workload.
-  int mask = 0;
-  if (const char* env = std::getenv("DOLINC_STAGE_MASK")) {  // tuning override (still bounded by the limit)
-    mask = std::atoi(env) & 5;
-  }
-  if (lds + FS::bytes(a.B, mask) > limit) mask = 0;
-  a.stage_mask = mask;
-  const size_t total = lds + FS::bytes(a.B, mask);
-  if (total > limit) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((k_flux<T, D, PK, SCH, BL>), dim3(8 * a.per_xcd), dim3(KTPB), total, s, a);
+  // LDS holds the partition's face fluxes only (rows are gathered from HBM/L2)
+  if (lds > flux_lds_limit()) return hipErrorInvalidConfiguration;
+  hipLaunchKernelGGL((k_flux<T, D, PK, SCH, BL>), dim3(8 * a.per_xcd), dim3(KTPB), lds, s, a);
   return hipGetLastError();
 }
 
@@ -253,12 +239,32 @@ __global__ __launch_bounds__(KTPB) void k_diag(int64_t nc, int nv, int euler, T 
   }
 }
 
+// The partials of k_diag combined in block order into out[nout] (one thread
+// per output; the same order every call, so repeated calls agree bit for bit)
 template <class T>
-hipError_t run_diag(dolinc_ctx_s* c, const void* U, double* part, int nblocks, hipStream_t s) {
+__global__ void k_diag_reduce(int nb, int nv, int euler, const double* __restrict__ part, double* __restrict__ out) {
+  const int k = threadIdx.x;
+  const int nout = nv + 3;
+  if (k >= nout) return;
+  const bool add = k < nv || k == nv + 2;
+  const bool take_min = k == nv || euler;
+  double acc = add ? 0.0 : (take_min ? 1e300 : -1e300);
+  for (int b = 0; b < nb; ++b) {
+    const double x = part[(int64_t)b * nout + k];
+    acc = add ? acc + x : (take_min ? fmin(acc, x) : fmax(acc, x));
+  }
+  out[k] = acc;
+}
+
+template <class T>
+hipError_t run_diag(dolinc_ctx_s* c, const void* U, double* part, int nblocks, double* out, hipStream_t s) {
   const int euler = c->params.pde == DOLINC_EULER;
   // interior cells only (auxiliary rows follow them)
   hipLaunchKernelGGL(k_diag<T>, dim3(nblocks), dim3(KTPB), 0, s, c->n_interior, c->w.nv, euler, (T)c->params.gamma,
                      (const T*)U, c->m.V, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_diag_reduce<T>, dim3(1), dim3(64), 0, s, nblocks, c->w.nv, euler, (const double*)part, out);
   return hipGetLastError();
 }
 

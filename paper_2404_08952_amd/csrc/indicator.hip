@@ -46,7 +46,10 @@ hipError_t grad_features_launch(dolinc_ctx_s* c, const void* U, void* G1, unsign
   return hipGetLastError();
 }
 
-hipError_t mlp_pack_launch(dolinc_ctx_s* c, hipStream_t s) {
+hipError_t mlp_set_launch(dolinc_ctx_s* c, const float* src, hipStream_t s) {
+  hipLaunchKernelGGL(k_mlp_set, dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, s, src, c->mlp.p, c->mlp.m, c->mlp.v);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_mlp_pack, dim3((MLP_H * MLP_H + 255) / 256), dim3(256), 0, s, c->mlp.p, c->mlp.w1b,
                      c->mlp.w2b);
   return hipGetLastError();

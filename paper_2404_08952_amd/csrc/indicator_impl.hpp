@@ -541,6 +541,16 @@ __global__ __launch_bounds__(256) void k_mlp_adam(int nparts, const float* __res
   }
 }
 
+// New parameters: copied from the caller's device array, Adam moments cleared.
+__global__ void k_mlp_set(const float* __restrict__ src, float* __restrict__ p, float* __restrict__ mom,
+                          float* __restrict__ vel) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= MLP_NPARAM) return;
+  p[k] = src[k];
+  mom[k] = 0.f;
+  vel[k] = 0.f;
+}
+
 __global__ void k_mlp_pack(const float* __restrict__ p, unsigned short* __restrict__ w1b,
                            unsigned short* __restrict__ w2b) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;

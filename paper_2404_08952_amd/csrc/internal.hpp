@@ -159,10 +159,10 @@ hipError_t launch_theta(dolinc_ctx_s* c, const void* U, const void* G1, float* t
 hipError_t launch_flux(dolinc_ctx_s* c, const void* Us, const void* Un, void* out, int mode, double alpha,
                        double beta, double dt, hipStream_t s);
 hipError_t launch_face_export(dolinc_ctx_s* c, const void* U, void* UL, void* UR, void* F, hipStream_t s);
-hipError_t launch_diagnostics(dolinc_ctx_s* c, const void* U, double* out_host, hipStream_t s);
 bool flux_supported(const dolinc_params& p, int dim);
 hipError_t features_launch(dolinc_ctx_s* c, const void* U, float* X32, unsigned short* Xb, hipStream_t s);
-hipError_t mlp_pack_launch(dolinc_ctx_s* c, hipStream_t s);
+// network parameters from a device array: copy, Adam moments cleared, bf16 copies
+hipError_t mlp_set_launch(dolinc_ctx_s* c, const float* src, hipStream_t s);
 hipError_t grad_features_launch(dolinc_ctx_s* c, const void* U, void* G1, unsigned short* Xf, hipStream_t s);
 // X rows xstride bf16 wide (24: packed stage features, 32: the API's rows)
 hipError_t mlp_forward_launch(dolinc_ctx_s* c, const unsigned short* X, int64_t n, float* theta, hipStream_t s,

@@ -99,7 +99,7 @@ def test_no_device_is_an_error_not_a_fallback():
     mesh = M.periodic_2d(4, 4, split=1.0)
     d, keep = b.mesh_desc(mesh)
     h = ctypes.c_void_p()
-    st = lib.dolinc_create(ctypes.byref(d), ctypes.byref(h))
+    st = lib.dolinc_create(ctypes.byref(d), None, ctypes.byref(h))
     assert st == b.EHIP
     assert lib.dolinc_residual(ctypes.c_void_p(1), None, None, None) == b.ESTATE
     del keep
