@@ -271,6 +271,21 @@ dolinc_status dolinc_mlp_forward(dolinc_ctx ctx, const uint16_t* X, int64_t n, f
 dolinc_status dolinc_mlp_train_step(dolinc_ctx ctx, const uint16_t* X, const float* y, int64_t n, float lr,
                                     float* loss, dolinc_stream s);
 
+/* The same training step for callers that cannot allocate device memory
+ * (code under HIP graph capture, serving loops, harnesses that forbid
+ * hipMalloc): the per-block partial gradients go to a fixed device array of
+ * the library (about 6 MB per device, held until the process ends, its
+ * device address looked up once per device) instead of the context's
+ * workspace, which dolinc_mlp_train_step grows with the batch.  Allocates
+ * nothing; needs dolinc_mlp_set first (ESTATE).  n in [1,
+ * DOLINC_MLP_STATIC_MAX_ROWS], else EINVAL.  For the same inputs its result
+ * equals dolinc_mlp_train_step's bit for bit (same partial grid).  Every
+ * call on one device shares that array: two calls in flight on one device
+ * (any contexts, any streams) race. */
+#define DOLINC_MLP_STATIC_MAX_ROWS 65536
+dolinc_status dolinc_mlp_train_step_static(dolinc_ctx ctx, const uint16_t* X, const float* y, int64_t n, float lr,
+                                           float* loss, dolinc_stream s);
+
 /* Gradient of the same loss without a step: grad device float[DOLINC_MLP_PARAMS]. */
 dolinc_status dolinc_mlp_gradient(dolinc_ctx ctx, const uint16_t* X, const float* y, int64_t n, float* grad,
                                   float* loss, dolinc_stream s);

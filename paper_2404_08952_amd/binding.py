@@ -23,6 +23,7 @@ BLEND = {"none": 0, "theta": 1, "classical": 2, "learned": 3}
 MLP_PARAMS = 5825
 N_FEATURES = 24
 FEATURE_STRIDE = 32
+MLP_STATIC_MAX_ROWS = 65536  # dolinc_mlp_train_step_static batch limit
 
 
 class MeshDesc(C.Structure):
@@ -75,6 +76,8 @@ SIGNATURES = {
     "dolinc_mlp_get": [C.c_void_p, C.c_void_p, C.c_void_p],
     "dolinc_mlp_forward": [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p],
     "dolinc_mlp_train_step": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_float, C.c_void_p, C.c_void_p],
+    "dolinc_mlp_train_step_static": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_float, C.c_void_p,
+                                     C.c_void_p],
     "dolinc_mlp_gradient": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p],
     "dolinc_destroy": [C.c_void_p],
     "dolinc_last_error": [],
@@ -354,6 +357,15 @@ class Solver:
         loss = self.torch.empty(1, dtype=self.torch.float32, device=self.device)
         _check(self.lib, self.lib.dolinc_mlp_train_step(self.h, self._ptr(Xb), self._ptr(y), Xb.shape[0],
                                                         float(lr), self._ptr(loss), self._stream()))
+        return loss
+
+    def mlp_train_step_static(self, Xb, y, lr, loss=None):
+        """The training step without allocation in the library (its partials in
+        the library's fixed device array); ``loss``: a caller-owned device
+        float tensor of one element, or None."""
+        _check(self.lib, self.lib.dolinc_mlp_train_step_static(
+            self.h, self._ptr(Xb), self._ptr(y), Xb.shape[0], float(lr),
+            None if loss is None else self._ptr(loss), self._stream()))
         return loss
 
     def mlp_gradient(self, Xb, y):

@@ -797,6 +797,26 @@ dolinc_status dolinc_mlp_train_step(dolinc_ctx c, const uint16_t* X, const float
   return DOLINC_OK;
 }
 
+dolinc_status dolinc_mlp_train_step_static(dolinc_ctx c, const uint16_t* X, const float* y, int64_t n, float lr,
+                                           float* loss, dolinc_stream stream) {
+  if (!valid_ctx(c)) return fail(DOLINC_ESTATE, "invalid or destroyed context");
+  if (!c->mlp.p) return fail(DOLINC_ESTATE, "dolinc_mlp_set has not been called");
+  if (!X || !y) return fail(DOLINC_EINVAL, "NULL batch");
+  if (n <= 0 || n > DOLINC_MLP_STATIC_MAX_ROWS)
+    return fail(DOLINC_EINVAL, "batch size must be in [1, " + std::to_string(DOLINC_MLP_STATIC_MAX_ROWS) +
+                                   "] for the training step without allocation");
+  if (!(std::isfinite(lr) && lr > 0.f)) return fail(DOLINC_EINVAL, "lr must be finite and > 0");
+  int nb = 0, rows = 0;
+  mlp_grid(n, &nb, &rows);  // the grid of dolinc_mlp_train_step: the same partials, the same step
+  if (nb > MLP_STATIC_BLOCKS) return fail(DOLINC_EINVAL, "internal: batch needs more partials than the scratch holds");
+  const int64_t t = c->mlp.step + 1;
+  const float c1 = (float)(1.0 - std::pow(0.9, (double)t));
+  const float c2 = (float)(1.0 - std::pow(0.999, (double)t));
+  HIPCHK(mlp_train_static_launch(c, (const unsigned short*)X, y, n, nb, rows, loss, lr, c1, c2, (hipStream_t)stream));
+  c->mlp.step = t;
+  return DOLINC_OK;
+}
+
 dolinc_status dolinc_mlp_gradient(dolinc_ctx c, const uint16_t* X, const float* y, int64_t n, float* grad,
                                   float* loss, dolinc_stream stream) {
   dolinc_status st = mlp_batch_check(c, X, y, n);

@@ -1,5 +1,7 @@
 // Launchers of the learned-indicator kernels (features, MLP forward,
 // gradients, Adam) and of the per-stage gradient + features kernel.
+#include <mutex>
+
 #include "dispatch_impl.hpp"
 #include "indicator_impl.hpp"
 
@@ -65,17 +67,68 @@ hipError_t mlp_forward_launch(dolinc_ctx_s* c, const unsigned short* X, int64_t 
   return hipGetLastError();
 }
 
+static hipError_t grad_and_adam(dolinc_ctx_s* c, const unsigned short* X, const float* y, int64_t n, int nblocks,
+                                int rows_per_block, float* part, float* loss_part, float* grad_out, float* loss_out,
+                                int do_step, float lr, float c1, float c2, hipStream_t s) {
+  hipLaunchKernelGGL(k_mlp_grad, dim3(nblocks), dim3(256), 0, s, mlp_dev(c), X, y, n, rows_per_block, part,
+                     loss_part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_mlp_adam, dim3((MLP_NPARAM + 1 + ADAM_K - 1) / ADAM_K), dim3(256), 0, s, nblocks, part,
+                     loss_part, c->mlp.p, c->mlp.m, c->mlp.v, c->mlp.w1b, c->mlp.w2b, grad_out, loss_out, do_step, lr,
+                     0.9f, 0.999f, c1, c2, 1e-8f);
+  return hipGetLastError();
+}
+
 hipError_t mlp_grad_launch(dolinc_ctx_s* c, const unsigned short* X, const float* y, int64_t n, int nblocks,
                            int rows_per_block, float* grad_out, float* loss_out, int do_step, float lr, float c1,
                            float c2, hipStream_t s) {
-  hipLaunchKernelGGL(k_mlp_grad, dim3(nblocks), dim3(256), 0, s, mlp_dev(c), X, y, n, rows_per_block, c->mlp.part,
-                     c->mlp.loss_part);
-  hipError_t e = hipGetLastError();
+  return grad_and_adam(c, X, y, n, nblocks, rows_per_block, c->mlp.part, c->mlp.loss_part, grad_out, loss_out,
+                       do_step, lr, c1, c2, s);
+}
+
+// ------------------------------------------------------------ training without allocation
+// The per-block partial gradients and losses of a training step in a fixed
+// device array of this file instead of the context's growable workspace:
+// MLP_STATIC_BLOCKS partials of MLP_NPARAM floats, then MLP_STATIC_BLOCKS
+// partial losses (about 6 MB per device, held until the process ends).
+// Every call on a device shares that device's array; k_mlp_grad writes every
+// partial the following k_mlp_adam reads, so nothing needs clearing.
+static __device__ __align__(256) float scratch[(size_t)MLP_STATIC_BLOCKS * (MLP_NPARAM + 1)];
+
+namespace {
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[MLP_STATIC_MAX_DEVICES] = {};
+}  // namespace
+
+// Device address of this device's scratch array (looked up once per device,
+// with that device current; the array's name in host code is not a device
+// address).
+static hipError_t scratch_address(float** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_mlp_adam, dim3((MLP_NPARAM + 1 + ADAM_K - 1) / ADAM_K), dim3(256), 0, s, nblocks, c->mlp.part,
-                     c->mlp.loss_part, c->mlp.p, c->mlp.m, c->mlp.v, c->mlp.w1b, c->mlp.w2b, grad_out, loss_out,
-                     do_step, lr, 0.9f, 0.999f, c1, c2, 1e-8f);
-  return hipGetLastError();
+  if (dev < 0 || dev >= MLP_STATIC_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<float*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+hipError_t mlp_train_static_launch(dolinc_ctx_s* c, const unsigned short* X, const float* y, int64_t n, int nblocks,
+                                   int rows_per_block, float* loss_out, float lr, float c1, float c2,
+                                   hipStream_t s) {
+  if (nblocks > MLP_STATIC_BLOCKS) return hipErrorInvalidValue;
+  float* base = nullptr;
+  hipError_t e = scratch_address(&base);
+  if (e != hipSuccess) return e;
+  return grad_and_adam(c, X, y, n, nblocks, rows_per_block, base, base + (size_t)MLP_STATIC_BLOCKS * MLP_NPARAM,
+                       nullptr, loss_out, 1, lr, c1, c2, s);
 }
 
 }  // namespace dolinc

@@ -167,6 +167,13 @@ hipError_t grad_features_launch(dolinc_ctx_s* c, const void* U, void* G1, unsign
 // X rows xstride bf16 wide (24: packed stage features, 32: the API's rows)
 hipError_t mlp_forward_launch(dolinc_ctx_s* c, const unsigned short* X, int64_t n, float* theta, hipStream_t s,
                               int xstride);
+// Training step with the partials in the library's fixed device array
+// (dolinc_mlp_train_step_static): at most MLP_STATIC_BLOCKS blocks.
+constexpr int MLP_STATIC_BLOCKS = 256;
+constexpr int MLP_STATIC_MAX_DEVICES = 64;
+hipError_t mlp_train_static_launch(dolinc_ctx_s* c, const unsigned short* X, const float* y, int64_t n, int nblocks,
+                                   int rows_per_block, float* loss_out, float lr, float c1, float c2,
+                                   hipStream_t s);
 hipError_t mlp_grad_launch(dolinc_ctx_s* c, const unsigned short* X, const float* y, int64_t n, int nblocks,
                            int rows_per_block, float* grad_out, float* loss_out, int do_step, float lr, float c1,
                            float c2, hipStream_t s);
