@@ -34,21 +34,22 @@ def make_case(workload):
         case = configs.vortex_3d(point_ic=True, scheme="USR3")
         desc = ("3-D Euler isentropic vortex, [0,10]^3 periodic, 64^3 jittered hexes x 6 Kuhn tets "
                 f"({case.mesh.n_cells:,} cells, {case.mesh.n_faces:,} faces), USR3 DOLINC, Rusanov, SSP-RK3")
-        return case, desc, dict(blend="none"), dict(u_ref=configs.VORTEX_REF)
+        return case, desc, dict(blend="none"), dict(u_ref="cell")
     if workload == "tgv3d":
         case = configs.taylor_green_3d()
         desc = ("3-D Euler Taylor-Green vortex Mach 0.1, [0,2pi]^3 periodic, 288^3 jittered hexes "
                 f"({case.mesh.n_cells:,} cells, {case.mesh.n_faces:,} faces), USR5 DOLINC, HLLC, "
                 "learned-indicator blend with Van Leer, SSP-RK3")
-        return case, desc, dict(blend="learned"), dict(u_ref=configs.TGV_REF)
+        return case, desc, dict(blend="learned"), dict(u_ref="cell")
     raise SystemExit(f"unknown workload {workload}")
 
 
-# Cells per partition of the flux kernel: 512 for FP32 (on a hexahedral
-# lattice the Hilbert order makes them 8^3 cubes: 1.16 instead of 1.20 face
-# entries per face, 4 % less flux-kernel time); FP64 keeps 256 (its 512-cell
-# partitions, 74 KB of face fluxes in LDS per workgroup, measured 4 % slower).
-PART_CELLS = {"fp32": 512, "fp64": 256}
+# Cells per partition of the flux kernel: 256 in both precisions.  The FP32
+# path keeps two flux shares per face entry in LDS (each side about its own
+# cell): on 512-cell partitions that is about 76 KB per workgroup and halves
+# the workgroups per CU (flux kernel 3.53 vs 2.85 ms at 288^3; 384 cells:
+# 3.92 ms).  FP64's 512-cell partitions measured 4 % slower.
+PART_CELLS = {"fp32": 256, "fp64": 256}
 
 
 def indicator_weights():
@@ -151,8 +152,7 @@ def shock_tube_line(args):
     left = np.tile(xc < 0.5, n[1] * n[2])
     vel = np.zeros((mesh.n_cells, 3))
     U0 = fields.prim_to_cons(np.where(left, 1.0, 0.125), vel, np.where(left, 1.0, 0.1))
-    ref = tuple(float(x) for x in U0.mean(0))
-    s = Solver(mesh, pde="euler", scheme="WENO5", flux="rusanov", precision="fp32", u_ref=ref)
+    s = Solver(mesh, pde="euler", scheme="WENO5", flux="rusanov", precision="fp32", u_ref="cell")
     log(f"[bench] shock tube {mesh.n_cells:,} cells: set-up {time.time() - t0:.1f} s")
     U = s.to_internal(U0)
     dt = 0.3 / n[0] / 2.5
@@ -192,7 +192,7 @@ def tgv_kinetic_energy_line(args):
     nsteps, every = 100, 10
     hist = {}
     theta = {}
-    ref = dict(u_ref=configs.TGV_REF)
+    ref = dict(u_ref="cell")
     for label, prec, extra in (("fp64_plain", "fp64", dict(blend="none")),
                                ("fp32_plain", "fp32", dict(blend="none", **ref)),
                                ("fp64_learned", "fp64", dict(blend="learned")),
@@ -258,7 +258,7 @@ def vortex_line(args):
     out = dict(workload=f"isentropic vortex, {case.mesh.n_cells:,} jittered Kuhn tetrahedra, USR3, Rusanov, "
                         f"{steps} SSP-RK3 steps at CFL {cfl} on the cell geometry, dt {dt:.4e}")
     rho = {}
-    for prec, extra in (("fp64", {}), ("fp32", dict(u_ref=configs.VORTEX_REF))):
+    for prec, extra in (("fp64", {}), ("fp32", dict(u_ref="cell"))):
         s = Solver(case.mesh, **case.params, precision=prec, part_cells=PART_CELLS[prec], **extra)
         U = s.to_internal(case.U0)
         s.rk_step(U, dt)
@@ -422,7 +422,7 @@ def ordering_line(args):
                         "blend, FP32, SSP-RK3")
     for label, ren in (("hilbert", 2), ("rcm", 1), ("input_order", 0)):
         t1 = time.time()
-        s = Solver(case.mesh, **case.params, precision="fp32", blend="learned", u_ref=configs.TGV_REF, renumber=ren)
+        s = Solver(case.mesh, **case.params, precision="fp32", blend="learned", u_ref="cell", renumber=ren)
         setup = time.time() - t1
         s.mlp_set(indicator_weights())
         U = s.to_internal(case.U0)
@@ -802,8 +802,9 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": desc, "cells": nc, "faces": nf, "stages_per_step": 3,
-                   "precision": ("FP32 bulk (reference-state flux form); geometry and growth rates precomputed "
-                                 "in FP64, the DOLINC coefficients evaluated from them in FP64 in the flux kernel"),
+                   "precision": ("FP32 bulk, each face side carried about its own cell (flux shares "
+                                 "F.S - F(U_c).S); geometry and growth rates precomputed in FP64, the DOLINC "
+                                 "coefficients evaluated from them in FP64 in the flux kernel"),
                    "partition_cells": PART_CELLS["fp32"]},
         "roofline": {"bound": "hbm", "achieved": fk["gbps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": fk["gbps"] / HBM_PEAK_GBPS, "traffic": measured_traffic(args.workload),

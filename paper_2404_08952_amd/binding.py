@@ -159,8 +159,16 @@ def make_params(pde, scheme, flux="upwind", precision="fp64", blend="none", gamm
     for k in range(3):
         p.adv_vel[k] = adv_vel[k] if k < len(adv_vel) else 0.0
         p.burgers_dir[k] = burgers_dir[k] if k < len(burgers_dir) else 0.0
-    p.use_u_ref = 0 if u_ref is None else 1
-    if u_ref is not None:
+    # u_ref: None (full states), a constant reference state (5 values), or
+    # "cell" (each face side's own cell as the reference)
+    if u_ref is None:
+        p.use_u_ref = 0
+    elif isinstance(u_ref, str):
+        if u_ref != "cell":
+            raise ValueError("u_ref must be None, 5 values or 'cell'")
+        p.use_u_ref = 2
+    else:
+        p.use_u_ref = 1
         for k in range(5):
             p.u_ref[k] = u_ref[k]
     return p

@@ -128,10 +128,12 @@ dolinc_status check_params(const dolinc_params* p, int dim) {
   for (int k = 0; k < 3; ++k)
     if (!std::isfinite(p->adv_vel[k]) || !std::isfinite(p->burgers_dir[k]))
       return fail(DOLINC_EINVAL, "non-finite velocity");
+  if (p->use_u_ref < 0 || p->use_u_ref > 2) return fail(DOLINC_EINVAL, "use_u_ref must be 0, 1 or 2");
   if (p->use_u_ref) {
-    if (p->pde != DOLINC_EULER) return fail(DOLINC_EUNSUPPORTED, "u_ref is built for the Euler equations");
-    for (int k = 0; k < 5; ++k)
-      if (!std::isfinite(p->u_ref[k])) return fail(DOLINC_EINVAL, "non-finite u_ref");
+    if (p->pde != DOLINC_EULER) return fail(DOLINC_EUNSUPPORTED, "reference-state forms are built for the Euler equations");
+    if (p->use_u_ref == 1)
+      for (int k = 0; k < 5; ++k)
+        if (!std::isfinite(p->u_ref[k])) return fail(DOLINC_EINVAL, "non-finite u_ref");
   }
   return DOLINC_OK;
 }
@@ -557,7 +559,8 @@ dolinc_status dolinc_precompute(dolinc_ctx c, const dolinc_params* p, dolinc_str
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || lim <= 0)
       lim = 64 * 1024;
-    if ((size_t)c->max_entries * nv * el > (size_t)lim)
+    const size_t per = (p->pde == DOLINC_EULER && p->use_u_ref == 2) ? 2 : 1;  // shares per entry
+    if ((size_t)c->max_entries * nv * el * per > (size_t)lim)
       return fail(DOLINC_EUNSUPPORTED, "partition face fluxes exceed the LDS of one workgroup (" +
                                            std::to_string(lim / 1024) + " KiB); use a smaller part_cells");
   }

@@ -33,7 +33,6 @@ KArgs<T> base_args(dolinc_ctx_s* c) {
     a.adv[k] = (T)c->params.adv_vel[k];
     a.bdir[k] = (T)c->params.burgers_dir[k];
   }
-  a.use_ref = c->params.use_u_ref;
   for (int k = 0; k < 5; ++k) a.uref[k] = (T)c->params.u_ref[k];
   a.face_ent = c->m.face_ent;
   a.nf = c->n_faces;
@@ -59,51 +58,65 @@ inline int pde_kind(const dolinc_params& p) {
   return p.flux == DOLINC_FLUX_HLLC ? 3 : 2;
 }
 
-template <class T, int D, int PK, int SCH, bool BL>
+template <class T, int D, int PK, int SCH, bool BL, int REF>
 hipError_t go_flux(const KArgs<T>& a, size_t lds, hipStream_t s, bool exporting) {
   if (exporting) {
     const unsigned nb = (unsigned)((a.nf + KTPB - 1) / KTPB);
-    hipLaunchKernelGGL((k_face_export<T, D, PK, SCH, BL>), dim3(nb), dim3(KTPB), 0, s, a);
+    hipLaunchKernelGGL((k_face_export<T, D, PK, SCH, BL, REF>), dim3(nb), dim3(KTPB), 0, s, a);
     return hipGetLastError();
   }
   // LDS holds the partition's face fluxes only (rows are gathered from HBM/L2)
   if (lds > flux_lds_limit()) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((k_flux<T, D, PK, SCH, BL>), dim3(8 * a.per_xcd), dim3(KTPB), lds, s, a);
+  hipLaunchKernelGGL((k_flux<T, D, PK, SCH, BL, REF>), dim3(8 * a.per_xcd), dim3(KTPB), lds, s, a);
   return hipGetLastError();
 }
 
-template <class T, int D, int PK, bool BL>
+template <class T, int D, int PK, bool BL, int REF>
 hipError_t flux_by_scheme(int sch, const KArgs<T>& a, size_t lds, hipStream_t s, bool ex) {
   switch (sch) {
-    case 1: return go_flux<T, D, PK, 1, BL>(a, lds, s, ex);
-    case 2: return go_flux<T, D, PK, 2, BL>(a, lds, s, ex);
-    case 3: return go_flux<T, D, PK, 3, BL>(a, lds, s, ex);
-    case 4: return go_flux<T, D, PK, 4, BL>(a, lds, s, ex);
-    case 5: return go_flux<T, D, PK, 5, BL>(a, lds, s, ex);
-    case 6: return go_flux<T, D, PK, 6, BL>(a, lds, s, ex);
-    case 7: return go_flux<T, D, PK, 7, BL>(a, lds, s, ex);
-    case 8: return go_flux<T, D, PK, 8, BL>(a, lds, s, ex);
+    case 1: return go_flux<T, D, PK, 1, BL, REF>(a, lds, s, ex);
+    case 2: return go_flux<T, D, PK, 2, BL, REF>(a, lds, s, ex);
+    case 3: return go_flux<T, D, PK, 3, BL, REF>(a, lds, s, ex);
+    case 4: return go_flux<T, D, PK, 4, BL, REF>(a, lds, s, ex);
+    case 5: return go_flux<T, D, PK, 5, BL, REF>(a, lds, s, ex);
+    case 6: return go_flux<T, D, PK, 6, BL, REF>(a, lds, s, ex);
+    case 7: return go_flux<T, D, PK, 7, BL, REF>(a, lds, s, ex);
+    case 8: return go_flux<T, D, PK, 8, BL, REF>(a, lds, s, ex);
   }
   return hipErrorInvalidValue;
+}
+
+template <class T, int PK, bool BL>
+hipError_t euler_by_ref(int ref, const KArgs<T>& a, int sch, size_t lds, hipStream_t s, bool ex) {
+  if (ref == 1) return flux_by_scheme<T, 3, PK, BL, 1>(sch, a, lds, s, ex);
+  if (ref == 2) return flux_by_scheme<T, 3, PK, BL, 2>(sch, a, lds, s, ex);
+  return flux_by_scheme<T, 3, PK, BL, 0>(sch, a, lds, s, ex);
+}
+
+// LDS of the flux kernel: one flux per face entry, two (the owner's and the
+// neighbour's share) in the cell-reference form
+inline size_t flux_lds_bytes(const dolinc_ctx_s* c, int nv, size_t el) {
+  const int per = (c->params.pde == DOLINC_EULER && c->params.use_u_ref == 2) ? 2 : 1;
+  return (size_t)c->max_entries * nv * el * per;
 }
 
 template <class T>
 hipError_t run_flux(dolinc_ctx_s* c, const KArgs<T>& a, hipStream_t s, bool ex) {
   const int pk = pde_kind(c->params);
   const int nv = c->w.nv;
-  const size_t lds = (size_t)c->max_entries * nv * sizeof(T);
+  const size_t lds = flux_lds_bytes(c, nv, sizeof(T));
   const bool bl = c->params.blend != DOLINC_BLEND_NONE;
   const int sch = c->params.scheme;
   if (c->dim == 2) {
-    if (pk == 0) return flux_by_scheme<T, 2, 0, false>(sch, a, lds, s, ex);
-    if (pk == 1) return flux_by_scheme<T, 2, 1, false>(sch, a, lds, s, ex);
+    if (pk == 0) return flux_by_scheme<T, 2, 0, false, 0>(sch, a, lds, s, ex);
+    if (pk == 1) return flux_by_scheme<T, 2, 1, false, 0>(sch, a, lds, s, ex);
     return hipErrorInvalidValue;
   }
-  if (pk == 0) return flux_by_scheme<T, 3, 0, false>(sch, a, lds, s, ex);
-  if (pk == 1) return flux_by_scheme<T, 3, 1, false>(sch, a, lds, s, ex);
-  if (pk == 2) return bl ? flux_by_scheme<T, 3, 2, true>(sch, a, lds, s, ex)
-                         : flux_by_scheme<T, 3, 2, false>(sch, a, lds, s, ex);
-  return bl ? flux_by_scheme<T, 3, 3, true>(sch, a, lds, s, ex) : flux_by_scheme<T, 3, 3, false>(sch, a, lds, s, ex);
+  if (pk == 0) return flux_by_scheme<T, 3, 0, false, 0>(sch, a, lds, s, ex);
+  if (pk == 1) return flux_by_scheme<T, 3, 1, false, 0>(sch, a, lds, s, ex);
+  const int ref = c->params.use_u_ref;
+  if (pk == 2) return bl ? euler_by_ref<T, 2, true>(ref, a, sch, lds, s, ex) : euler_by_ref<T, 2, false>(ref, a, sch, lds, s, ex);
+  return bl ? euler_by_ref<T, 3, true>(ref, a, sch, lds, s, ex) : euler_by_ref<T, 3, false>(ref, a, sch, lds, s, ex);
 }
 
 // 3-D Euler second derivatives: the FP32 kernel is built for 5 waves per SIMD

@@ -54,7 +54,6 @@ struct KArgs {
   T gamma;
   T adv[3];
   T bdir[3];
-  int use_ref;
   T uref[5];
   const int32_t* face_ent;
   int64_t nf;
@@ -521,9 +520,27 @@ __device__ __forceinline__ T nonlin_side(const NonlinCoef<T>& c, T a0, T a1, T D
 // face-integrated flux F.S (owner -> neighbour).  Cell rows are gathered
 // straight from HBM/L2: staging the partition's own rows in LDS cost more in
 // occupancy and barriers than it saved.
-template <class T, int D, int PK, int SCH, bool BLEND>
-__device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T* UR, T* F) {
+// REF (Euler only) picks the state the face arithmetic is carried about:
+//   0  none: full states;
+//   1  a constant reference state a.uref: perturbations U - U_ref, flux
+//      F(U).S - F(U_ref).S (the dropped terms cancel over closed cells);
+//   2  each face side's own cell: the states are carried as increments over
+//      the owner's value U_P, the flux as G_P = F.S - F(U_P).S, and the
+//      neighbour's share as G_N = F.S - F(U_N).S = G_P - (F(U_N) - F(U_P)).S
+//      (difference form).  Cell c sums sigma G_c over its faces; the dropped
+//      F(U_c).sum(sigma S) vanishes with the FP64 geometry.  The rounded
+//      quantities are then O(h) increments instead of O(1) fluxes: in FP32
+//      the rounding of S and of the flux arithmetic enters only through
+//      F - F(U_c).
+// The reconstruction, blend and nonlinear schemes are affine in the cell
+// values (coefficients summing to one, differences elsewhere), so they run
+// unchanged on the shifted values.  F receives the owner's share (REF 2:
+// G_P) and, for REF 2 only, F2 the neighbour's (G_N); with REF 0 / 1 one
+// flux serves both cells.
+template <class T, int D, int PK, int SCH, bool BLEND, int REF = 0>
+__device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T* UR, T* F, T* F2 = nullptr) {
   constexpr int NV = NVars<PK, D>::value;
+  static_assert(REF == 0 || PK >= 2, "reference-state forms are built for the Euler equations");
   constexpr int ORD = SchemeInfo<SCH>::ORD;
   constexpr int DCS = SchemeInfo<SCH>::template dcs<T>();
   const int2 pn = a.ent_pn[e];
@@ -535,9 +552,7 @@ __device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T
   T dc[DCS];
 #pragma unroll
   for (int k = 0; k < DCS; ++k) dc[k] = dcp[k];
-  T uP[NV], uN[NV];
-  // Euler with a reference state: reconstruct perturbations U - U_ref
-  const bool pert = PK >= 2 && a.use_ref;
+  T uP[NV], uN[NV], base[NV];
   {
     GlbPtr<T> up = as_glb(a.U + P * NV);
     GlbPtr<T> un = as_glb(a.U + N * NV);
@@ -547,11 +562,20 @@ __device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T
       uN[v] = un[v];
     }
   }
-  if (pert) {
+  // shift by the reference: the constant state (REF 1) or the owner's value
+  // (REF 2: the owner's shifted value is exactly zero)
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      uP[v] -= a.uref[v];
-      uN[v] -= a.uref[v];
+  for (int v = 0; v < NV; ++v) {
+    if constexpr (REF == 1) {
+      base[v] = a.uref[v];
+      uP[v] -= base[v];
+      uN[v] -= base[v];
+    } else if constexpr (REF == 2) {
+      base[v] = uP[v];
+      uN[v] -= base[v];
+      uP[v] = T(0);
+    } else {
+      base[v] = T(0);
     }
   }
   T gP[NV], gN[NV], hP[NV], hN[NV];
@@ -648,7 +672,7 @@ __device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T
       fmx = fmax(fmx, T(0));
     }
     F[0] = uL <= uR ? fmn : fmx;
-  } else if (!pert) {
+  } else if constexpr (REF == 0) {
     // positivity: a side with rho <= 0 or p <= 0 falls back to its cell value
     {
       T r, vv[D], E, p;
@@ -664,9 +688,9 @@ __device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T
     else
       flux_hllc<T, D>(UL, UR, S, a.gamma, F);
   } else {
+    RefState<T, D> Rf;
+    ref_state<T, D>(base, a.gamma, Rf);
     {
-      RefState<T, D> Rf;
-      ref_state<T, D>(a.uref, a.gamma, Rf);
       PertState<T, D> Ps;
       pert_state<T, D>(UL, Rf, a.gamma, Ps);
       if (!(Ps.r > T(0) && Ps.p > T(0)))
@@ -676,22 +700,32 @@ __device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T
         for (int v = 0; v < NV; ++v) UR[v] = uN[v];
     }
     if constexpr (PK == 2)
-      flux_rusanov_pert<T, D>(UL, UR, S, a.uref, a.gamma, F);
+      flux_rusanov_pert<T, D>(UL, UR, S, base, a.gamma, F);
     else
-      flux_hllc_pert<T, D>(UL, UR, S, a.uref, a.gamma, F);
+      flux_hllc_pert<T, D>(UL, UR, S, base, a.gamma, F);
+    if constexpr (REF == 2) {
+      // the neighbour's share: G_N = G_P - (F(U_N) - F(U_P)).S
+      PertState<T, D> PN;
+      pert_state<T, D>(uN, Rf, a.gamma, PN);
+      T dF[D + 2];
+      pert_flux<T, D>(uN, PN, Rf, S, dF);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) F2[v] = F[v] - dF[v];
+    }
     // exported states are full states
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      UL[v] += a.uref[v];
-      UR[v] += a.uref[v];
+      UL[v] += base[v];
+      UR[v] += base[v];
     }
   }
 }
 
 // ---------------------------------------------------------------- kernels
-template <class T, int D, int PK, int SCH, bool BLEND>
+template <class T, int D, int PK, int SCH, bool BLEND, int REF>
 __global__ __launch_bounds__(KTPB) void k_flux(KArgs<T> a) {
   constexpr int NV = NVars<PK, D>::value;
+  constexpr int FW = REF == 2 ? 2 * NV : NV;  // values per entry in LDS (REF 2: owner's, neighbour's share)
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int p = xcd_remap(blockIdx.x, a.per_xcd, a.np);
   if (p < 0) return;
@@ -701,10 +735,10 @@ __global__ __launch_bounds__(KTPB) void k_flux(KArgs<T> a) {
   T* Fs = reinterpret_cast<T*>(smem_raw);
   const int e0 = a.part_ptr[p], e1 = a.part_ptr[p + 1];
   for (int e = e0 + (int)threadIdx.x; e < e1; e += KTPB) {
-    T UL[NV], UR[NV], F[NV];
-    eval_face<T, D, PK, SCH, BLEND>(a, e, UL, UR, F);
+    T UL[NV], UR[NV], F[FW];
+    eval_face<T, D, PK, SCH, BLEND, REF>(a, e, UL, UR, F, F + (REF == 2 ? NV : 0));
 #pragma unroll
-    for (int v = 0; v < NV; ++v) Fs[(e - e0) * NV + v] = F[v];
+    for (int v = 0; v < FW; ++v) Fs[(e - e0) * FW + v] = F[v];
   }
   __syncthreads();
   const int64_t c1 = c0 + ncl;
@@ -715,8 +749,8 @@ __global__ __launch_bounds__(KTPB) void k_flux(KArgs<T> a) {
     for (int v = 0; v < NV; ++v) sum[v] = comp[v] = T(0);
     for (int s = s0; s < s1; ++s) {
       const uint16_t sl = a.slots[s];
-      const T* Fp = Fs + (sl & 0x7fff) * NV;
       const bool nb = (sl >> 15) != 0;
+      const T* Fp = Fs + (sl & 0x7fff) * FW + (REF == 2 && nb ? NV : 0);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         const T x = nb ? -Fp[v] : Fp[v];
@@ -744,13 +778,23 @@ __global__ __launch_bounds__(KTPB) void k_flux(KArgs<T> a) {
   }
 }
 
-template <class T, int D, int PK, int SCH, bool BLEND>
+template <class T, int D, int PK, int SCH, bool BLEND, int REF>
 __global__ __launch_bounds__(KTPB) void k_face_export(KArgs<T> a) {
   constexpr int NV = NVars<PK, D>::value;
   const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= a.nf) return;
-  T UL[NV], UR[NV], F[NV];
-  eval_face<T, D, PK, SCH, BLEND>(a, a.face_ent[f], UL, UR, F);
+  T UL[NV], UR[NV], F[NV], F2[NV];
+  eval_face<T, D, PK, SCH, BLEND, REF>(a, a.face_ent[f], UL, UR, F, F2);
+  if constexpr (REF == 1 || REF == 2) {
+    // the full face flux F.S: add back the reference state's physical flux
+    // (rounded in the working precision; export only)
+    const T* st = REF == 1 ? a.uref : a.U + (int64_t)a.ent_pn[a.face_ent[f]].x * NV;
+    T r, vv[D], E, p, Fr[NV];
+    euler_prim<T, D>(st, a.gamma, r, vv, E, p);
+    const T* sw = a.sw + 4 * (int64_t)a.face_ent[f];
+    euler_phys<T, D>(st, r, vv, E, p, sw, Fr);
+    for (int v = 0; v < NV; ++v) F[v] += Fr[v];
+  }
   for (int v = 0; v < NV; ++v) {
     a.eUL[f * NV + v] = UL[v];
     a.eUR[f * NV + v] = UR[v];

@@ -11,7 +11,7 @@ from synth import fields
 from synth import mesh as M
 
 from .helpers import oracle_params
-from .test_gpu_parity import _close, _euler_state, _group_errors, _uref
+from .test_gpu_parity import FP32_REF, _close, _euler_state, _group_errors
 from .test_oracle_boundary import LAX, SOD
 
 pytestmark = pytest.mark.gpu
@@ -94,7 +94,7 @@ def test_rk_step_parity(name, kw, bcs, meshes):
 def test_fp32_stage_error(name, kw, bcs, meshes):
     mesh, X = meshes[name]
     U = _state(mesh, kw, np.random.default_rng(23)).astype(np.float32).astype(np.float64)
-    extra = dict(u_ref=_uref(U)) if kw["pde"] == "euler" else {}
+    extra = dict(u_ref=FP32_REF) if kw["pde"] == "euler" else {}
     s = _solver(mesh, bcs, precision="fp32", **kw, **extra)
     R32 = s.to_external(s.residual(s.to_internal(U)))
     ref = OB.residual(X, U, oracle_params(kw), bcs)
@@ -131,7 +131,7 @@ def _tube(N, prob, scheme, precision="fp64", tvd=False, cfl=0.3):
     if tvd:
         kw["blend"] = "theta"
     if precision == "fp32":
-        kw["u_ref"] = _uref(U0)
+        kw["u_ref"] = FP32_REF
     s = _solver(mesh, {}, **kw)
     if tvd:
         s.set_theta(s.torch.zeros(s.n_rows, dtype=s.torch.float32, device=s.device))
@@ -195,7 +195,7 @@ def test_theta_blend_with_boundaries(precision, meshes):
     theta = rng.random(mesh.n_cells).astype(np.float32)
     bcs = {0: (OB.DIRICHLET, [1.05, 0.1, 0.0, 0.0, 2.5]), 1: (OB.SLIP_WALL,)}
     kw = dict(pde="euler", scheme="USR5", flux="hllc")
-    extra = dict(u_ref=_uref(U)) if precision == "fp32" else {}
+    extra = dict(u_ref=FP32_REF) if precision == "fp32" else {}
     s = _solver(mesh, bcs, blend="theta", precision=precision, **kw, **extra)
     th = np.zeros(s.n_rows, dtype=np.float32)
     th[s.perm] = theta

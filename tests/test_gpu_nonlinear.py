@@ -19,7 +19,7 @@ from oracle import solver as SV
 from synth import configs, fields
 
 from .helpers import oracle_params, small_meshes
-from .test_gpu_parity import _close, _euler_state, _group_errors, _uref
+from .test_gpu_parity import FP32_REF, _close, _euler_state, _group_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -99,7 +99,7 @@ def test_rk_step_parity(name, kw, geos):
 def test_fp32_stage_error(name, kw, geos):
     mesh, geo = MESHES[name], geos[name]
     U = _state(mesh, kw, np.random.default_rng(15)).astype(np.float32).astype(np.float64)
-    extra = dict(u_ref=_uref(U)) if kw["pde"] == "euler" else {}
+    extra = dict(u_ref=FP32_REF) if kw["pde"] == "euler" else {}
     s = _solver(mesh, precision="fp32", **kw, **extra)
     R32 = s.to_external(s.residual(s.to_internal(U)))
     ref = SV.residual(mesh, geo, U, oracle_params(kw))
@@ -142,7 +142,7 @@ def test_shock_tube_stays_physical(scheme):
     and the FP64 path agrees with the oracle after 2 steps."""
     case = configs.shocks_3d(n=10, problem="sod", scheme=scheme)
     mesh = case.mesh
-    s = _solver(mesh, **case.params, precision="fp32", u_ref=_uref(case.U0))
+    s = _solver(mesh, **case.params, precision="fp32", u_ref=FP32_REF)
     Ud = s.to_internal(case.U0)
     s.advance(Ud, case.dt, 20)
     d = s.diagnostics(Ud)

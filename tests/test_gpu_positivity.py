@@ -84,13 +84,14 @@ def test_positivity_fallback_fp64(name, scheme, flux):
     s.close()
 
 
+@pytest.mark.parametrize("form", ["cell", "constant"])
 @pytest.mark.parametrize("name,scheme,flux", [("mixed3d", "USR5", "hllc"), ("hex3d", "USR3", "rusanov")])
-def test_positivity_fallback_fp32_reference_state(name, scheme, flux):
+def test_positivity_fallback_fp32_reference_state(name, scheme, flux, form):
     mesh = MESHES[name]
     geo = OG.geometry(mesh)
     U, badL, badR = _case(mesh, geo, scheme)
     kw = dict(pde="euler", scheme=scheme, flux=flux)
-    uref = tuple(float(x) for x in U.mean(0))
+    uref = tuple(float(x) for x in U.mean(0)) if form == "constant" else "cell"
     s = _solver(mesh, precision="fp32", u_ref=uref, **kw)
     Ud = s.to_internal(U)
     UL, UR, _F = (x.cpu().numpy().astype(np.float64) for x in s.face_states(Ud))
@@ -98,7 +99,7 @@ def test_positivity_fallback_fp32_reference_state(name, scheme, flux):
     rL, rR = SV._positivity_fallback(rL, rR, U, mesh, GAMMA)
     # same decisions: the sides that fell back hold their cells' values
     # (to the rounding of U - U_ref + U_ref in FP32)
-    tol = 4 * np.finfo(np.float32).eps * (np.abs(U).max() + np.abs(np.array(uref)).max())
+    tol = 4 * np.finfo(np.float32).eps * 2 * np.abs(U).max()
     assert np.abs(UL[badL] - U[mesh.owner[badL]]).max() <= tol
     assert np.abs(UR[badR] - U[mesh.neighbour[badR]]).max() <= tol
     assert rel_l2(UL, rL) <= 1e-5 and rel_l2(UR, rR) <= 1e-5

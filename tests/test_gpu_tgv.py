@@ -43,7 +43,7 @@ def _history(case, steps, **kw):
 def test_tgv_fp32_follows_fp64_and_learned_beats_classical():
     case = configs.taylor_green_3d(n=40)
     steps = 30
-    ref = dict(u_ref=configs.TGV_REF)
+    ref = dict(u_ref="cell")
     k64, _ = _history(case, steps, precision="fp64")
     k32, _ = _history(case, steps, precision="fp32", **ref)
     assert np.max(np.abs(k32 - k64) / k64) < 2e-5, np.abs(k32 - k64) / k64
@@ -69,7 +69,7 @@ def test_learned_stage_network_stream():
     case = configs.taylor_green_3d(n=24)
     w = np.load(WEIGHTS)
     for prec in ("fp64", "fp32"):
-        kw = dict(precision=prec, u_ref=configs.TGV_REF)
+        kw = dict(precision=prec, u_ref="cell")
         sl = Solver(case.mesh, **case.params, blend="learned", **kw)
         sl.mlp_set(w)
         st = Solver(case.mesh, **case.params, blend="theta", **kw)
