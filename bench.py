@@ -62,19 +62,37 @@ def flux_kernel_bytes(nc, nf, nv, dim, el, scheme, blend=False):
     read once, its output written once (Un counted in 2 of 3 stages)."""
     ord_ = 0 if scheme in ("FOU", "CD2") else (1 if scheme in ("USR3", "CSR4") else 2)
     if el == 4 or scheme in ("ENO3", "WENO5"):
-        dcs = 4  # d and the growth rate; the coefficients are evaluated in the kernel
+        dcs = 3  # d; the coefficients are evaluated in the kernel from omega
     else:        # FP64: d and the stored coefficients of both sides
         nc_ = {"FOU": 2, "CD2": 2, "USR3": 4, "CSR4": 3, "USR5": 8, "CSR6": 5}[scheme]
         dcs = (3 + nc_ + 3) & ~3
     # second differentials arrive contracted with d, one value per face side
     per_cell = nv * el + (nv * dim * el if ord_ >= 1 or blend else 0) \
         + el + 4 + nv * el + (2.0 / 3.0) * nv * el + (4 if blend else 0)
-    per_face = 8 + 4 * el + dcs * el + 4 + (2 * nv * el if ord_ >= 2 else 0)
+    # second differentials: the record index pair and d.H.d of both cells
+    per_face = 8 + 4 * el + dcs * el + 4 + (8 + 2 * nv * el if ord_ >= 2 else 0)
     return nc * per_cell + nf * per_face, per_cell, per_face
 
 
-def grad_kernel_bytes(nc, nf, nq, dim, el, out_per_cell):
-    return nc * (nq * el + out_per_cell * el + el + 4) + nf * (8 + 4 * el + 4)
+def grad_features_bytes(nc, nrec, nv, dim, el):
+    """Algorithmic bytes of the first-gradient + features kernel: U and 1/V
+    per cell, the two 16-value-byte face records (sigma w S + the other cell,
+    sigma d + sigma) per record, G1 and the 24 bf16 features written."""
+    return nc * (nv * el + el + nv * dim * el + 48) + nrec * 8 * el
+
+
+def hface_bytes(nc, nrec, nv, dim, el):
+    """Algorithmic bytes of the second-derivative kernel: the cell's G1 row,
+    1/V and its face count per cell, the two face records and d.H.d written
+    per record."""
+    return nc * (nv * dim * el + el + 4) + nrec * (8 * el + nv * el)
+
+
+# Compulsory bytes per cell and stage of the Taylor-Green workload (USR5,
+# hexahedra: 3 faces per cell): U in, U^n in, U out; per face two cell
+# indices, S, omega and d, and the DOLINC coefficients of both sides (8
+# doubles: the FP64 values the method precomputes).
+COMPULSORY_BYTES = {"fp32": 3 * 20 + 3 * (8 + 4 * 7 + 64), "fp64": 3 * 40 + 3 * (8 + 8 * 7 + 64)}
 
 
 def time_path(s, case, precision, extra, steps, warmup, params=None, windows=0, window_steps=34):
@@ -121,18 +139,19 @@ def time_path(s, case, precision, extra, steps, warmup, params=None, windows=0, 
     return out
 
 
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_flux_tgv288_usr5_hllc_learned.txt")
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "stage_kernels_tgv288_usr5_hllc_learned.txt")
 
 
 def measured_traffic(workload):
-    """HBM bytes per launch of the FP32 flux kernel from the committed
-    rocprofv3 counter summary, or None when it belongs to other sources."""
+    """HBM bytes per launch of the stage kernels ({"fp32 k_flux": bytes, ...})
+    from the committed rocprofv3 counter summary, or {} when it belongs to
+    other sources."""
     if workload != "tgv3d":
-        return None
+        return {}
     from paper_2404_08952_amd import profiling
     got = profiling.read_summary(TRAFFIC_SUMMARY)
     if got is None or got[1] != profiling.source_hash():
-        return None
+        return {}
     return got[0]
 
 
@@ -759,34 +778,60 @@ def main():
     gbps_copy = copy_bandwidth()
     log(f"[bench] streaming y = -x: {gbps_copy:.0f} GB/s")
 
+    traffic = measured_traffic(args.workload)
+
     def summarize(prec):
         r = res[prec]
         el = 4 if prec == "fp32" else 8
         stages = 3 * args.steps
         cups = nc * stages / (r["ms_total"] * 1e-3)
+        nrec = r["stats"]["n_slots"]
         fb, fpc, fpf = flux_kernel_bytes(nc, nf, nv, dim, el, scheme, blend)
-        gb = grad_kernel_bytes(nc, nf, nv, dim, el, nv * dim)
         per = lambda k: r["kernel_ms"][k] / max(r["kernel_n"][k], 1)  # noqa: E731
-        # With the learned blend in 3-D the first-gradient pass is fused with
-        # the indicator's features (timed as kind 2); its algorithmic bytes
-        # add the 24 bf16 features written per cell.  The network itself runs
-        # on a second stream beside the second-derivative kernel (untimed).
-        if r["kernel_n"][0]:
-            grad = dict(kernel="k_grad", avg_ms=per(0), alg_bytes=gb, gbps=gb / (per(0) * 1e-3) / 1e9)
+        # kinds of the per-kernel events: 0 first gradient, 1 second
+        # derivatives (d.H.d per face record), 2 sensor, or with the learned
+        # blend the first gradient fused with the features, 3 flux + update
+        kern = {}
+
+        def add(name, kind, alg):
+            if not r["kernel_n"][kind]:
+                return
+            ms = per(kind)
+            gbps = alg / (ms * 1e-3) / 1e9
+            t = traffic.get(f"{prec} {name}")
+            kern[name] = dict(avg_ms=ms, alg_bytes=alg, gbps=gbps, frac=gbps / HBM_PEAK_GBPS,
+                              traffic_bytes=t, traffic_over_alg=(t / alg if t else None))
+        add("k_flux", 3, fb)
+        if blend:
+            add("k_grad_features", 2, grad_features_bytes(nc, nrec, nv, dim, el))
         else:
-            gbi = gb + nc * 48
-            grad = dict(kernel="k_grad_features", avg_ms=per(2), alg_bytes=gbi,
-                        gbps=gbi / (per(2) * 1e-3) / 1e9 if r["kernel_n"][2] else None)
+            add("k_grad", 0, grad_features_bytes(nc, nrec, nv, dim, el) - nc * 48)
+        add("k_hface", 1, hface_bytes(nc, nrec, nv, dim, el))
+        comp = COMPULSORY_BYTES[prec] * cups / 1e9
         return dict(value=cups, ms_per_step=r["ms_per_step"], ms_per_stage=r["ms_per_step"] / 3,
                     flux_kernel=dict(avg_ms=per(3), alg_bytes=fb, gbps=fb / (per(3) * 1e-3) / 1e9,
                                      bytes_per_cell=fpc, bytes_per_face=fpf),
-                    grad_kernel=grad,
-                    grad2_kernel_ms=per(1), indicator_kernel_ms=per(2),
+                    stage_kernels=kern,
+                    stage_effective=dict(compulsory_bytes_per_cell=COMPULSORY_BYTES[prec], gbps=comp,
+                                         frac=comp / HBM_PEAK_GBPS,
+                                         alg_bytes_per_stage=sum(k["alg_bytes"] for k in kern.values())),
                     stage_kernel_ms=sum(per(k) for k in range(4) if r["kernel_n"][k]),
                     finite=r["finite"], min_rho=r["min_rho"], min_p=r["min_p"], partitions=r["stats"],
                     windows=r.get("windows"))
 
     s32, s64 = summarize("fp32"), summarize("fp64")
+    for prec, sm in (("fp32", s32), ("fp64", s64)):
+        for name, k in sm["stage_kernels"].items():
+            log(f"[bench] {prec} {name}: {k['avg_ms']:.3f} ms, {k['alg_bytes'] / 1e9:.3f} GB algorithmic, "
+                f"{k['gbps']:.0f} GB/s = {k['frac']:.3f} of peak"
+                + (f", counter traffic {k['traffic_bytes'] / 1e9:.3f} GB = {k['traffic_over_alg']:.2f} x algorithmic"
+                   if k["traffic_bytes"] else ""))
+        se = sm["stage_effective"]
+        log(f"[bench] {prec} stage: {sm['ms_per_stage']:.3f} ms, compulsory {se['compulsory_bytes_per_cell']} B/cell "
+            f"x {sm['value']:.3e} cell-updates/s = {se['gbps']:.0f} GB/s = {se['frac']:.3f} of peak")
+    log("[bench] algorithmic bytes per launch: " +
+        " ".join(f'"{p} {n}={k["alg_bytes"]:.6e}"' for p, sm in (("fp32", s32), ("fp64", s64))
+                 for n, k in sm["stage_kernels"].items()))
     fk = s32["flux_kernel"]
     out = {
         "metric": METRIC,
@@ -807,12 +852,15 @@ def main():
                                  "coefficients evaluated from them in FP64 in the flux kernel"),
                    "partition_cells": PART_CELLS["fp32"]},
         "roofline": {"bound": "hbm", "achieved": fk["gbps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": fk["gbps"] / HBM_PEAK_GBPS, "traffic": measured_traffic(args.workload),
+                     "frac": fk["gbps"] / HBM_PEAK_GBPS, "traffic": traffic.get("fp32 k_flux"),
                      "kernel": "k_flux (reconstruction + blend + Riemann flux + segmented accumulation + RK update)",
                      "alg_bytes_per_launch": fk["alg_bytes"], "avg_launch_ms": fk["avg_ms"]},
         "fp64": {"value": s64["value"], "ms_per_step": s64["ms_per_step"], "dtype": "f64",
                  "flux_kernel_gbps": s64["flux_kernel"]["gbps"],
                  "flux_kernel_frac": s64["flux_kernel"]["gbps"] / HBM_PEAK_GBPS},
+        "stage_kernels_fp32": s32["stage_kernels"],
+        "stage_kernels_fp64": s64["stage_kernels"],
+        "stage_effective_bandwidth": {"fp32": s32["stage_effective"], "fp64": s64["stage_effective"]},
         "fp32_detail": s32,
         "fp64_detail": s64,
         "fp32_over_fp64": s32["value"] / s64["value"],

@@ -282,13 +282,25 @@ __device__ __forceinline__ void load_weights32(const MlpDev& m, MlpRegs32& R) {
 // lane l's cell l % 16; optionally the hidden activations in accumulator
 // layout (H1, H2: lane l holds units 16t + 4g + i of cell l % 16) and the
 // logit z3, which the training kernel's backward uses.
+// This lane's 8 input slots of the tile at X (zero beyond nrow rows and in
+// the padding slots 24..31).
+__device__ __forceinline__ v8s mlp_tile_input(const unsigned short* X, int nrow, int xstride) {
+  const int l = threadIdx.x & 63;
+  const int r = l & 15, g = l >> 4;
+  return (r < nrow && 8 * g < MLP_IN) ? load8(X + r * xstride + 8 * g) : v8s{0, 0, 0, 0, 0, 0, 0, 0};
+}
+
 template <class P>
 __device__ __forceinline__ float mlp_tile_fwd32(const MlpVec<P>& m, const MlpRegs32& R, const unsigned short* X,
                                                 int nrow, int xstride, v4f* H1 = nullptr, v4f* H2 = nullptr,
-                                                float* z3out = nullptr) {
+                                                float* z3out = nullptr);
+
+// The same from inputs already loaded (xb: mlp_tile_input of the tile).
+template <class P>
+__device__ __forceinline__ float mlp_tile_fwd32_x(const MlpVec<P>& m, const MlpRegs32& R, v8s xb, v4f* H1 = nullptr,
+                                                  v4f* H2 = nullptr, float* z3out = nullptr) {
   const int l = threadIdx.x & 63;
-  const int r = l & 15, g = l >> 4;
-  const v8s xb = (r < nrow && 8 * g < MLP_IN) ? load8(X + r * xstride + 8 * g) : v8s{0, 0, 0, 0, 0, 0, 0, 0};
+  const int g = l >> 4;
   v8s h1[2];
   for (int t = 0; t < 4; ++t) {
     v4f acc;
@@ -320,6 +332,12 @@ __device__ __forceinline__ float mlp_tile_fwd32(const MlpVec<P>& m, const MlpReg
   return __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(z3 * -1.4426950408889634f));
 }
 
+template <class P>
+__device__ __forceinline__ float mlp_tile_fwd32(const MlpVec<P>& m, const MlpRegs32& R, const unsigned short* X,
+                                                int nrow, int xstride, v4f* H1, v4f* H2, float* z3out) {
+  return mlp_tile_fwd32_x(m, R, mlp_tile_input(X, nrow, xstride), H1, H2, z3out);
+}
+
 __global__ __launch_bounds__(256) void k_mlp_fwd(MlpDev m, const unsigned short* __restrict__ X, int64_t n,
                                                  float* __restrict__ theta, int xstride) {
   // biases and output weights in LDS, re-read at every tile (compiler
@@ -340,12 +358,19 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(MlpDev m, const unsigned short*
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   const int64_t ntile = (n + 15) / 16;
+  // the next tile's inputs are loaded before this tile is computed, so the
+  // load's latency overlaps the matrix and vector work of the tile
+  auto rows = [&](int64_t t) { return (int)((n - t * 16) < 16 ? (n - t * 16) : 16); };
+  v8s xb = wave < ntile ? mlp_tile_input(X + wave * 16 * xstride, rows(wave), xstride) : v8s{0, 0, 0, 0, 0, 0, 0, 0};
   for (int64_t t = wave; t < ntile; t += nwaves) {
     const int64_t row0 = t * 16;
-    const int nrow = (int)((n - row0) < 16 ? (n - row0) : 16);
+    const int nrow = rows(t);
+    const int64_t tn = t + nwaves;
+    const v8s xn = tn < ntile ? mlp_tile_input(X + tn * 16 * xstride, rows(tn), xstride) : v8s{0, 0, 0, 0, 0, 0, 0, 0};
     __asm__ volatile("" ::: "memory");
-    const float th = mlp_tile_fwd32(mv, R, X + row0 * xstride, nrow, xstride);
+    const float th = mlp_tile_fwd32_x(mv, R, xb, nullptr, nullptr, nullptr);
     if (l < nrow) theta[row0 + l] = th;
+    xb = xn;
   }
 }
 

@@ -190,10 +190,9 @@ __global__ void k_entry_fill(int64_t ne, int dim, int scheme, int dcs, const int
     double cf[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     face_coefficients(scheme, g[f], cf);
     for (int k = 3; k < dcs; ++k) o[k] = (T)cf[k - 3];
-    return;
   }
-  // the growth rate: the kernels evaluate the coefficients from it in FP64
-  o[3] = (T)g[f];
+  // otherwise d alone: the kernels evaluate the coefficients in FP64 from
+  // the growth rate omega / (1 - omega) of the entry's omega
 }
 
 // Auxiliary cells of boundary faces: the mirror image of the boundary cell

@@ -80,10 +80,10 @@ struct SchemeInfo {
   static constexpr int ORD = SCH <= 2 ? 0 : (SCH <= 4 ? 1 : 2);
   static constexpr bool NONLIN = SCH == 6 || SCH == 7;  // ENO3, WENO5
   static constexpr int NC = SCH <= 2 ? 2 : (SCH == 3 ? 4 : (SCH == 4 ? 3 : (SCH == 8 ? 5 : 8)));
-  // values per face entry in dc: d and g, or (FP64, linear) d and the coefficients
+  // values per face entry in dc: d, or (FP64, linear) d and the coefficients
   template <class T>
   static constexpr int dcs() {
-    return (NONLIN || sizeof(T) == 4) ? 4 : (3 + NC + 3) & ~3;
+    return (NONLIN || sizeof(T) == 4) ? 3 : (3 + NC + 3) & ~3;
   }
 };
 
@@ -600,23 +600,26 @@ __device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T
     // left state: frame P -> N, growth g; right state: frame N -> P,
     // growth 1/g, d -> -d (odd differentials change sign)
     NonlinCoef<T> cf;
-    nonlin_coef<T>(dc[3], cf);
+    // growth rate of the P -> N frame from the owner's weight, in FP64
+    const double gd = (double)om / (1.0 - (double)om);
+    nonlin_coef<T>((T)gd, cf);
 #pragma unroll
     for (int v = 0; v < NV; ++v)
       UL[v] = nonlin_side<T, SCH>(cf, uP[v], uN[v], T(2) * gP[v], T(2) * gN[v], T(4) * hP[v]);
-    nonlin_coef<T>(fdiv(T(1), dc[3]), cf);
+    nonlin_coef<T>((T)((1.0 - (double)om) / (double)om), cf);
 #pragma unroll
     for (int v = 0; v < NV; ++v)
       UR[v] = nonlin_side<T, SCH>(cf, uN[v], uP[v], T(-2) * gN[v], T(-2) * gP[v], T(4) * hN[v]);
   } else {
     // coefficients of both sides: stored (FP64) or from g in FP64, rounded once to T
     T c[8];
-    if constexpr (DCS > 4) {
+    if constexpr (DCS > 3) {
 #pragma unroll
       for (int k = 0; k < 8; ++k) c[k] = 3 + k < DCS ? dc[3 + k] : T(0);
     } else {
+      // growth rate g = omega / (1 - omega) of the P -> N frame, in FP64
       double cd[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-      face_coefficients(SCH, (double)dc[3], cd);
+      face_coefficients(SCH, (double)om / (1.0 - (double)om), cd);
 #pragma unroll
       for (int k = 0; k < 8; ++k) c[k] = (T)cd[k];
     }

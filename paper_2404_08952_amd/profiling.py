@@ -1,6 +1,6 @@
 """Summaries of rocprofv3 output for the stage kernels.
 
-``python -m paper_2404_08952_amd.profiling <stats_dir> <fetch_dir> <write_dir> <out.md> [--launch-bytes B]``
+``python -m paper_2404_08952_amd.profiling <stats_dir> <fetch_dir> <write_dir> <out.md> ["<kernel>=<bytes>" ...]``
 (``... --mfma <stats_dir> <pmc_dir> <rows>`` instead summarises the indicator
 network kernels' matrix-core use from an ``SQ_INSTS_VALU_MFMA_MOPS_BF16`` run)
 reads the CSV files that ``rocprofv3 --kernel-trace --stats`` and two
@@ -8,11 +8,12 @@ reads the CSV files that ``rocprofv3 --kernel-trace --stats`` and two
 wrote, and prints (or writes) a short text summary:
 
 * per-kernel call counts and average durations;
-* HBM traffic of the dominant kernel per launch: the FETCH_SIZE and
+* HBM traffic per launch of every stage kernel: the FETCH_SIZE and
   WRITE_SIZE counters (KiB per dispatch) scaled by what the same counters
   read for a plain streaming kernel of known size (``bench.py`` runs one:
   ``y = -x`` over 2 GiB of float32), so the factors absorb whatever the
-  counters do not see;
+  counters do not see; beside it the algorithmic bytes given on the command
+  line (``bench.py`` prints them);
 * the SHA-256 of the kernel sources the numbers belong to.  ``bench.py``
   reports the traffic only while the sources still hash to that value.
 """
@@ -27,9 +28,21 @@ import statistics
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-# sources that the FP32 flux kernel is compiled from
-FLUX_SOURCES = ("csrc/residual_impl.hpp", "csrc/dispatch_impl.hpp", "csrc/kernels_f32.hip")
-FLUX_KERNEL = r"k_flux<float, 3, 3, 5, true>"
+# sources that the stage kernels are compiled from
+FLUX_SOURCES = ("csrc/residual_impl.hpp", "csrc/dispatch_impl.hpp", "csrc/kernels_f32.hip",
+                "csrc/indicator_impl.hpp", "csrc/indicator.hip", "csrc/coefficients.hpp")
+FLUX_KERNEL = r"k_flux<float, 3, 3, 5, true, 2>"
+# the stage kernels of the headline workload (USR5 + HLLC + learned blend):
+# short name -> kernel-name pattern, FP32 (cell-reference form) and FP64
+STAGE_KERNELS = (
+    ("fp32 k_flux", re.escape("k_flux<float, 3, 3, 5, true, 2>")),
+    ("fp32 k_grad_features", re.escape("k_grad_features<float, 3>")),
+    ("fp32 k_hface", re.escape("k_hface_w5<float, 3, 5>")),
+    ("fp64 k_flux", re.escape("k_flux<double, 3, 3, 5, true, 0>")),
+    ("fp64 k_grad_features", re.escape("k_grad_features<double, 3>")),
+    ("fp64 k_hface", re.escape("k_hface<double, 3, 5>")),
+    ("k_mlp_fwd", re.escape("k_mlp_fwd")),
+)
 CALIB_KERNEL = r"neg_kernel"
 CALIB_BYTES = 2 * 4 * (1 << 29)  # read + write of 2 GiB each
 
@@ -91,18 +104,22 @@ def traffic(fetch_dir, write_dir, kernel_regex=re.escape(FLUX_KERNEL), calib_reg
 
 
 def read_summary(path):
-    """(traffic bytes per launch, source hash) from a summary file, or None."""
+    """({short kernel name: traffic bytes per launch}, source hash) from a
+    summary file, or None."""
     if not os.path.exists(path):
         return None
-    vals = {}
+    per, sha = {}, None
     with open(path) as fh:
         for line in fh:
-            m = re.match(r"\s*(traffic_bytes_per_launch|kernel_source_sha256)\s*=\s*(\S+)", line)
+            m = re.match(r"\s*traffic_bytes_per_launch\[(.+)\]\s*=\s*(\S+)", line)
             if m:
-                vals[m.group(1)] = m.group(2)
-    if len(vals) != 2:
+                per[m.group(1)] = float(m.group(2))
+            m = re.match(r"\s*kernel_source_sha256\s*=\s*(\S+)", line)
+            if m:
+                sha = m.group(1)
+    if not per or sha is None:
         return None
-    return float(vals["traffic_bytes_per_launch"]), vals["kernel_source_sha256"]
+    return per, sha
 
 
 MFMA_KERNELS = (("k_mlp_fwd", 2 * (24 * 64 + 64 * 64 + 64)), ("k_mlp_grad", 3 * 2 * (24 * 64 + 64 * 64 + 64)))
@@ -143,25 +160,42 @@ def main(argv):
         print(__doc__)
         return 2
     stats_dir, fetch_dir, write_dir, out = argv[1:5]
-    launch_bytes = None
-    if "--launch-bytes" in argv:
-        launch_bytes = float(argv[argv.index("--launch-bytes") + 1])
+    # algorithmic bytes per launch: --bytes "fp32 k_flux=9.0e9" ...
+    alg = {}
+    for a in argv[5:]:
+        if "=" in a:
+            k, v = a.rsplit("=", 1)
+            alg[k] = float(v)
+    stats = kernel_stats(stats_dir)
     lines = []
     lines.append("kernel statistics (rocprofv3 --kernel-trace --stats):")
     lines.append(f"{'kernel':80s} {'calls':>6s} {'avg_us':>10s} {'pct':>7s}")
-    for name, calls, avg, pct in kernel_stats(stats_dir)[:14]:
+    for name, calls, avg, pct in stats[:16]:
         lines.append(f"{name[:80]:80s} {calls:6d} {avg:10.1f} {pct:7.2f}")
-    t = traffic(fetch_dir, write_dir)
     lines.append("")
-    lines.append(f"HBM traffic of {FLUX_KERNEL} per launch (median over {t['launches'][0]} dispatches):")
-    lines.append(f"  FETCH_SIZE {t['fetch_kib_raw']:.0f} KiB x {t['fetch_factor']:.3f} = {t['fetch_bytes'] / 1e9:.3f} GB")
-    lines.append(f"  WRITE_SIZE {t['write_kib_raw']:.0f} KiB x {t['write_factor']:.3f} = {t['write_bytes'] / 1e9:.3f} GB")
-    lines.append("  (factors: the same counters on the 2 GiB streaming kernel y = -x, whose true traffic is"
-                 " 2 GiB read + 2 GiB written)")
-    if launch_bytes:
-        lines.append(f"  algorithmic bytes per launch {launch_bytes / 1e9:.3f} GB; measured / algorithmic = "
-                     f"{t['bytes'] / launch_bytes:.2f}")
-    lines.append(f"traffic_bytes_per_launch = {t['bytes']:.6e}")
+    lines.append("HBM traffic per launch of the stage kernels (FETCH_SIZE and WRITE_SIZE, median over the")
+    lines.append("full-size dispatches, calibrated on the 2 GiB streaming kernel y = -x whose true traffic is")
+    lines.append("2 GiB read + 2 GiB written), against the kernel's algorithmic bytes:")
+    lines.append(f"{'kernel':22s} {'avg_us':>8s} {'fetch GB':>9s} {'write GB':>9s} {'traffic GB':>10s} {'TB/s':>6s}"
+                 f" {'alg GB':>8s} {'alg TB/s':>9s} {'traffic/alg':>11s}")
+    traffic_lines = []
+    for short, rx in STAGE_KERNELS:
+        try:
+            t = traffic(fetch_dir, write_dir, kernel_regex=rx)
+        except ValueError:
+            continue
+        us = [a for n, _c, a, _p in stats if re.search(rx, n)]
+        us = us[0] if us else float("nan")
+        ag = alg.get(short)
+        lines.append(f"{short:22s} {us:8.1f} {t['fetch_bytes'] / 1e9:9.3f} {t['write_bytes'] / 1e9:9.3f}"
+                     f" {t['bytes'] / 1e9:10.3f} {t['bytes'] / (us * 1e-6) / 1e12:6.2f}"
+                     + (f" {ag / 1e9:8.3f} {ag / (us * 1e-6) / 1e12:9.2f} {t['bytes'] / ag:11.2f}" if ag else ""))
+        traffic_lines.append(f"traffic_bytes_per_launch[{short}] = {t['bytes']:.6e}")
+        if ag:
+            traffic_lines.append(f"algorithmic_bytes_per_launch[{short}] = {ag:.6e}")
+    t = traffic(fetch_dir, write_dir, kernel_regex=re.escape(FLUX_KERNEL))
+    lines.append(f"  (calibration factors: FETCH_SIZE x {t['fetch_factor']:.3f}, WRITE_SIZE x {t['write_factor']:.3f})")
+    lines += traffic_lines
     lines.append(f"kernel_source_sha256 = {source_hash()}")
     text = "\n".join(lines) + "\n"
     if out == "-":

@@ -8,13 +8,23 @@ def test_flux_kernel_bytes_taylor_green_fp32():
     total, per_cell, per_face = bench.flux_kernel_bytes(nc, nf, 5, 3, 4, "USR5", blend=True)
     # per cell: U 20 + G1 60 + 1/V 4 + slot_ptr 4 + R/U out 20 + 2/3 of U^n 20 + theta 4
     assert abs(per_cell - (20 + 60 + 4 + 4 + 20 + 20 * 2 / 3 + 4)) < 1e-9
-    # per face: owner/neighbour 8 + S, omega 16 + d, g 16 + two slots 4 + d.H.d of both cells 40
-    assert per_face == 8 + 16 + 16 + 4 + 40
-    assert abs(total - 9.013690368e9) < 1.0
+    # per face: owner/neighbour 8 + S, omega 16 + d 12 + two slots 4 + record pair 8 + d.H.d of both cells 40
+    assert per_face == 8 + 16 + 12 + 4 + 8 + 40
+    assert abs(total - (9.013690368e9 + 4 * nf)) < 1.0
 
 
 def test_flux_kernel_bytes_fp64_stores_coefficients():
     _t, per_cell, per_face = bench.flux_kernel_bytes(1, 1, 5, 3, 8, "USR5", blend=True)
     # FP64: d (3) + 8 coefficients rounded up to a multiple of 4 values = 12 doubles
-    assert per_face == 8 + 32 + 12 * 8 + 4 + 80
+    assert per_face == 8 + 32 + 12 * 8 + 4 + 8 + 80
     assert abs(per_cell - (40 + 120 + 8 + 4 + 40 + 40 * 2 / 3 + 4)) < 1e-9
+
+
+def test_gradient_kernel_bytes_taylor_green_fp32():
+    nc = 288 ** 3
+    nrec = 6 * nc  # six face records per hexahedron
+    # per cell: U 20 + 1/V 4 + G1 60 + features 48; per record: two 16-byte records
+    assert bench.grad_features_bytes(nc, nrec, 5, 3, 4) == nc * (20 + 4 + 60 + 48) + nrec * 32
+    # per cell: G1 60 + 1/V 4 + face count 4; per record: two records 32 + d.H.d 20
+    assert bench.hface_bytes(nc, nrec, 5, 3, 4) == nc * (60 + 4 + 4) + nrec * (32 + 20)
+    assert bench.COMPULSORY_BYTES["fp32"] == 360 and bench.COMPULSORY_BYTES["fp64"] == 504
