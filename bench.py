@@ -75,17 +75,18 @@ def flux_kernel_bytes(nc, nf, nv, dim, el, scheme, blend=False):
 
 
 def grad_features_bytes(nc, nrec, nv, dim, el):
-    """Algorithmic bytes of the first-gradient + features kernel: U and 1/V
-    per cell, the two 16-value-byte face records (sigma w S + the other cell,
-    sigma d + sigma) per record, G1 and the 24 bf16 features written."""
-    return nc * (nv * el + el + nv * dim * el + 48) + nrec * 8 * el
+    """Algorithmic bytes of the first-gradient + features kernel: U, 1/V and
+    the face count per cell, the two face records (sigma w S + the other
+    cell: 4 values; sigma d: 3) per record, G1 and the 24 bf16 features
+    written."""
+    return nc * (nv * el + el + 4 + nv * dim * el + 48) + nrec * 7 * el
 
 
 def hface_bytes(nc, nrec, nv, dim, el):
     """Algorithmic bytes of the second-derivative kernel: the cell's G1 row,
-    1/V and its face count per cell, the two face records and d.H.d written
-    per record."""
-    return nc * (nv * dim * el + el + 4) + nrec * (8 * el + nv * el)
+    1/V and its face count per cell, the two face records (7 values) and
+    d.H.d written per record."""
+    return nc * (nv * dim * el + el + 4) + nrec * (7 * el + nv * el)
 
 
 # Compulsory bytes per cell and stage of the Taylor-Green workload (USR5,

@@ -165,6 +165,7 @@ __device__ void cell_features_from(const KArgs<T>& a, int dcs, int64_t c, const 
   const int64_t b = c / KTPB;
   const int lane = (int)(c - b * KTPB);
   const int r0 = a.ell_ptr[b], m = (a.ell_ptr[b + 1] - r0) / KTPB;
+  const int nfc = a.slot_ptr[c + 1] - a.slot_ptr[c];  // the cell's faces; records beyond are padding
   T qc[4], gqc[4][D];
   T Uc[NV];
   load_row<T, NV>(Uc, Ulds, a.U, c0, n, c);
@@ -181,10 +182,10 @@ __device__ void cell_features_from(const KArgs<T>& a, int dcs, int64_t c, const 
     for (int jj = 0; jj < GB; ++jj) {
       const bool ok = j + jj < m;
       const int64_t r = (int64_t)r0 + (int64_t)(ok ? j + jj : j) * KTPB + lane;
-      GlbPtr<T> rd = as_glb(a.ell_d + 4 * r);
+      GlbPtr<T> rd = as_glb(a.ell_d + 3 * r);
 #pragma unroll
       for (int x = 0; x < D; ++x) dv[jj][x] = rd[x];
-      sg[jj] = ok ? rd[3] : T(0);
+      sg[jj] = (ok && j + jj < nfc) ? T(1) : T(0);
       o[jj] = ok ? rec_cell(a.ell_sw[4 * r + 3]) : c;
     }
     T Uo[GB][NV];
@@ -609,6 +610,7 @@ __global__ __launch_bounds__(KTPB) void k_grad_features(KArgs<T> a, int dcs, T* 
   T g[NV * D];
   if (c < a.nc) {
     const int r0 = a.ell_ptr[b], m = (a.ell_ptr[b + 1] - r0) / KTPB;  // faces per cell in this block
+    const int nfc = a.slot_ptr[c + 1] - a.slot_ptr[c];                 // this cell's faces
     const T rv = a.rV[c];
     float f[MLP_IN];
     constexpr int FB = 6;
@@ -627,7 +629,7 @@ __global__ __launch_bounds__(KTPB) void k_grad_features(KArgs<T> a, int dcs, T* 
         const bool ok = jj < m;
         const int64_t r = (int64_t)r0 + (int64_t)(ok ? jj : 0) * KTPB + lane;
         GlbPtr<T> rec = as_glb(a.ell_sw + 4 * r);
-        GlbPtr<T> rd = as_glb(a.ell_d + 4 * r);
+        GlbPtr<T> rd = as_glb(a.ell_d + 3 * r);
         T v[4];
 #pragma unroll
         for (int x = 0; x < 4; ++x) v[x] = rec[x];
@@ -637,7 +639,7 @@ __global__ __launch_bounds__(KTPB) void k_grad_features(KArgs<T> a, int dcs, T* 
           Sw[jj][x] = ok ? v[x] : T(0);
           dv[jj][x] = rd[x];
         }
-        sg[jj] = ok ? rd[3] : T(0);
+        sg[jj] = (ok && jj < nfc) ? T(1) : T(0);
       }
       T Uo[FB][NV];
 #pragma unroll

@@ -32,7 +32,8 @@ namespace dolinc {
 //                  interpolation), sigma = +1 on the owner side, -1 on the
 //                  neighbour side, so the Gauss-linear sum of a cell is
 //                  sum_r (phi_o - phi_c) ell_sw[r][0..D).
-//   ell_d[r][4]  : sigma d_x, sigma d_y, sigma d_z, sigma (0 for padding).
+//   ell_d[r][3]  : sigma d_x, sigma d_y, sigma d_z (0 for padding).  A cell's
+//                  records j >= its face count (slot_ptr) are padding.
 constexpr int ELL_BLOCK = 256;
 inline bool nonlinear_scheme(int scheme) { return scheme == 6 || scheme == 7; }
 // coefficients per face of the linear schemes (both sides)

@@ -236,7 +236,7 @@ __global__ void k_ell_fill(int64_t nc, int B, const int32_t* __restrict__ part_p
   for (int j = 0; j < m; ++j) {
     const int64_t r = (int64_t)r0 + (int64_t)j * ELL_BLOCK + lane;
     T* q = ell_sw + 4 * r;
-    T* dd = ell_d + 4 * r;
+    T* dd = ell_d + 3 * r;
     int64_t o = c;
     if (j < nf) {
       const uint16_t sl = slots[s0 + j];
@@ -251,12 +251,9 @@ __global__ void k_ell_fill(int64_t nc, int B, const int32_t* __restrict__ part_p
         q[x] = wgt * sw[4 * e + x];
         dd[x] = sg * dc[(int64_t)dcs * e + x];
       }
-      dd[3] = sg;
     } else {
-      for (int x = 0; x < 4; ++x) {
-        q[x] = T(0);
-        dd[x] = T(0);
-      }
+      for (int x = 0; x < 4; ++x) q[x] = T(0);
+      for (int x = 0; x < 3; ++x) dd[x] = T(0);
     }
     if constexpr (sizeof(T) == 4) {
       q[3] = __int_as_float((int)o);

@@ -1039,7 +1039,7 @@ __device__ __forceinline__ void hface_block(const KArgs<T>& a, const T* __restri
   const int nfc = a.slot_ptr[c + 1] - a.slot_ptr[c];
   for (int j = 0; j < nfc; ++j) {
     const int64_t r = (int64_t)r0 + (int64_t)j * KTPB + threadIdx.x;
-    GlbPtr<T> rd = as_glb(a.ell_d + 4 * r);
+    GlbPtr<T> rd = as_glb(a.ell_d + 3 * r);
     T d[3];
 #pragma unroll
     for (int x = 0; x < D; ++x) d[x] = rd[x];
@@ -1071,13 +1071,12 @@ __global__ __launch_bounds__(KTPB) void k_theta(KArgs<T> a, int dcs, float* __re
   if (b < 0) return;
   const int64_t c = (int64_t)b * KTPB + threadIdx.x;
   if (c >= a.nc) return;
-  const int r0 = a.ell_ptr[b], m = (a.ell_ptr[b + 1] - r0) / KTPB;
+  const int r0 = a.ell_ptr[b];
+  const int nfc = a.slot_ptr[c + 1] - a.slot_ptr[c];  // records beyond the cell's faces are padding
   T beta = T(0);
-  for (int j = 0; j < m; ++j) {
+  for (int j = 0; j < nfc; ++j) {
     const int64_t r = (int64_t)r0 + (int64_t)j * KTPB + threadIdx.x;
-    GlbPtr<T> rd = as_glb(a.ell_d + 4 * r);
-    const T sg = rd[3];
-    if (sg == T(0)) continue;  // padding
+    GlbPtr<T> rd = as_glb(a.ell_d + 3 * r);
     const int64_t o = rec_cell(a.ell_sw[4 * r + 3]);
 #pragma unroll
     for (int q = 0; q < (NV == 1 ? 1 : 2); ++q) {
