@@ -166,6 +166,19 @@ typedef struct {
   double adv_vel[3];             /* advection velocity                                */
   double burgers_dir[3];         /* Burgers flux u^2/2 * burgers_dir                   */
   double u_ref[5];               /* reference state for the FP32 perturbation flux     */
+  int32_t positivity;            /* Euler, meshes without boundary faces, use_u_ref 0  */
+                                 /* or 2: 1 scales every cell's face-side states      */
+                                 /* toward the cell value, U_c + theta_c (U_c,f -     */
+                                 /* U_c), with the largest theta_c in [0, 1] for      */
+                                 /* which U* = U_c - theta_c sum_f a_f (U_c,f - U_c)  */
+                                 /* (a_f = |S_f| / sum |S|) keeps rho and p >= 1e-6   */
+                                 /* of the cell's: the update of a cell is then a     */
+                                 /* convex combination of first-order Lax-Friedrichs  */
+                                 /* updates, admissible for dt lambda sum|S|/V <= 1/2 */
+                                 /* (Zhang-Shu style; not in the paper, for shock     */
+                                 /* workloads).  A first pass per stage writes the    */
+                                 /* increments and theta_c; 0 leaves the states as    */
+                                 /* they are.                                         */
 } dolinc_params;
 
 typedef struct {                 /* host-side partition statistics                    */

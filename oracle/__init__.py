@@ -13,8 +13,9 @@ scheme    Gauss-linear gradient (Sec. 2.3), DOLINC differentials, far-cell
           reconstruction (Sec. 2.4)
 flux      upwind / Godunov-Burgers / Rusanov / HLLC
 limiter   Van Leer state, classical sensor, blend
+positivity  per-cell scaling of the face-side states (shock workloads)
 solver    residual, SSP-RK3, conservation and error norms
 """
-from . import flux, geometry, limiter, scheme, solver  # noqa: F401
+from . import flux, geometry, limiter, positivity, scheme, solver  # noqa: F401
 from .geometry import Geometry, geometry as compute_geometry  # noqa: F401
 from .solver import residual, rk_step, ssp_rk3  # noqa: F401

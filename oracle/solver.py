@@ -2,7 +2,9 @@
 
 Test infrastructure only.
 
-Residual of the finite-volume update on cell averages (Sec. 2.2, Sec. 3):
+Residual of the finite-volume update on cell averages (Sec. 2.2, Sec. 3);
+with params["positivity"] the face-side states of the Euler equations are
+scaled per cell first (positivity.py):
     R_P = -V_P^-1 sum_{f of P} sigma_{P,f} F_f,   sigma = +1 owner, -1 neighbour,
 with F_f the numerical flux of the reconstructed face states.  Time
 integration is the third-order TVD (SSP) Runge-Kutta method named in Sec. 3:
@@ -15,6 +17,7 @@ import numpy as np
 
 from . import flux as _flux
 from . import limiter as _lim
+from . import positivity as _pos
 from . import scheme as _sch
 from .geometry import geometry  # noqa: F401  (re-exported)
 
@@ -49,6 +52,8 @@ def face_flux(mesh, geo, U, params, theta=None):
         return _flux.godunov_burgers(UL, UR, geo.S, params.get("burgers_dir", (1.0, 1.0, 0.0)))
     gamma = params.get("gamma", 1.4)
     UL, UR = _positivity_fallback(UL, UR, U, mesh, gamma)
+    if params.get("positivity"):
+        UL, UR, _th = _pos.scale_face_states(mesh, geo, U, UL, UR, gamma)
     if params["flux"] == "rusanov":
         return _flux.rusanov(UL, UR, geo.S, gamma)
     if params["flux"] == "hllc":

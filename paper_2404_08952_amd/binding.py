@@ -37,7 +37,8 @@ class MeshDesc(C.Structure):
 class Params(C.Structure):
     _fields_ = [("pde", C.c_int32), ("scheme", C.c_int32), ("flux", C.c_int32), ("precision", C.c_int32),
                 ("blend", C.c_int32), ("use_u_ref", C.c_int32), ("gamma", C.c_double),
-                ("adv_vel", C.c_double * 3), ("burgers_dir", C.c_double * 3), ("u_ref", C.c_double * 5)]
+                ("adv_vel", C.c_double * 3), ("burgers_dir", C.c_double * 3), ("u_ref", C.c_double * 5),
+                ("positivity", C.c_int32)]
 
 
 class MeshStats(C.Structure):
@@ -148,13 +149,14 @@ def mesh_prepare(mesh, renumber=2, part_cells=0):
 
 
 def make_params(pde, scheme, flux="upwind", precision="fp64", blend="none", gamma=1.4,
-                adv_vel=(1.0, 0.5, 0.0), burgers_dir=(1.0, 1.0, 0.0), u_ref=None):
+                adv_vel=(1.0, 0.5, 0.0), burgers_dir=(1.0, 1.0, 0.0), u_ref=None, positivity=False):
     p = Params()
     p.pde = PDE[pde]
     p.scheme = SCHEME[scheme]
     p.flux = FLUX[flux]
     p.precision = PRECISION[precision]
     p.blend = BLEND[blend]
+    p.positivity = int(bool(positivity))
     p.gamma = gamma
     for k in range(3):
         p.adv_vel[k] = adv_vel[k] if k < len(adv_vel) else 0.0
@@ -183,7 +185,7 @@ class Solver:
 
     def __init__(self, mesh, pde, scheme, flux="upwind", precision="fp64", blend="none", gamma=1.4,
                  adv_vel=(1.0, 0.5, 0.0), burgers_dir=(1.0, 1.0, 0.0), u_ref=None, renumber=2,
-                 part_cells=0, device="cuda:0"):
+                 part_cells=0, device="cuda:0", positivity=False):
         import torch
         self.torch = torch
         self.lib = load()
@@ -204,11 +206,11 @@ class Solver:
         st = MeshStats()
         _check(self.lib, self.lib.dolinc_stats(self.h, C.byref(st)))
         self.n_rows = int(st.n_rows)          # device rows: cells, then boundary auxiliary cells
-        self.configure(pde, scheme, flux, precision, blend, gamma, adv_vel, burgers_dir, u_ref)
+        self.configure(pde, scheme, flux, precision, blend, gamma, adv_vel, burgers_dir, u_ref, positivity)
 
     def configure(self, pde, scheme, flux="upwind", precision="fp64", blend="none", gamma=1.4,
-                  adv_vel=(1.0, 0.5, 0.0), burgers_dir=(1.0, 1.0, 0.0), u_ref=None):
-        p = make_params(pde, scheme, flux, precision, blend, gamma, adv_vel, burgers_dir, u_ref)
+                  adv_vel=(1.0, 0.5, 0.0), burgers_dir=(1.0, 1.0, 0.0), u_ref=None, positivity=False):
+        p = make_params(pde, scheme, flux, precision, blend, gamma, adv_vel, burgers_dir, u_ref, positivity)
         self.pde, self.scheme, self.precision = pde, scheme, precision
         self.nv = self.dim + 2 if pde == "euler" else 1
         self.dtype = self.torch.float64 if precision == "fp64" else self.torch.float32

@@ -87,6 +87,8 @@ void free_work(dolinc_ctx c) {
   dfree(w.sw); dfree(w.ell_sw); dfree(w.ell_d); dfree(w.dc); dfree(w.rV); dfree(w.G1); dfree(w.Hf); dfree(w.W1); dfree(w.W2);
   dfree_t(w.theta);
   dfree_t(w.Xf);
+  dfree(w.estate);
+  dfree(w.thpos);
   w.scheme = w.precision = -1;
   w.nv = 0;
 }
@@ -129,6 +131,10 @@ dolinc_status check_params(const dolinc_params* p, int dim) {
     if (!std::isfinite(p->adv_vel[k]) || !std::isfinite(p->burgers_dir[k]))
       return fail(DOLINC_EINVAL, "non-finite velocity");
   if (p->use_u_ref < 0 || p->use_u_ref > 2) return fail(DOLINC_EINVAL, "use_u_ref must be 0, 1 or 2");
+  if (p->positivity) {
+    if (p->pde != DOLINC_EULER) return fail(DOLINC_EUNSUPPORTED, "the positivity rule is built for the Euler equations");
+    if (p->use_u_ref == 1) return fail(DOLINC_EUNSUPPORTED, "the positivity rule takes use_u_ref 0 or 2");
+  }
   if (p->use_u_ref) {
     if (p->pde != DOLINC_EULER) return fail(DOLINC_EUNSUPPORTED, "reference-state forms are built for the Euler equations");
     if (p->use_u_ref == 1)
@@ -532,6 +538,8 @@ dolinc_status dolinc_precompute(dolinc_ctx c, const dolinc_params* p, dolinc_str
   if (!valid_ctx(c)) return fail(DOLINC_ESTATE, "invalid or destroyed context");
   dolinc_status st = check_params(p, c->dim);
   if (st != DOLINC_OK) return st;
+  if (p->positivity && c->n_ghost)
+    return fail(DOLINC_EUNSUPPORTED, "the positivity rule is built for meshes without boundary faces");
   hipStream_t s = (hipStream_t)stream;
   c->precomputed = false;
   if (!c->geometry_done) {
@@ -564,7 +572,8 @@ dolinc_status dolinc_precompute(dolinc_ctx c, const dolinc_params* p, dolinc_str
       return fail(DOLINC_EUNSUPPORTED, "partition face fluxes exceed the LDS of one workgroup (" +
                                            std::to_string(lim / 1024) + " KiB); use a smaller part_cells");
   }
-  if (c->w.precision != p->precision || c->w.scheme != p->scheme || c->w.nv != nv || c->w.blend != p->blend) {
+  if (c->w.precision != p->precision || c->w.scheme != p->scheme || c->w.nv != nv || c->w.blend != p->blend ||
+      (c->w.estate != nullptr) != (p->positivity != 0)) {
     if (c->s_net) HIPCHK(hipStreamSynchronize(c->s_net));  // the network may still read the old buffers
     free_work(c);
     const size_t nc = (size_t)c->n_cells, ne = (size_t)c->n_entries;
@@ -583,6 +592,10 @@ dolinc_status dolinc_precompute(dolinc_ctx c, const dolinc_params* p, dolinc_str
     al(&c->w.W2, nc * nv * el);
     if (bl) al((void**)&c->w.theta, nc * sizeof(float));
     if (p->blend == DOLINC_BLEND_LEARNED && c->dim == 3) al((void**)&c->w.Xf, nc * DOLINC_N_FEATURES * sizeof(unsigned short));
+    if (p->positivity) {
+      al(&c->w.estate, ne * 2 * nv * el);
+      al(&c->w.thpos, nc * el);
+    }
     if (e != hipSuccess) {
       free_work(c);
       return fail(DOLINC_ENOMEM, std::string("workspace allocation failed: ") + hipGetErrorString(e));

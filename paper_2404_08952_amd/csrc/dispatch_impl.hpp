@@ -36,6 +36,10 @@ KArgs<T> base_args(dolinc_ctx_s* c) {
   for (int k = 0; k < 5; ++k) a.uref[k] = (T)c->params.u_ref[k];
   a.face_ent = c->m.face_ent;
   a.nf = c->n_faces;
+  a.max_entries = c->max_entries;
+  // the positivity rule's workspace (only with params.positivity)
+  a.estate = (T*)c->w.estate;
+  a.thpos = (T*)c->w.thpos;
   return a;
 }
 
@@ -59,7 +63,25 @@ inline int pde_kind(const dolinc_params& p) {
 }
 
 template <class T, int D, int PK, int SCH, bool BL, int REF>
-hipError_t go_flux(const KArgs<T>& a, size_t lds, hipStream_t s, bool exporting) {
+hipError_t go_flux(const KArgs<T>& a0, size_t lds, hipStream_t s, bool exporting) {
+  KArgs<T> a = a0;
+  if constexpr (PK >= 2 && REF != 1) {
+    if (a.thpos) {
+      // positivity rule of the cell averages: the face-side increments and
+      // theta_pos per cell first (LDS: both increments and the area per entry)
+      const size_t lds1 = (size_t)a.max_entries * (2 * NVars<PK, D>::value + 1) * sizeof(T);
+      if (lds1 > flux_lds_limit()) return hipErrorInvalidConfiguration;
+      hipLaunchKernelGGL((k_pos_states<T, D, PK, SCH, BL, REF>), dim3(8 * a.per_xcd), dim3(KTPB), lds1, s, a);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      if (!exporting) {
+        if (lds > flux_lds_limit()) return hipErrorInvalidConfiguration;
+        hipLaunchKernelGGL((k_flux<T, D, PK, SCH, BL, REF, 2>), dim3(8 * a.per_xcd), dim3(KTPB), lds, s, a);
+        return hipGetLastError();
+      }
+    }
+  }
+  if (!a.thpos) a.estate = nullptr;  // export reads the scaled states only after the first pass
   if (exporting) {
     const unsigned nb = (unsigned)((a.nf + KTPB - 1) / KTPB);
     hipLaunchKernelGGL((k_face_export<T, D, PK, SCH, BL, REF>), dim3(nb), dim3(KTPB), 0, s, a);
@@ -67,7 +89,7 @@ hipError_t go_flux(const KArgs<T>& a, size_t lds, hipStream_t s, bool exporting)
   }
   // LDS holds the partition's face fluxes only (rows are gathered from HBM/L2)
   if (lds > flux_lds_limit()) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((k_flux<T, D, PK, SCH, BL, REF>), dim3(8 * a.per_xcd), dim3(KTPB), lds, s, a);
+  hipLaunchKernelGGL((k_flux<T, D, PK, SCH, BL, REF, 0>), dim3(8 * a.per_xcd), dim3(KTPB), lds, s, a);
   return hipGetLastError();
 }
 

@@ -112,6 +112,8 @@ struct Work {
   void* W2 = nullptr;
   float* theta = nullptr;
   unsigned short* Xf = nullptr;  // learned blend: the stage's bf16 features [n_cells][24]
+  void* estate = nullptr;        // positivity rule: face-side increments [entries][2][nv]
+  void* thpos = nullptr;         // positivity rule: scaling per cell [n_cells]
   double* diag = nullptr;  // partial sums for diagnostics
   int* flag = nullptr;     // device error flag
   size_t elem = 0;         // sizeof working type

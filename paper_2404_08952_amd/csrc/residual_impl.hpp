@@ -30,7 +30,7 @@ constexpr int KTPB = 256;
 
 template <class T>
 struct KArgs {
-  int64_t nc;
+  int64_t nc, max_entries;
   int np, B, per_xcd, n_cell_blocks, cell_per_xcd;
   const int32_t* part_ptr;
   const int2* ent_pn;
@@ -60,6 +60,10 @@ struct KArgs {
   T* eUL;
   T* eUR;
   T* eF;
+  // positivity rule of the cell averages: per entry the face-side increments
+  // [2][NV] (owner side, neighbour side), per cell the scaling theta
+  T* estate;
+  T* thpos;
 };
 
 // Partitions are handed out so that each XCD (workgroups go round-robin
@@ -537,10 +541,15 @@ __device__ __forceinline__ T nonlin_side(const NonlinCoef<T>& c, T a0, T a1, T D
 // unchanged on the shifted values.  F receives the owner's share (REF 2:
 // G_P) and, for REF 2 only, F2 the neighbour's (G_N); with REF 0 / 1 one
 // flux serves both cells.
-template <class T, int D, int PK, int SCH, bool BLEND, int REF = 0>
+// MODE (Euler with the positivity rule of the cell averages): 0 the whole
+// face; 1 the face-side states only, returned as increments over their own
+// cells (UL - U_P, UR - U_N) for the per-cell scaling; 2 the flux from the
+// scaled increments a.estate, a.thpos (the first pass's output).
+template <class T, int D, int PK, int SCH, bool BLEND, int REF = 0, int MODE = 0>
 __device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T* UR, T* F, T* F2 = nullptr) {
   constexpr int NV = NVars<PK, D>::value;
   static_assert(REF == 0 || PK >= 2, "reference-state forms are built for the Euler equations");
+  static_assert(MODE == 0 || PK >= 2, "the positivity rule is built for the Euler equations");
   constexpr int ORD = SchemeInfo<SCH>::ORD;
   constexpr int DCS = SchemeInfo<SCH>::template dcs<T>();
   const int2 pn = a.ent_pn[e];
@@ -578,6 +587,16 @@ __device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T
       base[v] = T(0);
     }
   }
+  if constexpr (MODE == 2) {
+    // the scaled face-side states: own value + theta_pos x increment
+    const T* es = a.estate + (int64_t)2 * NV * e;
+    const T tp = a.thpos[P], tn = a.thpos[N];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      UL[v] = uP[v] + tp * es[v];
+      UR[v] = uN[v] + tn * es[NV + v];
+    }
+  } else {
   T gP[NV], gN[NV], hP[NV], hN[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) gP[v] = gN[v] = hP[v] = hN[v] = T(0);
@@ -656,6 +675,7 @@ __device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T
       UR[v] = tf * UR[v] + (T(1) - tf) * VR;
     }
   }
+  }  // MODE != 2
   if constexpr (PK == 0) {
     T an = T(0);
 #pragma unroll
@@ -677,7 +697,7 @@ __device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T
     F[0] = uL <= uR ? fmn : fmx;
   } else if constexpr (REF == 0) {
     // positivity: a side with rho <= 0 or p <= 0 falls back to its cell value
-    {
+    if constexpr (MODE != 2) {
       T r, vv[D], E, p;
       euler_prim<T, D>(UL, a.gamma, r, vv, E, p);
       if (!(r > T(0) && p > T(0)))
@@ -686,6 +706,14 @@ __device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T
       if (!(r > T(0) && p > T(0)))
         for (int v = 0; v < NV; ++v) UR[v] = uN[v];
     }
+    if constexpr (MODE == 1) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        UL[v] -= uP[v];
+        UR[v] -= uN[v];
+      }
+      return;
+    }
     if constexpr (PK == 2)
       flux_rusanov<T, D>(UL, UR, S, a.gamma, F);
     else
@@ -693,7 +721,7 @@ __device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T
   } else {
     RefState<T, D> Rf;
     ref_state<T, D>(base, a.gamma, Rf);
-    {
+    if constexpr (MODE != 2) {
       PertState<T, D> Ps;
       pert_state<T, D>(UL, Rf, a.gamma, Ps);
       if (!(Ps.r > T(0) && Ps.p > T(0)))
@@ -701,6 +729,14 @@ __device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T
       pert_state<T, D>(UR, Rf, a.gamma, Ps);
       if (!(Ps.r > T(0) && Ps.p > T(0)))
         for (int v = 0; v < NV; ++v) UR[v] = uN[v];
+    }
+    if constexpr (MODE == 1) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        UL[v] -= uP[v];
+        UR[v] -= uN[v];
+      }
+      return;
     }
     if constexpr (PK == 2)
       flux_rusanov_pert<T, D>(UL, UR, S, base, a.gamma, F);
@@ -725,7 +761,7 @@ __device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T
 }
 
 // ---------------------------------------------------------------- kernels
-template <class T, int D, int PK, int SCH, bool BLEND, int REF>
+template <class T, int D, int PK, int SCH, bool BLEND, int REF, int MODE>
 __global__ __launch_bounds__(KTPB) void k_flux(KArgs<T> a) {
   constexpr int NV = NVars<PK, D>::value;
   constexpr int FW = REF == 2 ? 2 * NV : NV;  // values per entry in LDS (REF 2: owner's, neighbour's share)
@@ -739,7 +775,7 @@ __global__ __launch_bounds__(KTPB) void k_flux(KArgs<T> a) {
   const int e0 = a.part_ptr[p], e1 = a.part_ptr[p + 1];
   for (int e = e0 + (int)threadIdx.x; e < e1; e += KTPB) {
     T UL[NV], UR[NV], F[FW];
-    eval_face<T, D, PK, SCH, BLEND, REF>(a, e, UL, UR, F, F + (REF == 2 ? NV : 0));
+    eval_face<T, D, PK, SCH, BLEND, REF, MODE>(a, e, UL, UR, F, F + (REF == 2 ? NV : 0));
 #pragma unroll
     for (int v = 0; v < FW; ++v) Fs[(e - e0) * FW + v] = F[v];
   }
@@ -781,13 +817,121 @@ __global__ __launch_bounds__(KTPB) void k_flux(KArgs<T> a) {
   }
 }
 
+// Positivity rule of the cell averages, first pass (Euler): per partition,
+// every entry's face-side states as increments over their own cells
+// (written to a.estate and kept in LDS with the face area), then for every
+// cell of the partition theta_pos, the largest theta in [0, 1] for which
+// U* = U_c - theta sum_f a_f e_{c,f} keeps rho >= 1e-6 rho_c and
+// p >= 1e-6 p_c (a_f = |S_f| / sum |S|; e_{c,f} the cell's face-side
+// increments): 1 when theta = 1 qualifies, else the smaller of the density's
+// linear root and the pressure's first positive root of
+//   f(theta) = rho* (E* - k) - |m*|^2 / 2,  k = 1e-6 p_c / (gamma - 1).
+// With the scaled states U_c + theta_pos e_{c,f} the forward Euler update is
+// a convex combination of admissible Lax-Friedrichs updates when
+// dt lambda sum |S| / V <= 1/2.  Seam entries are evaluated identically by
+// both partitions, so each cell sees all of its face-side states here.
+template <class T, int D, int PK, int SCH, bool BLEND, int REF>
+__global__ __launch_bounds__(KTPB) void k_pos_states(KArgs<T> a) {
+  constexpr int NV = NVars<PK, D>::value;
+  constexpr int EW = 2 * NV + 1;  // LDS per entry: both sides' increments, the area
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int p = xcd_remap(blockIdx.x, a.per_xcd, a.np);
+  if (p < 0) return;
+  const int64_t c0 = (int64_t)p * a.B;
+  const int ncl = (int)(a.nc - c0 < a.B ? a.nc - c0 : a.B);
+  T* Es = reinterpret_cast<T*>(smem_raw);
+  const int e0 = a.part_ptr[p], e1 = a.part_ptr[p + 1];
+  for (int e = e0 + (int)threadIdx.x; e < e1; e += KTPB) {
+    T eL[NV], eR[NV], F[NV];
+    eval_face<T, D, PK, SCH, BLEND, REF, 1>(a, e, eL, eR, F);
+    const T* sw = a.sw + 4 * (int64_t)e;
+    const T area = fsqrt(sw[0] * sw[0] + sw[1] * sw[1] + sw[2] * sw[2]);
+    T* es = a.estate + (int64_t)2 * NV * e;
+    T* ls = Es + (e - e0) * EW;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      es[v] = eL[v];
+      es[NV + v] = eR[v];
+      ls[v] = eL[v];
+      ls[NV + v] = eR[v];
+    }
+    ls[2 * NV] = area;
+  }
+  __syncthreads();
+  const int64_t c1 = c0 + ncl;
+  for (int64_t c = c0 + threadIdx.x; c < c1; c += KTPB) {
+    const int s0 = a.slot_ptr[c], s1 = a.slot_ptr[c + 1];
+    T db[NV], tot = T(0);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) db[v] = T(0);
+    for (int s = s0; s < s1; ++s) {
+      const uint16_t sl = a.slots[s];
+      const bool nb = (sl >> 15) != 0;
+      const T* ls = Es + (sl & 0x7fff) * EW;
+      const T ar = ls[2 * NV];
+      tot += ar;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) db[v] += ar * ls[(nb ? NV : 0) + v];
+    }
+    const T it = fdiv(T(1), tot);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) db[v] *= it;
+    // theta_pos of the cell
+    const T* U = a.U + c * NV;
+    T r, vv[D], E, pc;
+    euler_prim<T, D>(U, a.gamma, r, vv, E, pc);
+    constexpr double DEL = 1e-6;
+    const T k = T(DEL) * pc / (a.gamma - T(1));
+    T mm = T(0), md = T(0), dd = T(0);
+#pragma unroll
+    for (int x = 0; x < D; ++x) {
+      mm += U[1 + x] * U[1 + x];
+      md += U[1 + x] * db[1 + x];
+      dd += db[1 + x] * db[1 + x];
+    }
+    const T dr = db[0], dE = db[D + 1];
+    const T r1 = r - dr, E1 = E - dE;
+    T m1 = T(0);
+#pragma unroll
+    for (int x = 0; x < D; ++x) m1 += (U[1 + x] - db[1 + x]) * (U[1 + x] - db[1 + x]);
+    T th = T(1);
+    if (!(r1 >= T(DEL) * r && r1 * (E1 - k) - T(0.5) * m1 >= T(0))) {
+      T th_r = T(1);
+      if (dr > T(0)) th_r = fmin(T(1), fdiv((T(1) - T(DEL)) * r, dr));
+      const T A = dr * dE - T(0.5) * dd;
+      const T B = -r * dE - dr * (E - k) + md;
+      const T C = r * (E - k) - T(0.5) * mm;
+      const T disc = fmax(B * B - T(4) * A * C, T(0));
+      const T q = T(-0.5) * (B + (B >= T(0) ? T(1) : T(-1)) * fsqrt(disc));
+      T th_p = T(1);
+      if (A != T(0)) {
+        const T ra = fdiv(q, A);
+        if (ra > T(0)) th_p = fmin(th_p, ra);
+      }
+      if (q != T(0)) {
+        const T rb = fdiv(C, q);
+        if (rb > T(0)) th_p = fmin(th_p, rb);
+      }
+      th = fmin(th_r, th_p);
+    }
+    a.thpos[c] = th;
+  }
+}
+
 template <class T, int D, int PK, int SCH, bool BLEND, int REF>
 __global__ __launch_bounds__(KTPB) void k_face_export(KArgs<T> a) {
   constexpr int NV = NVars<PK, D>::value;
   const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= a.nf) return;
   T UL[NV], UR[NV], F[NV], F2[NV];
-  eval_face<T, D, PK, SCH, BLEND, REF>(a, a.face_ent[f], UL, UR, F, F2);
+  if constexpr (PK >= 2) {
+    if (a.estate)  // the positivity rule's first pass has run: its scaled states
+      eval_face<T, D, PK, SCH, BLEND, REF, 2>(a, a.face_ent[f], UL, UR, F, F2);
+    else
+      eval_face<T, D, PK, SCH, BLEND, REF, 0>(a, a.face_ent[f], UL, UR, F, F2);
+  } else {
+    eval_face<T, D, PK, SCH, BLEND, REF, 0>(a, a.face_ent[f], UL, UR, F, F2);
+  }
   if constexpr (REF == 1 || REF == 2) {
     // the full face flux F.S: add back the reference state's physical flux
     // (rounded in the working precision; export only)

@@ -31,11 +31,11 @@ def _save(name, res):
             json.dump(res, f, indent=1)
 
 
-def _run(case, mode, params=None, precision="fp64"):
+def _run(case, mode, params=None, precision="fp64", **extra):
     import torch
 
     from paper_2404_08952_amd import Solver
-    s = Solver(case.mesh, **case.params, precision=precision, blend=mode if mode != "limited" else "theta")
+    s = Solver(case.mesh, **case.params, precision=precision, blend=mode if mode != "limited" else "theta", **extra)
     if mode == "limited":
         s.set_theta(torch.zeros(case.mesh.n_cells, dtype=torch.float32, device=s.device))
     if mode == "learned":
@@ -92,18 +92,20 @@ def test_learned_indicator_gain():
     assert abs(res["learned"]["shock_pos_err"]) <= abs(res["limited"]["shock_pos_err"]) + 0.5 / 40, res
 
 
-@pytest.mark.skip(reason="the Van Leer state limited everywhere (FP64, capped or not, at any time step down to a "
-                         "tenth of the geometric CFL limit) drives a sliver cell's pressure below zero near t = 2e-3 "
-                         "on this mesh, the same in the oracle; the method has no cell-level positivity rule yet")
 def test_blast_learned_vs_classical():
     """Spherical blast (p 10 inside r < 0.2, 0.1 outside, at rest) to t = 0.05
-    on the 40^3 mixed mesh: the FP32 path with the committed network against
-    the FP64 classical-sensor run and the FP64 run limited everywhere, all
-    scored by a 1-D radial solution on 2000 shells.  Every run stays positive
-    and finite; the learned blend is no further from the radial solution
-    than the run limited everywhere (parity unpinned: no closed form)."""
+    on the 40^3 mixed mesh with the per-cell positivity rule and the time
+    step on the cell geometry (CFL 0.2): the FP32 path with the committed
+    network against the FP64 classical-sensor run and the FP64 run limited
+    everywhere, all scored by a 1-D radial solution on 2000 shells.  Every
+    run stays positive and finite (without the rule the run limited
+    everywhere loses positivity in a sliver cell near t = 2e-3, at any time
+    step); the learned blend is no further from the radial solution than the
+    run limited everywhere (parity unpinned: no closed form)."""
+    from bench import geometric_dt
     case = configs.shocks_3d(n=40, problem="blast")
     t_end = case.dt * case.steps
+    case.dt, case.steps = geometric_dt(case, 0.2, "euler", t_end=t_end)
     r = np.linalg.norm(fields.cell_points(case.mesh) - 0.5, axis=1)
     rho_ref = fields.blast_reference(t_end, n=2000)(r)[0]
     weights = np.load(os.path.join(ROOT, "paper_2404_08952_amd", "data", "indicator_weights.npy"))
@@ -111,7 +113,8 @@ def test_blast_learned_vs_classical():
     rho = {}
     for label, mode, prec in (("fp64_limited", "limited", "fp64"), ("fp64_classical", "classical", "fp64"),
                               ("fp32_learned", "learned", "fp32")):
-        U, V, diag, th = _run(case, mode, weights, precision=prec)
+        U, V, diag, th = _run(case, mode, weights, precision=prec, positivity=True,
+                              **(dict(u_ref="cell") if prec == "fp32" else {}))
         rho[label] = U[:, 0].astype(np.float64)
         res[label] = dict(l1_rho=float(np.sum(V * np.abs(rho[label] - rho_ref)) / V.sum()),
                           min_rho=float(diag[5]), min_p=float(diag[6]), nonfinite=float(diag[7]),

@@ -108,3 +108,75 @@ def test_positivity_fallback_fp32_reference_state(name, scheme, flux, form):
     errs = [rel_l2(R[:, 0], ref[:, 0]), rel_l2(R[:, 1:4], ref[:, 1:4]), rel_l2(R[:, 4], ref[:, 4])]
     assert max(errs) <= 1e-5, errs
     s.close()
+
+
+# ---------------------------------------------------------------- positivity of the cell averages
+@pytest.mark.parametrize("name,scheme,flux,blend", [("mixed3d", "USR3", "rusanov", "theta"),
+                                                    ("mixed3d", "USR5", "hllc", "none"),
+                                                    ("tet3d", "CSR4", "rusanov", "none")])
+def test_cell_positivity_scaling_fp64(name, scheme, flux, blend):
+    """The per-cell scaling of the face-side states (params positivity): FP64
+    residual and exported face states equal the oracle's element by element
+    on states where many cells are scaled."""
+    from oracle import positivity as OP
+    mesh = MESHES[name]
+    geo = OG.geometry(mesh)
+    U, _bl, _br = _case(mesh, geo, scheme)
+    kw = dict(pde="euler", scheme=scheme, flux=flux)
+    rng = np.random.default_rng(7)
+    theta = rng.random(mesh.n_cells).astype(np.float32) if blend == "theta" else None
+    s = _solver(mesh, **kw, blend=blend, positivity=True)
+    if theta is not None:
+        th = np.empty_like(theta)
+        th[s.perm] = theta
+        s.set_theta(s.torch.from_numpy(th).to(s.device))
+    th64 = None if theta is None else theta.astype(np.float64)
+    Ud = s.to_internal(U)
+    R = s.to_external(s.residual(Ud))
+    ref = SV.residual(mesh, geo, U, dict(oracle_params(kw), positivity=True), theta=th64)
+    np.testing.assert_allclose(R, ref, rtol=1e-10, atol=1e-12 * np.abs(ref).max())
+    # the scaling acts: it changes the residual of many cells
+    plain = SV.residual(mesh, geo, U, oracle_params(kw), theta=th64)
+    assert (np.abs(plain - ref).max(1) > 1e-6 * np.abs(ref).max()).sum() > 10
+    UL, UR, _F = (x.cpu().numpy() for x in s.face_states(Ud))
+    G = OS.cell_derivs(mesh, geo, U, max(OS.scheme_order(scheme), 1))
+    rL, rR, _ = OS.face_states(mesh, geo, U, scheme, G)
+    if th64 is not None:
+        from oracle import limiter as OL
+        LL, LR = OL.limited_states(mesh, geo, U, G[1])
+        rL, rR = OL.blend(rL, rR, LL, LR, th64, mesh)
+    rL, rR = SV._positivity_fallback(rL, rR, U, mesh, GAMMA)
+    rL, rR, _t = OP.scale_face_states(mesh, geo, U, rL, rR, GAMMA)
+    scale = np.abs(U).max()
+    np.testing.assert_allclose(UL, rL, rtol=1e-10, atol=1e-12 * scale)
+    np.testing.assert_allclose(UR, rR, rtol=1e-10, atol=1e-12 * scale)
+    s.close()
+
+
+def test_cell_positivity_scaling_fp32_cell_form():
+    mesh = MESHES["mixed3d"]
+    geo = OG.geometry(mesh)
+    U, _bl, _br = _case(mesh, geo, "USR5")
+    kw = dict(pde="euler", scheme="USR5", flux="hllc")
+    s = _solver(mesh, precision="fp32", u_ref="cell", positivity=True, **kw)
+    R = s.to_external(s.residual(s.to_internal(U)))
+    ref = SV.residual(mesh, geo, U, dict(oracle_params(kw), positivity=True))
+    errs = [rel_l2(R[:, 0], ref[:, 0]), rel_l2(R[:, 1:4], ref[:, 1:4]), rel_l2(R[:, 4], ref[:, 4])]
+    assert max(errs) <= 1e-5, errs
+    s.close()
+
+
+def test_cell_positivity_refused_where_not_built():
+    from paper_2404_08952_amd import binding as B
+    from synth import mesh as M
+    with pytest.raises(B.DolincError) as e:
+        _solver(MESHES["tri2d"], pde="advection", scheme="USR3", positivity=True)
+    assert e.value.status in (B.EUNSUPPORTED, B.EINVAL)
+    with pytest.raises(B.DolincError) as e:
+        _solver(MESHES["hex3d"], pde="euler", scheme="USR3", flux="rusanov", u_ref=(1, 0, 0, 0, 2.5),
+                positivity=True)
+    assert e.value.status == B.EUNSUPPORTED
+    bm = M.bounded(M.periodic_3d(4, 3, 3), 0)
+    with pytest.raises(B.DolincError) as e:
+        _solver(bm, pde="euler", scheme="USR3", flux="rusanov", positivity=True)
+    assert e.value.status == B.EUNSUPPORTED
