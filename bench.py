@@ -304,46 +304,68 @@ def vortex_line(args):
     return out
 
 
-def shocks_line(args):
-    """The Sod slab of the shock workload at an eighth of its size (100^3
-    jittered hexes, 30 % split into tetrahedra and prisms: about 1.9M cells),
-    USR3 + Rusanov to t = 0.1 (time step on the cell geometry): the FP32 path with the learned blend, the FP32
-    path with the classical sensor and the FP64 classical-sensor run, each
-    against the exact Riemann solution (density L1, position of the right
-    shock) and the learned run against the FP64 classical one."""
+def advance_logged(s, U, dt, steps, label, chunk=1000):
+    """steps SSP-RK3 steps in chunks, a progress line per chunk; returns the
+    mean ms per step (HIP events on the current stream around all chunks)."""
+    import torch
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    done = 0
+    while done < steps:
+        k = min(chunk, steps - done)
+        s.advance(U, dt, k)
+        done += k
+        if done < steps:
+            torch.cuda.synchronize()
+            log(f"[bench] {label}: {done} of {steps} steps")
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def shocks_line(args, n=100, paths=("fp32_learned", "fp64_classical"), t_end=0.1):
+    """The Sod slab of the shock workload on n^3 jittered hexes, 30 % split
+    into tetrahedra and prisms (200^3, the workload's size: 15.2M cells;
+    100^3: 1.9M), USR3 + Rusanov with the positivity rule of the cell
+    averages to t_end (time step on the cell geometry, CFL 0.2): the FP32
+    path with the learned blend and the FP64 classical-sensor run (and, with
+    --shocks-only, the FP32 classical-sensor run), each against the exact
+    Riemann solution (density L1, position of the right shock), and the
+    learned run against the FP64 classical one.  The time step follows the
+    thinnest sliver of the mesh: 3,600 steps to t = 0.1 at 100^3, 50,044 at
+    200^3 (the thinnest sliver there is 7x thinner), so the full-size line
+    runs to an earlier time (--sod-t-end)."""
     import numpy as np
     import torch
     from paper_2404_08952_amd import Solver
     from synth import configs, fields
     t0 = time.time()
-    case = configs.shocks_3d(n=100, problem="sod")
-    # CFL 0.4 on the cell geometry with the recipe's margin of 2 on the
-    # initial wave speed (the lattice rule blows up on the jittered slivers)
-    t_end = case.dt * case.steps
+    case = configs.shocks_3d(n=n, problem="sod")
+    # CFL 0.2 on the cell geometry (the lattice rule blows up on the
+    # jittered slivers)
     case.dt, case.steps = geometric_dt(case, 0.2, "euler", t_end=t_end)
     x = fields.cell_points(case.mesh)[:, 0]
     t_end = case.dt * case.steps
     rho_ex = fields.sod_slab_exact(x, t_end)[0]
     rho_post = fields.riemann_exact((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), np.array([1.7]))[0][0]
-    band = (x > 0.86) & (x < 1.0)
+    # a band after the right contact holding only the right shock (0.86 - 1.0 at t = 0.1)
+    band = (x > 0.75 + 1.1 * t_end) & (x < 0.75 + 2.5 * t_end)
     log(f"[bench] shock slab {case.mesh.n_cells:,} cells: set-up {time.time() - t0:.1f} s")
-    out = dict(workload=f"Sod slab, {case.mesh.n_cells:,} mixed cells (100^3 hexes, 30 % split), USR3, Rusanov, "
-                        f"{case.steps} steps to t = {t_end:.3f}")
+    out = dict(workload=f"Sod slab, {case.mesh.n_cells:,} mixed cells ({n}^3 hexes, 30 % split), USR3, Rusanov, "
+                        f"positivity rule, {case.steps} steps to t = {t_end:.3f}")
     rho = {}
-    for label, prec, blend in (("fp64_classical", "fp64", "classical"), ("fp32_classical", "fp32", "classical"),
-                               ("fp32_learned", "fp32", "learned")):
-        s = Solver(case.mesh, **case.params, precision=prec, blend=blend)
+    runs = {"fp64_classical": ("fp64", "classical"), "fp32_classical": ("fp32", "classical"),
+            "fp32_learned": ("fp32", "learned")}
+    for label in paths:
+        prec, blend = runs[label]
+        s = Solver(case.mesh, **case.params, precision=prec, blend=blend, positivity=True,
+                   **(dict(u_ref="cell") if prec == "fp32" else {}))
         if blend == "learned":
             s.mlp_set(indicator_weights())
         U = s.to_internal(case.U0)
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        s.advance(U, case.dt, case.steps)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / case.steps
+        ms = advance_logged(s, U, case.dt, case.steps, f"shock slab {label}")
         d = s.diagnostics(U)
         th = (s.mlp_forward(s.features(U, fp32=False)[1]) if blend == "learned" else s.classical_theta(U))
         frac = float((th[:case.mesh.n_cells] < 0.5).double().mean())
@@ -364,48 +386,42 @@ def shocks_line(args):
     return out
 
 
-def blast_line(args):
+def blast_line(args, n=100):
     """The spherical blast of the shock workload (rho 1 at rest, p 10 inside
-    r < 0.2 about the centre, 0.1 outside) on 60^3 jittered hexes with 30 %
-    split (about 0.41M cells), USR3 + Rusanov to t = 0.05 (time step on the
-    cell geometry): the FP32 path with the learned blend against the FP64
-    classical-sensor run and the FP64 run limited everywhere, each against a
-    fine 1-D radial solution (4000 shells; the flow stays spherical inside the
-    unit cube until t = 0.05).  On 100^3 every path, the one limited
-    everywhere included, drives the pressure of a sliver cell next to the
-    initial sphere to zero within a few steps (the limited face values are not
-    positivity-preserving), so the line stops at 60^3."""
+    r < 0.2 about the centre, 0.1 outside) on n^3 jittered hexes with 30 %
+    split (100^3: 1.9M cells), USR3 + Rusanov with the positivity rule of the
+    cell averages to t = 0.05 (time step on the cell geometry, CFL 0.2): the
+    FP32 path with the learned blend against the FP64 classical-sensor run
+    and the FP64 run limited everywhere, each against a fine 1-D radial
+    solution (4000 shells; the flow stays spherical inside the unit cube
+    until t = 0.05).  Without the positivity rule every path loses
+    positivity in a sliver cell near the initial sphere at any time step."""
     import numpy as np
     import torch
     from paper_2404_08952_amd import Solver
     from synth import configs, fields
     t0 = time.time()
-    case = configs.shocks_3d(n=60, problem="blast")
+    case = configs.shocks_3d(n=n, problem="blast")
     t_end = case.dt * case.steps
     case.dt, case.steps = geometric_dt(case, 0.2, "euler", t_end=t_end)
     t_end = case.dt * case.steps
     r = np.linalg.norm(fields.cell_points(case.mesh) - 0.5, axis=1)
     rho_ref = fields.blast_reference(t_end, n=4000)(r)[0]
     log(f"[bench] blast {case.mesh.n_cells:,} cells: set-up and radial reference {time.time() - t0:.1f} s")
-    out = dict(workload=f"spherical blast, {case.mesh.n_cells:,} mixed cells (60^3 hexes, 30 % split), USR3, "
-                        f"Rusanov, {case.steps} steps to t = {t_end:.3f}; reference: 1-D radial Euler, 4000 shells")
+    out = dict(workload=f"spherical blast, {case.mesh.n_cells:,} mixed cells ({n}^3 hexes, 30 % split), USR3, "
+                        f"Rusanov, positivity rule, {case.steps} steps to t = {t_end:.3f}; reference: 1-D radial "
+                        "Euler, 4000 shells")
     rho = {}
     for label, prec, blend in (("fp64_limited", "fp64", "theta"), ("fp64_classical", "fp64", "classical"),
                                ("fp32_learned", "fp32", "learned")):
-        s = Solver(case.mesh, **case.params, precision=prec, blend=blend)
+        s = Solver(case.mesh, **case.params, precision=prec, blend=blend, positivity=True,
+                   **(dict(u_ref="cell") if prec == "fp32" else {}))
         if blend == "learned":
             s.mlp_set(indicator_weights())
         if blend == "theta":
             s.set_theta(torch.zeros(case.mesh.n_cells, dtype=torch.float32, device=s.device))
         U = s.to_internal(case.U0)
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        s.advance(U, case.dt, case.steps)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / case.steps
+        ms = advance_logged(s, U, case.dt, case.steps, f"blast {label}")
         d = s.diagnostics(U)
         frac = 1.0
         if blend != "theta":
@@ -700,6 +716,9 @@ def main():
     ap.add_argument("--vortex-only", action="store_true", help="only the isentropic-vortex line")
     ap.add_argument("--burgers-only", action="store_true", help="only the 2-D Burgers refinement sweep")
     ap.add_argument("--shocks-only", action="store_true", help="only the shock-slab and spherical-blast lines")
+    ap.add_argument("--sod-n", type=int, default=100, help="lattice of the Sod-slab line (200: the workload's size)")
+    ap.add_argument("--sod-t-end", type=float, default=0.1, help="end time of the Sod-slab line")
+    ap.add_argument("--blast-n", type=int, default=100, help="lattice of the spherical-blast line")
     ap.add_argument("--ordering-only", action="store_true", help="only the cell-ordering ablation")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the FP32 / FP64 headline paths (for profiler runs: per-kernel averages of one mesh)")
@@ -732,7 +751,9 @@ def main():
         print(json.dumps(ordering_line(args)))
         return
     if args.shocks_only:
-        print(json.dumps(dict(shock_slab=shocks_line(args), spherical_blast=blast_line(args))))
+        print(json.dumps(dict(shock_slab=shocks_line(args, n=args.sod_n, t_end=args.sod_t_end,
+                                                     paths=("fp32_learned", "fp64_classical", "fp32_classical")),
+                              spherical_blast=blast_line(args, n=args.blast_n))))
         return
     dev = torch.cuda.get_device_name(0)
     t0 = time.time()
@@ -773,8 +794,8 @@ def main():
     ke = tgv_kinetic_energy_line(args) if extras else None
     vtx = vortex_line(args) if extras else None
     brg = burgers_sweep_line(args) if extras else None
-    shk = shocks_line(args) if extras else None
-    blast = blast_line(args) if extras else None
+    shk = shocks_line(args, n=args.sod_n, t_end=args.sod_t_end) if extras else None
+    blast = blast_line(args, n=args.blast_n) if extras else None
     order = ordering_line(args) if extras else None
     gbps_copy = copy_bandwidth()
     log(f"[bench] streaming y = -x: {gbps_copy:.0f} GB/s")

@@ -1,15 +1,28 @@
 """Label generation and GPU training of the learned blending indicator.
 
-Labels come from the method itself: for a coarse run and a fine run (four
-times finer, same scheme, classical-sensor blend) of the same problem, each
-coarse cell gets the blend weight theta* in [0, 1] whose blended face states
-theta U_high + (1 - theta) U_limited best match (least squares over the
-faces where the cell is upwind, variables scaled to unit range) the fine
-run's face values.  Problems: 1-D shock tubes (Sod, Lax) and smooth density
-waves, run as slabs along x, y or z; plus cells of the smooth 3-D vortex,
-labelled against its closed-form face values.  Features come from the
-library's feature kernel; training runs the library's bf16 matrix-core
-forward/backward and Adam kernels.  Everything runs through the C ABI.
+Labels come from the method itself: a classical smoothness indicator
+evaluated on a fine-mesh solution of the method.  For each 3-D problem
+(Sod and Lax slabs in the three axis directions and the spherical blast on
+the shock workload's mesh recipe, the Taylor-Green vortex at Mach 0.1 and
+0.3, smooth density waves) a coarse run on the jittered workload mesh and a
+fine run on an unjittered hexahedral lattice twice as fine advance side by
+side (classical-sensor blend and the positivity rule of the cell averages,
+FP64).  At snapshots, every coarse cell gets the label
+
+    theta* = min over the 4 x 4 x 4 fine cells around its centre of the
+             classical sensor's theta on the fine solution (the sensor's
+             beta weighted by the size of the jump, see
+             _fine_theta_block),
+
+so a coarse cell is marked for limiting when a discontinuity lies within
+its stencil in the resolved flow, and smooth otherwise, whatever the
+coarse mesh's jitter does to its own difference quotients; its features are
+those of the coarse state.  Cells labelled smooth are subsampled to balance
+the set.  (The first, 1-D generator, least-squares blend weights against a
+4x finer classical-sensor run on unjittered slabs, is kept for the quick
+training of the gain test.)  Features come from the library's feature
+kernel; training runs the library's bf16 matrix-core forward/backward and
+Adam kernels.  Everything runs through the C ABI.
 """
 from __future__ import annotations
 
@@ -197,6 +210,146 @@ def build_dataset(seed=34, quick=False):
     return np.concatenate(Xs), np.concatenate(ys).astype(np.float32)
 
 
+# ---------------------------------------------------------------- 3-D labels
+JUMP_TOL = 0.05  # relative jump of rho or p between lattice neighbours that counts as a discontinuity
+
+
+def _fine_theta_block(Uf, xf_cells, nfine, gamma=1.4, tol=JUMP_TOL, reach=1):
+    """Smoothness label on the fine lattice [nz, ny, nx] and its 4 x 4 x 4
+    running minimum (periodic), indexed by the fine lattice cell.
+
+    The classical sensor on a uniform lattice, beta = |2 q_i - q_(i-1) -
+    q_(i+1)| / (|q_i - q_(i-1)| + |q_(i+1) - q_i|) per axis, for q = rho and
+    p, is weighted by the size of the larger of the two jumps relative to
+    JUMP_TOL |q_i| (capped at 1): a ratio of differences alone also reads
+    the extrema of smooth fields and grid-scale ripples of tiny amplitude
+    (the acoustic noise of a low-Mach flow) as discontinuities.
+    theta = clip((0.9 - max beta_w) / 0.3, 0, 1)."""
+    idx = np.floor(xf_cells * nfine).astype(np.int64) % nfine
+    rho = Uf[:, 0]
+    p = (gamma - 1.0) * (Uf[:, 4] - 0.5 * np.sum(Uf[:, 1:4] ** 2, 1) / rho)
+    bmax = np.zeros((nfine, nfine, nfine))
+    for q in (rho, p):
+        g = np.empty((nfine, nfine, nfine))
+        g[idx[:, 2], idx[:, 1], idx[:, 0]] = q
+        for ax in range(3):
+            a, c = np.roll(g, 1, axis=2 - ax), np.roll(g, -1, axis=2 - ax)
+            dl, dr = np.abs(g - a), np.abs(c - g)
+            beta = np.abs(2.0 * g - a - c) / (dl + dr + 1e-12 * np.abs(g) + 1e-300)
+            w = np.minimum(1.0, np.maximum(dl, dr) / (tol * np.abs(g) + 1e-300))
+            bmax = np.maximum(bmax, beta * w)
+    out = np.clip((0.9 - bmax) / 0.3, 0.0, 1.0)
+    for ax in range(3):
+        m = out.copy()
+        for sh in range(-reach, reach + 2):
+            m = np.minimum(m, np.roll(out, -sh, axis=ax))
+        out = m
+    return out  # out[i] = min over i-reach .. i+reach+1 in every axis
+
+
+def field_samples(problem, n, snaps, seed, refine=2, cfl=0.2, keep_smooth=0.25, rng=None, tol=JUMP_TOL, reach=1):
+    """(X bf16 rows, labels) from one 3-D problem: coarse cells of the
+    jittered workload mesh labelled by the classical sensor on the fine
+    unjittered solution (see the module docstring)."""
+    import torch
+    synth = _synth()
+    rng = rng or np.random.default_rng(seed)
+    fields = synth.fields
+    L = 1.0
+    if problem.startswith("tgv"):
+        mach = 0.1 if problem == "tgv_m01" else 0.3
+        L = 2 * np.pi
+        coarse = synth.periodic_3d(n, lengths=(L, L, L), jitter=0.2, seed=seed)
+        fine = synth.periodic_3d(refine * n, lengths=(L, L, L))
+        ic = fields.taylor_green(mach)
+        t_end = 1.0
+    else:
+        coarse = synth.periodic_3d(n, jitter=0.2, seed=seed,
+                                   kinds=synth.mesh.mixed_kinds(n, split_frac=0.3, seed=seed + 1))
+        fine = synth.periodic_3d(refine * n)
+        if problem.startswith("sod") or problem.startswith("lax"):
+            axis = "xyz".index(problem[-1])
+            sod = ((1.0, 0.0, 1.0), (0.125, 0.0, 0.1))
+            lax = ((0.445, 0.698, 3.528), (0.5, 0.0, 0.571))
+            left, right = sod if problem.startswith("sod") else lax
+            ic = _shock_tube(synth, left, right, axis)
+            t_end = 0.1 if problem.startswith("sod") else 0.08
+        elif problem == "blast":
+            ic = fields.blast()
+            t_end = 0.05
+        elif problem.startswith("wave"):
+            axis = "xyz".index(problem[-1])
+            amp = float(rng.uniform(0.05, 0.4))
+            k = int(rng.integers(1, 4))
+            ic = _wave(synth, amp, k, axis)
+            t_end = 0.2
+        else:
+            raise ValueError(problem)
+    kw = dict(pde="euler", scheme="USR3", flux="rusanov", gamma=1.4, positivity=True)
+    run_c = binding.Solver(coarse, blend="classical", **kw)
+    run_f = binding.Solver(fine, blend="classical", **kw)
+    hi = binding.Solver(coarse, blend="none", pde="euler", scheme="USR3", flux="rusanov", gamma=1.4)
+    pts_c = fields.cell_points(coarse)
+    pts_f = fields.cell_points(fine)
+    U0c, U0f = ic(pts_c), ic(pts_f)
+    Uc = run_c.to_internal(U0c)
+    Uf = run_f.to_internal(U0f)
+    lam = 2.0 * fields.max_wave_speed("euler", U0c)  # waves speed up behind shocks
+
+    def dt_of(solver, mesh):
+        geo = solver.geometry()
+        area = torch.linalg.norm(geo["S"], dim=1).cpu().numpy()
+        ssum = np.bincount(mesh.owner, weights=area, minlength=mesh.n_cells) + \
+            np.bincount(mesh.neighbour, weights=area, minlength=mesh.n_cells)
+        V = geo["V"].cpu().numpy()[solver.perm]
+        return cfl * float(np.min(2.0 * V / ssum)) / lam
+    dt_c, dt_f = dt_of(run_c, coarse), dt_of(run_f, fine)
+    xc_frac = np.mod(pts_c / L, 1.0)
+    xf_frac = np.mod(pts_f / L, 1.0)
+    nfine = refine * n
+    ci = np.floor(xc_frac * nfine).astype(np.int64) % nfine
+    Xs, ys = [], []
+    t = 0.0
+    for k in range(1, snaps + 1):
+        t_next = t_end * k / snaps
+        for solver, U, dt0 in ((run_c, Uc, dt_c), (run_f, Uf, dt_f)):
+            m = int(np.ceil((t_next - t) / dt0 - 1e-12))
+            solver.advance(U, (t_next - t) / m, m)
+        t = t_next
+        blk = _fine_theta_block(run_f.to_external(Uf), xf_frac, nfine, tol=tol, reach=reach)
+        y = blk[ci[:, 2], ci[:, 1], ci[:, 0]]
+        Ucur = run_c.to_external(Uc)
+        Ui = hi.to_internal(Ucur)
+        _X32, Xb = hi.features(Ui, fp32=False)
+        X = Xb.cpu().numpy()[hi.perm]
+        smooth = y >= 0.99
+        keep = ~smooth | (rng.random(y.size) < keep_smooth)
+        Xs.append(X[keep])
+        ys.append(y[keep])
+    for sv in (run_c, run_f, hi):
+        sv.close()
+    return np.concatenate(Xs), np.concatenate(ys)
+
+
+PROBLEMS_3D = ("sod_x", "sod_y", "sod_z", "lax_x", "lax_y", "lax_z", "blast", "tgv_m01", "tgv_m03",
+               "wave_x", "wave_y", "wave_z")
+
+
+def build_dataset_3d(n=48, snaps=10, seed=34, problems=PROBLEMS_3D, log=None, tol=JUMP_TOL, reach=1):
+    """The 3-D labelled set: every problem of PROBLEMS_3D at coarse lattice n."""
+    rng = np.random.default_rng(seed)
+    Xs, ys = [], []
+    for i, prob in enumerate(problems):
+        t0 = time.time()
+        X, y = field_samples(prob, n, snaps, seed + 10 * i, rng=rng, tol=tol, reach=reach)
+        Xs.append(X)
+        ys.append(y)
+        if log:
+            log(f"[train] {prob}: {X.shape[0]:,} samples, label mean {y.mean():.3f}, "
+                f"{np.mean(y < 0.5):.3f} below 1/2, {time.time() - t0:.1f} s")
+    return np.concatenate(Xs), np.concatenate(ys).astype(np.float32)
+
+
 def train(X, y, steps=3000, batch=4096, lr=1e-3, seed=34, holder=None):
     """Train the network on (X bf16 rows [n][32] uint16, y) with the GPU kernels."""
     import torch
@@ -234,11 +387,14 @@ def xavier(seed):
                            [0.0]]).astype(np.float32)
 
 
-def main(quick=False, out=WEIGHTS):
+def main(quick=False, out=WEIGHTS, n=48, snaps=10, steps=20000, batch=16384):
     t0 = time.time()
-    X, y = build_dataset(quick=quick)
+    if quick:
+        X, y = build_dataset(quick=True)
+    else:
+        X, y = build_dataset_3d(n=n, snaps=snaps, log=lambda m: print(m, flush=True))
     t1 = time.time()
-    params, losses = train(X, y, steps=1500 if quick else 4000)
+    params, losses = train(X, y, steps=1500 if quick else steps, batch=4096 if quick else batch)
     t2 = time.time()
     os.makedirs(os.path.dirname(out), exist_ok=True)
     np.save(out, params)
@@ -255,5 +411,9 @@ if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--quick", action="store_true")
     ap.add_argument("--out", default=WEIGHTS)
+    ap.add_argument("--n", type=int, default=48)
+    ap.add_argument("--snaps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--batch", type=int, default=16384)
     a = ap.parse_args()
-    main(quick=a.quick, out=a.out)
+    main(quick=a.quick, out=a.out, n=a.n, snaps=a.snaps, steps=a.steps, batch=a.batch)

@@ -1,9 +1,10 @@
 """Taylor-Green vortex (Mach 0.1, jittered hexes) through the C ABI: the
-FP32 reference-state path follows the FP64 path's kinetic-energy history,
-and on this smooth flow the learned indicator keeps more of the high-order
-weight, and dissipates less, than the classical sensor (which the
+FP32 path follows the FP64 path's kinetic-energy history, and on this smooth
+flow the learned indicator leaves the high-order reconstruction alone
+(theta >= 0.9 on at least 90 % of the cells, kinetic-energy decay within
+25 % of the FP64 plain path) where the classical sensor, which the
 first-order-accurate Gauss gradients of a jittered mesh trip almost
-everywhere)."""
+everywhere, limits and dissipates more."""
 import numpy as np
 import pytest
 
@@ -37,7 +38,7 @@ def _history(case, steps, **kw):
         th = s.classical_theta(U)[:n]
     s.close()
     torch.cuda.synchronize()
-    return np.array(h), (None if th is None else float(th.mean()))
+    return np.array(h), (None if th is None else (float(th.mean()), float((th >= 0.9).double().mean())))
 
 
 def test_tgv_fp32_follows_fp64_and_learned_beats_classical():
@@ -50,8 +51,10 @@ def test_tgv_fp32_follows_fp64_and_learned_beats_classical():
     assert k64[-1] < k64[0] and abs((k32[0] - k32[-1]) / (k64[0] - k64[-1]) - 1) < 0.1
     kl, thl = _history(case, steps, precision="fp32", blend="learned", **ref)
     kc, thc = _history(case, steps, precision="fp32", blend="classical", **ref)
-    assert thl > thc + 0.3, (thl, thc)
-    assert k64[0] - k64[-1] < kl[0] - kl[-1] < kc[0] - kc[-1], (k64, kl, kc)
+    assert thl[1] >= 0.9, (thl, thc)
+    assert thl[0] > thc[0] + 0.3, (thl, thc)
+    d64, dl, dc = k64[0] - k64[-1], kl[0] - kl[-1], kc[0] - kc[-1]
+    assert abs(dl / d64 - 1.0) <= 0.25 and dc > 1.25 * d64, (d64, dl, dc)
 
 
 def test_learned_stage_network_stream():
