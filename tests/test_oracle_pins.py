@@ -375,26 +375,6 @@ def test_hllc_star_flux_is_physical_flux_of_star_state():
         np.testing.assert_allclose(F[4], (Es + ps) * Ss, rtol=1e-12, atol=1e-13)
 
 
-def test_second_order_dolinc_unstable_on_jittered_tets():
-    """Recorded finding: on jittered Kuhn tetrahedra the central CSR4 state
-    (U_L = U_R, no upwind dissipation in Rusanov) grows without bound within
-    a few dozen steps, while the upwind-biased USR3 stays bounded; the same
-    CSR4 run on an unjittered mesh stays bounded."""
-    def blows_up(jitter, scheme, steps=40):
-        case = configs.vortex_3d(n=6, jitter=jitter, point_ic=True, scheme=scheme)
-        geo = OG.geometry(case.mesh)
-        U = case.U0.copy()
-        with np.errstate(all="ignore"):
-            for _ in range(steps):
-                U = SV.rk_step(case.mesh, geo, U, case.dt, case.params)
-                if not np.all(np.isfinite(U)) or U[:, 0].min() <= 0:
-                    return True
-        return False
-    assert blows_up(0.2, "CSR4")
-    assert not blows_up(0.2, "USR3")
-    assert not blows_up(0.0, "CSR4")
-
-
 # ---------------------------------------------------------------- ENO3 / WENO5
 def test_weno5_linear_weights_uniform_and_consistent():
     """Uniform mesh: the textbook weights (3/10, 6/10, 1/10) for the stencils
