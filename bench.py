@@ -636,10 +636,13 @@ def copy_bandwidth():
     return gbps
 
 
-def cpu_baseline_leg(budget_s, workload):
+def cpu_baseline_leg(budget_s, workload, lattice):
     """The FP64 oracle, single-threaded, on a bounded sample of the workload:
     the same pipeline (for the Taylor-Green workload: features, indicator
-    network, blended USR5 + HLLC residual) on a smaller lattice."""
+    network, blended USR5 + HLLC residual) on the same generator's mesh at a
+    smaller lattice -- by default the 126^3 (2.0M-cell) subset mesh of the
+    Taylor-Green workload, or the vortex workload's full 64^3 mesh.  Stages
+    run until the budget is spent (at these sizes: one stage)."""
     import numpy as np
 
     from oracle import geometry as OG
@@ -647,14 +650,16 @@ def cpu_baseline_leg(budget_s, workload):
     from oracle import scheme as OS
     from oracle import solver as SV
     from synth import configs
+    t_set = time.perf_counter()
     if workload == "tgv3d":
-        case = configs.taylor_green_3d(n=24)
+        case = configs.taylor_green_3d(n=lattice)
         params = indicator_weights().astype(np.float64)
     else:
-        case = configs.vortex_3d(n=24, point_ic=True, scheme="USR3")
+        case = configs.vortex_3d(n=lattice, point_ic=True, scheme="USR3")
         params = None
     geo = OG.geometry(case.mesh)
     U = case.U0
+    t_set = time.perf_counter() - t_set
 
     def stage():
         th = None
@@ -662,7 +667,6 @@ def cpu_baseline_leg(budget_s, workload):
             X = OI.features(case.mesh, geo, U, OS.gauss_linear(case.mesh, geo, U))
             th, _ = OI.forward(params, X)
         return SV.residual(case.mesh, geo, U, case.params, theta=th)
-    stage()  # warm
     n, t0 = 0, time.perf_counter()
     while True:
         stage()
@@ -674,9 +678,10 @@ def cpu_baseline_leg(budget_s, workload):
     return dict(value=case.mesh.n_cells * n / dt, unit="cell-updates/s", cores=1, kind="oracle",
                 sample=(f"oracle residual stages (FP64 NumPy, same scheme and flux"
                         f"{', indicator features + network + blend' if params is not None else ''}) on the "
-                        f"same workload at a {lat}^3 lattice ({case.mesh.n_cells:,} cells), {n} stages in "
-                        f"{dt:.1f} s, one thread"),
-                cpu=_cpu_model(), host_cpus=os.cpu_count(), stages=n, seconds=dt)
+                        f"same workload's generator at a {lat}^3 lattice ({case.mesh.n_cells:,} cells), "
+                        f"{n} stage(s) in {dt:.1f} s, one thread, run beside the GPU legs "
+                        f"(mesh and geometry set-up {t_set:.0f} s, untimed)"),
+                cpu=_cpu_model(), host_cpus=os.cpu_count(), stages=n, seconds=dt, lattice=lat)
 
 
 def _cpu_model():
@@ -689,16 +694,32 @@ def _cpu_model():
     return "unknown"
 
 
-def run_cpu_baseline(budget_s, workload):
+def start_cpu_baseline(budget_s, workload, lattice):
+    """The oracle leg in a child process of its own (one thread), started
+    before the GPU legs so that its minutes overlap theirs."""
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1",
                NUMEXPR_NUM_THREADS="1")
     cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-only", "--cpu-budget", str(budget_s),
-           "--workload", workload]
-    r = subprocess.run(cmd, env=env, capture_output=True, text=True, timeout=600)
-    if r.returncode != 0:
-        log(r.stderr[-2000:])
+           "--workload", workload, "--cpu-lattice", str(lattice)]
+    return subprocess.Popen(cmd, env=env, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
+
+
+def finish_cpu_baseline(proc, timeout_s=900):
+    try:
+        out, err = proc.communicate(timeout=timeout_s)
+    except subprocess.TimeoutExpired:
+        proc.kill()
+        proc.communicate()
+        log("[bench] CPU oracle baseline did not finish in time")
         return None
-    return json.loads(r.stdout.strip().splitlines()[-1])
+    if proc.returncode != 0:
+        log(err[-2000:])
+        return None
+    return json.loads(out.strip().splitlines()[-1])
+
+
+def cpu_lattice(args):
+    return args.cpu_lattice or (126 if args.workload == "tgv3d" else 64)
 
 
 def main():
@@ -709,6 +730,8 @@ def main():
     ap.add_argument("--workload", default="tgv3d", choices=["vortex3d", "tgv3d"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--cpu-lattice", type=int, default=0,
+                    help="lattice of the oracle sample (default: 126 for the Taylor-Green workload, 64 for the vortex)")
     ap.add_argument("--cpu-baseline-only", action="store_true")
     ap.add_argument("--indicator-only", action="store_true",
                     help="only the indicator network's inference / training throughput (for counter runs)")
@@ -725,7 +748,7 @@ def main():
     args = ap.parse_args()
 
     if args.cpu_baseline_only:
-        print(json.dumps(cpu_baseline_leg(args.cpu_budget, args.workload)))
+        print(json.dumps(cpu_baseline_leg(args.cpu_budget, args.workload, cpu_lattice(args))))
         return
     if args.gpus != 1:
         raise SystemExit("this benchmark runs on one GPU only (no multi-GPU path is built); use --gpus 1")
@@ -755,6 +778,10 @@ def main():
                                                      paths=("fp32_learned", "fp64_classical", "fp32_classical")),
                               spherical_blast=blast_line(args, n=args.blast_n))))
         return
+    cpu_proc = None
+    if not args.no_cpu_baseline:
+        log(f"[bench] CPU oracle baseline started beside the GPU legs ({cpu_lattice(args)}^3 lattice)")
+        cpu_proc = start_cpu_baseline(args.cpu_budget, args.workload, cpu_lattice(args))
     dev = torch.cuda.get_device_name(0)
     t0 = time.time()
     case, desc, extra, fp32_extra = make_case(args.workload)
@@ -899,9 +926,9 @@ def main():
         "device": dev,
         "copy_gbps": gbps_copy,
     }
-    if not args.no_cpu_baseline:
-        log("[bench] CPU oracle baseline ...")
-        out["cpu_baseline"] = run_cpu_baseline(args.cpu_budget, args.workload)
+    if cpu_proc is not None:
+        log("[bench] waiting for the CPU oracle baseline ...")
+        out["cpu_baseline"] = finish_cpu_baseline(cpu_proc)
     print(json.dumps(out))
 
 
