@@ -82,6 +82,12 @@ def grad_features_bytes(nc, nrec, nv, dim, el):
     return nc * (nv * el + el + 4 + nv * dim * el + 48) + nrec * 7 * el
 
 
+def grad_bytes(nc, nrec, nv, dim, el):
+    """The plain first-gradient kernel: U and 1/V per cell, the records'
+    sigma w S and other cell (it needs no face vector), G1 written."""
+    return nc * (nv * el + el + nv * dim * el) + nrec * 4 * el
+
+
 def hface_bytes(nc, nrec, nv, dim, el):
     """Algorithmic bytes of the second-derivative kernel: the cell's G1 row,
     1/V and its face count per cell, the two face records (7 values) and
@@ -854,7 +860,7 @@ def main():
         if blend:
             add("k_grad_features", 2, grad_features_bytes(nc, nrec, nv, dim, el))
         else:
-            add("k_grad", 0, grad_features_bytes(nc, nrec, nv, dim, el) - nc * 48)
+            add("k_grad", 0, grad_bytes(nc, nrec, nv, dim, el))
         add("k_hface", 1, hface_bytes(nc, nrec, nv, dim, el))
         comp = COMPULSORY_BYTES[prec] * cups / 1e9
         return dict(value=cups, ms_per_step=r["ms_per_step"], ms_per_stage=r["ms_per_step"] / 3,

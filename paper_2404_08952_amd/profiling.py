@@ -31,14 +31,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # sources that the stage kernels are compiled from
 FLUX_SOURCES = ("csrc/residual_impl.hpp", "csrc/dispatch_impl.hpp", "csrc/kernels_f32.hip",
                 "csrc/indicator_impl.hpp", "csrc/indicator.hip", "csrc/coefficients.hpp")
-FLUX_KERNEL = r"k_flux<float, 3, 3, 5, true, 2>"
+FLUX_KERNEL = r"k_flux<float, 3, 3, 5, true, 2, 0>"
 # the stage kernels of the headline workload (USR5 + HLLC + learned blend):
 # short name -> kernel-name pattern, FP32 (cell-reference form) and FP64
 STAGE_KERNELS = (
-    ("fp32 k_flux", re.escape("k_flux<float, 3, 3, 5, true, 2>")),
+    ("fp32 k_flux", re.escape("k_flux<float, 3, 3, 5, true, 2, 0>")),
     ("fp32 k_grad_features", re.escape("k_grad_features<float, 3>")),
     ("fp32 k_hface", re.escape("k_hface_w5<float, 3, 5>")),
-    ("fp64 k_flux", re.escape("k_flux<double, 3, 3, 5, true, 0>")),
+    ("fp64 k_flux", re.escape("k_flux<double, 3, 3, 5, true, 0, 0>")),
     ("fp64 k_grad_features", re.escape("k_grad_features<double, 3>")),
     ("fp64 k_hface", re.escape("k_hface<double, 3, 5>")),
     ("k_mlp_fwd", re.escape("k_mlp_fwd")),

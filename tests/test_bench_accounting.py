@@ -25,6 +25,8 @@ def test_gradient_kernel_bytes_taylor_green_fp32():
     nrec = 6 * nc  # six face records per hexahedron
     # per cell: U 20 + 1/V 4 + face count 4 + G1 60 + features 48; per record: 16 + 12 bytes of records
     assert bench.grad_features_bytes(nc, nrec, 5, 3, 4) == nc * (20 + 4 + 4 + 60 + 48) + nrec * 28
+    # plain gradient: U 20 + 1/V 4 + G1 60 per cell, sigma w S and the other cell (16) per record
+    assert bench.grad_bytes(nc, nrec, 5, 3, 4) == nc * (20 + 4 + 60) + nrec * 16
     # per cell: G1 60 + 1/V 4 + face count 4; per record: records 28 + d.H.d 20
     assert bench.hface_bytes(nc, nrec, 5, 3, 4) == nc * (60 + 4 + 4) + nrec * (28 + 20)
     assert bench.COMPULSORY_BYTES["fp32"] == 360 and bench.COMPULSORY_BYTES["fp64"] == 504
