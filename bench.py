@@ -61,11 +61,7 @@ def flux_kernel_bytes(nc, nf, nv, dim, el, scheme, blend=False):
     """Algorithmic bytes of one flux + update launch: every array it needs
     read once, its output written once (Un counted in 2 of 3 stages)."""
     ord_ = 0 if scheme in ("FOU", "CD2") else (1 if scheme in ("USR3", "CSR4") else 2)
-    if el == 4 or scheme in ("ENO3", "WENO5"):
-        dcs = 3  # d; the coefficients are evaluated in the kernel from omega
-    else:        # FP64: d and the stored coefficients of both sides
-        nc_ = {"FOU": 2, "CD2": 2, "USR3": 4, "CSR4": 3, "USR5": 8, "CSR6": 5}[scheme]
-        dcs = (3 + nc_ + 3) & ~3
+    dcs = 3  # d; the coefficients are evaluated in the kernel from omega
     # second differentials arrive contracted with d, one value per face side
     per_cell = nv * el + (nv * dim * el if ord_ >= 1 or blend else 0) \
         + el + 4 + nv * el + (2.0 / 3.0) * nv * el + (4 if blend else 0)

@@ -86,10 +86,11 @@ typedef enum {
  * (Sec. 3.3); RUSANOV: local Lax-Friedrichs (Sec. 3.4); HLLC (Toro). */
 typedef enum { DOLINC_FLUX_UPWIND = 0, DOLINC_FLUX_RUSANOV = 1, DOLINC_FLUX_HLLC = 2 } dolinc_flux;
 
-/* FP64: all arithmetic in double.  FP32_MIXED: geometry and inversion /
- * reconstruction coefficients computed in double, stored rounded to float;
- * gradient, reconstruction, flux and update in float with compensated
- * (Neumaier) face-to-cell sums. */
+/* FP64: all arithmetic in double.  FP32_MIXED: geometry computed in double
+ * and stored rounded to float; the inversion / reconstruction coefficients
+ * evaluated in double from each face's growth rate in the flux kernel and
+ * rounded once to float; gradient, reconstruction, flux and update in float
+ * with compensated (Neumaier) face-to-cell sums. */
 typedef enum { DOLINC_FP64 = 0, DOLINC_FP32_MIXED = 1 } dolinc_precision;
 
 /* Blend of the high-order face state with a Van Leer limited second-order
@@ -218,10 +219,12 @@ dolinc_status dolinc_stats(dolinc_ctx ctx, dolinc_mesh_stats* stats);
 dolinc_status dolinc_set_boundary(dolinc_ctx ctx, int32_t patch, int32_t type, const double* values);
 
 /* FP64 precompute on the device (Sec. 2.2 growth rate g and weight omega,
- * centre distance d; Sec. 2.3-2.4 inversion and reconstruction coefficients
- * folded into the DOLINC representation eq:USR3 / eq:CSR4), then allocates
- * the gradient and Runge-Kutta workspaces.  Synchronises before returning.
- * May be called again to change params (re-allocates as needed). */
+ * centre distance d, face area vectors, volumes; the flux kernel evaluates
+ * the Sec. 2.3-2.4 inversion and reconstruction coefficients, folded into
+ * the DOLINC representation eq:USR3 / eq:CSR4, from g in double), then
+ * allocates the gradient and Runge-Kutta workspaces.  Synchronises before
+ * returning.  May be called again to change params (re-allocates as
+ * needed). */
 dolinc_status dolinc_precompute(dolinc_ctx ctx, const dolinc_params* params, dolinc_stream s);
 
 /* R = dU/dt = -V^-1 sum_f sigma F_f (device [n_cells][n_v] each, U != R). */

@@ -13,14 +13,11 @@ namespace dolinc {
 
 // Per-face record layout (one record per partition entry).
 //   sw[e][4]  : S_x, S_y, S_z (0 in 2-D), omega (owner weight)
-//   dc[e][DC] : d_x, d_y, d_z, then (FP64 working type, linear schemes) the
-//               coefficients of the DOLINC representation of each side in
-//               the order of face_coefficients (coefficients.hpp); else d
-//               alone (DC = 3): the FP32 flux kernel and the nonlinear
-//               schemes evaluate the coefficients in FP64 from the growth
-//               rate g = omega / (1 - omega) of the entry's omega (fewer
-//               bytes per entry; the FP64 kernel, short of registers, reads
-//               them).
+//   dc[e][3]  : d_x, d_y, d_z.  The flux kernel evaluates the coefficients
+//               of the DOLINC representation in FP64 from the growth rate
+//               g = omega / (1 - omega) of the entry's omega
+//               (face_coefficients, coefficients.hpp): arithmetic is cheaper
+//               than 8 more values per entry in a memory-bound kernel.
 // Per-cell face records in sliced ELL order: cells are taken in blocks of
 // ELL_BLOCK; block b holds m_b = (max faces of a cell in b) records per
 // cell, record j of cell lane l at ell_ptr[b] + j * ELL_BLOCK + l, so that
@@ -36,17 +33,8 @@ namespace dolinc {
 //                  records j >= its face count (slot_ptr) are padding.
 constexpr int ELL_BLOCK = 256;
 inline bool nonlinear_scheme(int scheme) { return scheme == 6 || scheme == 7; }
-// coefficients per face of the linear schemes (both sides)
-inline int face_coef_count(int scheme) {
-  return scheme <= 2 ? 2 : scheme == 3 ? 4 : scheme == 4 ? 3 : scheme == 8 ? 5 : 8;
-}
-inline bool coefficients_stored(int scheme, int precision) {
-  return precision == DOLINC_FP64 && !nonlinear_scheme(scheme);
-}
-inline int dc_stride(int scheme, int precision) {
-  if (!coefficients_stored(scheme, precision)) return 3;
-  return (3 + face_coef_count(scheme) + 3) & ~3;
-}
+// values per face entry in dc (d)
+inline int dc_stride(int /*scheme*/, int /*precision*/) { return 3; }
 inline int scheme_order(int scheme) { return scheme <= 2 ? 0 : scheme <= 4 ? 1 : 2; }
 
 struct DevMesh {

@@ -14,7 +14,6 @@
 // evaluates them in FP64 (coefficients.hpp).
 #include <hip/hip_runtime.h>
 
-#include "coefficients.hpp"
 #include "internal.hpp"
 
 namespace dolinc {
@@ -169,10 +168,9 @@ __global__ void k_face_scalars(int64_t nf, int dim, const int32_t* __restrict__ 
 }
 
 template <class T>
-__global__ void k_entry_fill(int64_t ne, int dim, int scheme, int dcs, const int32_t* __restrict__ ent_face,
+__global__ void k_entry_fill(int64_t ne, int dcs, const int32_t* __restrict__ ent_face,
                              const double* __restrict__ S, const double* __restrict__ omega,
-                             const double* __restrict__ g, const double* __restrict__ dvec, T* __restrict__ sw,
-                             T* __restrict__ dc) {
+                             const double* __restrict__ dvec, T* __restrict__ sw, T* __restrict__ dc) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= ne) return;
   const int f = ent_face[e];
@@ -185,14 +183,8 @@ __global__ void k_entry_fill(int64_t ne, int dim, int scheme, int dcs, const int
   o[0] = (T)dvec[3 * f + 0];
   o[1] = (T)dvec[3 * f + 1];
   o[2] = (T)dvec[3 * f + 2];
-  if (sizeof(T) == 8 && scheme != DOLINC_ENO3 && scheme != DOLINC_WENO5) {
-    // FP64 working type: the coefficients of both sides, stored
-    double cf[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    face_coefficients(scheme, g[f], cf);
-    for (int k = 3; k < dcs; ++k) o[k] = (T)cf[k - 3];
-  }
-  // otherwise d alone: the kernels evaluate the coefficients in FP64 from
-  // the growth rate omega / (1 - omega) of the entry's omega
+  // the kernels evaluate the coefficients in FP64 from the growth rate
+  // omega / (1 - omega) of the entry's omega
 }
 
 // Auxiliary cells of boundary faces: the mirror image of the boundary cell
@@ -293,16 +285,16 @@ hipError_t launch_entry_fill(dolinc_ctx_s* c, hipStream_t s) {
   const int sch = c->params.scheme;
   const int dcs = dc_stride(sch, c->w.precision);
   if (c->w.precision == DOLINC_FP64) {
-    hipLaunchKernelGGL(k_entry_fill<double>, dim3(nblk(c->n_entries)), dim3(TPB), 0, s, c->n_entries, c->dim, sch,
-                       dcs, m.ent_face, m.S, m.omega, m.g, m.dvec, (double*)c->w.sw, (double*)c->w.dc);
+    hipLaunchKernelGGL(k_entry_fill<double>, dim3(nblk(c->n_entries)), dim3(TPB), 0, s, c->n_entries, dcs,
+                       m.ent_face, m.S, m.omega, m.dvec, (double*)c->w.sw, (double*)c->w.dc);
     hipLaunchKernelGGL(k_ell_fill<double>, dim3(nblk(c->n_cells)), dim3(TPB), 0, s, c->n_cells, c->part_cells,
                        m.part_ptr, m.slot_ptr, m.slots, m.ent_pn, m.ell_ptr, dcs, (const double*)c->w.sw,
                        (const double*)c->w.dc, (double*)c->w.ell_sw, (double*)c->w.ell_d);
     hipLaunchKernelGGL(k_recip<double>, dim3(nblk(c->n_cells)), dim3(TPB), 0, s, c->n_cells, m.V,
                        (double*)c->w.rV);
   } else {
-    hipLaunchKernelGGL(k_entry_fill<float>, dim3(nblk(c->n_entries)), dim3(TPB), 0, s, c->n_entries, c->dim, sch,
-                       dcs, m.ent_face, m.S, m.omega, m.g, m.dvec, (float*)c->w.sw, (float*)c->w.dc);
+    hipLaunchKernelGGL(k_entry_fill<float>, dim3(nblk(c->n_entries)), dim3(TPB), 0, s, c->n_entries, dcs,
+                       m.ent_face, m.S, m.omega, m.dvec, (float*)c->w.sw, (float*)c->w.dc);
     hipLaunchKernelGGL(k_ell_fill<float>, dim3(nblk(c->n_cells)), dim3(TPB), 0, s, c->n_cells, c->part_cells,
                        m.part_ptr, m.slot_ptr, m.slots, m.ent_pn, m.ell_ptr, dcs, (const float*)c->w.sw,
                        (const float*)c->w.dc, (float*)c->w.ell_sw, (float*)c->w.ell_d);

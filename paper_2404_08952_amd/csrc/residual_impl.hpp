@@ -83,12 +83,6 @@ template <int SCH>
 struct SchemeInfo {
   static constexpr int ORD = SCH <= 2 ? 0 : (SCH <= 4 ? 1 : 2);
   static constexpr bool NONLIN = SCH == 6 || SCH == 7;  // ENO3, WENO5
-  static constexpr int NC = SCH <= 2 ? 2 : (SCH == 3 ? 4 : (SCH == 4 ? 3 : (SCH == 8 ? 5 : 8)));
-  // values per face entry in dc: d, or (FP64, linear) d and the coefficients
-  template <class T>
-  static constexpr int dcs() {
-    return (NONLIN || sizeof(T) == 4) ? 3 : (3 + NC + 3) & ~3;
-  }
 };
 
 // A partition's cells are a contiguous index range, so their rows of a
@@ -551,7 +545,7 @@ __device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T
   static_assert(REF == 0 || PK >= 2, "reference-state forms are built for the Euler equations");
   static_assert(MODE == 0 || PK >= 2, "the positivity rule is built for the Euler equations");
   constexpr int ORD = SchemeInfo<SCH>::ORD;
-  constexpr int DCS = SchemeInfo<SCH>::template dcs<T>();
+  constexpr int DCS = 3;  // d per face entry
   const int2 pn = a.ent_pn[e];
   const int64_t P = pn.x, N = pn.y;
   const T* swp = a.sw + 4 * e;
@@ -630,13 +624,11 @@ __device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T
     for (int v = 0; v < NV; ++v)
       UR[v] = nonlin_side<T, SCH>(cf, uN[v], uP[v], T(-2) * gN[v], T(-2) * gP[v], T(4) * hN[v]);
   } else {
-    // coefficients of both sides: stored (FP64) or from g in FP64, rounded once to T
+    // coefficients of both sides from the growth rate g = omega / (1 - omega)
+    // of the P -> N frame, in FP64 (the operations that define them; in FP64
+    // the same bits as a stored copy would hold), rounded once to T
     T c[8];
-    if constexpr (DCS > 3) {
-#pragma unroll
-      for (int k = 0; k < 8; ++k) c[k] = 3 + k < DCS ? dc[3 + k] : T(0);
-    } else {
-      // growth rate g = omega / (1 - omega) of the P -> N frame, in FP64
+    {
       double cd[8] = {0, 0, 0, 0, 0, 0, 0, 0};
       face_coefficients(SCH, (double)om / (1.0 - (double)om), cd);
 #pragma unroll

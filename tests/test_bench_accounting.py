@@ -13,10 +13,10 @@ def test_flux_kernel_bytes_taylor_green_fp32():
     assert abs(total - (9.013690368e9 + 4 * nf)) < 1.0
 
 
-def test_flux_kernel_bytes_fp64_stores_coefficients():
+def test_flux_kernel_bytes_fp64():
     _t, per_cell, per_face = bench.flux_kernel_bytes(1, 1, 5, 3, 8, "USR5", blend=True)
-    # FP64: d (3) + 8 coefficients rounded up to a multiple of 4 values = 12 doubles
-    assert per_face == 8 + 32 + 12 * 8 + 4 + 8 + 80
+    # FP64: d (3 doubles); the coefficients are evaluated in the kernel
+    assert per_face == 8 + 32 + 3 * 8 + 4 + 8 + 80
     assert abs(per_cell - (40 + 120 + 8 + 4 + 40 + 40 * 2 / 3 + 4)) < 1e-9
 
 
