@@ -1008,7 +1008,6 @@ __device__ __forceinline__ void grad2_sums(const KArgs<T>& a, const T* __restric
                                            T (*acc2)[D * (D + 1) / 2], const T* lds, int64_t c0, int n) {
   constexpr int NQ = NV * D;
   constexpr int NS2 = D * (D + 1) / 2;
-  constexpr int GB = 1;  // one record, then its row: measured fastest (2 and 3 are slower)
   const int64_t b = c / KTPB;
   const int lane = (int)(c - b * KTPB);
   const int r0 = a.ell_ptr[b], m = (a.ell_ptr[b + 1] - r0) / KTPB;
@@ -1018,41 +1017,42 @@ __device__ __forceinline__ void grad2_sums(const KArgs<T>& a, const T* __restric
   for (int v = 0; v < NV; ++v)
 #pragma unroll
     for (int k = 0; k < NS2; ++k) acc2[v][k] = T(0);
-  for (int j = 0; j < m; j += GB) {
-    int64_t o[GB];
-    T Sw[GB][D];
+  // one record, then its row (batches of 2 or 3 need more registers and
+  // measured slower); the next record is requested before the row, so the
+  // two loads of an iteration wait on one memory latency
+  T nx[4];
+  {
+    GlbPtr<T> rec = as_glb(a.ell_sw + 4 * ((int64_t)r0 + lane));
 #pragma unroll
-    for (int jj = 0; jj < GB; ++jj) {
-      const bool ok = j + jj < m;
-      const int64_t r = (int64_t)r0 + (int64_t)(ok ? j + jj : j) * KTPB + lane;
-      GlbPtr<T> rec = as_glb(a.ell_sw + 4 * r);
-      T v[4];
+    for (int x = 0; x < 4; ++x) nx[x] = m > 0 ? rec[x] : T(0);
+  }
+  for (int j = 0; j < m; ++j) {
+    T v[4];
 #pragma unroll
-      for (int x = 0; x < 4; ++x) v[x] = rec[x];
-      o[jj] = ok ? rec_cell(v[3]) : c;
+    for (int x = 0; x < 4; ++x) v[x] = nx[x];
+    if (j + 1 < m) {
+      GlbPtr<T> rec = as_glb(a.ell_sw + 4 * ((int64_t)r0 + (int64_t)(j + 1) * KTPB + lane));
 #pragma unroll
-      for (int x = 0; x < D; ++x) Sw[jj][x] = ok ? v[x] : T(0);
+      for (int x = 0; x < 4; ++x) nx[x] = rec[x];
     }
-    T qo[GB][NQ];
+    const int64_t o = rec_cell(v[3]);
+    T qo[NQ];
+    load_row<T, NQ>(qo, lds, phi, c0, n, o);
 #pragma unroll
-    for (int jj = 0; jj < GB; ++jj) load_row<T, NQ>(qo[jj], lds, phi, c0, n, o[jj]);
+    for (int v2 = 0; v2 < NV; ++v2) {
+      T dq[D];
 #pragma unroll
-    for (int jj = 0; jj < GB; ++jj)
+      for (int i = 0; i < D; ++i) dq[i] = qo[v2 * D + i] - q[v2 * D + i];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        T dq[D];
-#pragma unroll
-        for (int i = 0; i < D; ++i) dq[i] = qo[jj][v * D + i] - q[v * D + i];
-#pragma unroll
-        for (int i = 0; i < D; ++i) acc2[v][i] += dq[i] * Sw[jj][i];
-        if constexpr (D == 3) {
-          acc2[v][3] += dq[0] * Sw[jj][1] + dq[1] * Sw[jj][0];
-          acc2[v][4] += dq[0] * Sw[jj][2] + dq[2] * Sw[jj][0];
-          acc2[v][5] += dq[1] * Sw[jj][2] + dq[2] * Sw[jj][1];
-        } else {
-          acc2[v][2] += dq[0] * Sw[jj][1] + dq[1] * Sw[jj][0];
-        }
+      for (int i = 0; i < D; ++i) acc2[v2][i] += dq[i] * v[i];
+      if constexpr (D == 3) {
+        acc2[v2][3] += dq[0] * v[1] + dq[1] * v[0];
+        acc2[v2][4] += dq[0] * v[2] + dq[2] * v[0];
+        acc2[v2][5] += dq[1] * v[2] + dq[2] * v[1];
+      } else {
+        acc2[v2][2] += dq[0] * v[1] + dq[1] * v[0];
       }
+    }
   }
 }
 
