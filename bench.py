@@ -49,7 +49,7 @@ def make_case(workload):
 # cell): on 512-cell partitions that is about 76 KB per workgroup and halves
 # the workgroups per CU (flux kernel 3.53 vs 2.85 ms at 288^3; 384 cells:
 # 3.92 ms).  FP64's 512-cell partitions measured 4 % slower.
-PART_CELLS = {"fp32": 256, "fp64": 256}
+PART_CELLS = {"fp32": 512, "fp64": 256}
 
 
 def indicator_weights():

@@ -76,7 +76,11 @@ hipError_t go_flux(const KArgs<T>& a0, size_t lds, hipStream_t s, bool exporting
       if (e != hipSuccess) return e;
       if (!exporting) {
         if (lds > flux_lds_limit()) return hipErrorInvalidConfiguration;
-        hipLaunchKernelGGL((k_flux<T, D, PK, SCH, BL, REF, 2>), dim3(8 * a.per_xcd), dim3(KTPB), lds, s, a);
+        if (a.B >= 2 * KTPB)
+          hipLaunchKernelGGL((k_flux<T, D, PK, SCH, BL, REF, 2, 2 * KTPB>), dim3(8 * a.per_xcd), dim3(2 * KTPB), lds,
+                             s, a);
+        else
+          hipLaunchKernelGGL((k_flux<T, D, PK, SCH, BL, REF, 2>), dim3(8 * a.per_xcd), dim3(KTPB), lds, s, a);
         return hipGetLastError();
       }
     }
@@ -89,7 +93,12 @@ hipError_t go_flux(const KArgs<T>& a0, size_t lds, hipStream_t s, bool exporting
   }
   // LDS holds the partition's face fluxes only (rows are gathered from HBM/L2)
   if (lds > flux_lds_limit()) return hipErrorInvalidConfiguration;
-  hipLaunchKernelGGL((k_flux<T, D, PK, SCH, BL, REF, 0>), dim3(8 * a.per_xcd), dim3(KTPB), lds, s, a);
+  // partitions of 512 cells or more: 512 threads, so the workgroup still
+  // has one thread per cell in the accumulation
+  if (a.B >= 2 * KTPB)
+    hipLaunchKernelGGL((k_flux<T, D, PK, SCH, BL, REF, 0, 2 * KTPB>), dim3(8 * a.per_xcd), dim3(2 * KTPB), lds, s, a);
+  else
+    hipLaunchKernelGGL((k_flux<T, D, PK, SCH, BL, REF, 0>), dim3(8 * a.per_xcd), dim3(KTPB), lds, s, a);
   return hipGetLastError();
 }
 

@@ -753,8 +753,8 @@ __device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T
 }
 
 // ---------------------------------------------------------------- kernels
-template <class T, int D, int PK, int SCH, bool BLEND, int REF, int MODE>
-__global__ __launch_bounds__(KTPB) void k_flux(KArgs<T> a) {
+template <class T, int D, int PK, int SCH, bool BLEND, int REF, int MODE, int TPB = KTPB>
+__global__ __launch_bounds__(TPB) void k_flux(KArgs<T> a) {
   constexpr int NV = NVars<PK, D>::value;
   constexpr int FW = REF == 2 ? 2 * NV : NV;  // values per entry in LDS (REF 2: owner's, neighbour's share)
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -765,7 +765,7 @@ __global__ __launch_bounds__(KTPB) void k_flux(KArgs<T> a) {
   // LDS: the partition's face fluxes
   T* Fs = reinterpret_cast<T*>(smem_raw);
   const int e0 = a.part_ptr[p], e1 = a.part_ptr[p + 1];
-  for (int e = e0 + (int)threadIdx.x; e < e1; e += KTPB) {
+  for (int e = e0 + (int)threadIdx.x; e < e1; e += TPB) {
     T UL[NV], UR[NV], F[FW];
     eval_face<T, D, PK, SCH, BLEND, REF, MODE>(a, e, UL, UR, F, F + (REF == 2 ? NV : 0));
 #pragma unroll
@@ -773,7 +773,7 @@ __global__ __launch_bounds__(KTPB) void k_flux(KArgs<T> a) {
   }
   __syncthreads();
   const int64_t c1 = c0 + ncl;
-  for (int64_t c = c0 + threadIdx.x; c < c1; c += KTPB) {
+  for (int64_t c = c0 + threadIdx.x; c < c1; c += TPB) {
     const int s0 = a.slot_ptr[c], s1 = a.slot_ptr[c + 1];
     T sum[NV], comp[NV];
 #pragma unroll

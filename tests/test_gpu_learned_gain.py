@@ -4,9 +4,9 @@ The network is trained on the GPU from labels the method generates (fine-mesh
 runs of the same scheme) and then drives the blend on a Sod slab over a
 mixed hex / tetrahedron / prism mesh shaped like the shock workload.  It is
 scored by the exact Riemann solution: its density L1 error is no worse than
-the Van Leer limited scheme everywhere, with no positivity failure; the
-classical-sensor blend is reported beside it.  (No closed form fixes the
-size of the gain: parity unpinned.)
+the Van Leer limited scheme everywhere or the classical-sensor blend, with
+no positivity failure.  (No closed form fixes the size of the gain: parity
+unpinned.)
 """
 import json
 import os
@@ -89,6 +89,7 @@ def test_learned_indicator_gain():
     for mode in ("limited", "classical", "learned"):
         assert res[mode]["nonfinite"] == 0 and res[mode]["min_rho"] > 0 and res[mode]["min_p"] > 0, res
     assert res["learned"]["l1_rho"] <= res["limited"]["l1_rho"], res
+    assert res["learned"]["l1_rho"] <= res["classical"]["l1_rho"], res
     assert abs(res["learned"]["shock_pos_err"]) <= abs(res["limited"]["shock_pos_err"]) + 0.5 / 40, res
 
 
@@ -100,8 +101,8 @@ def test_blast_learned_vs_classical():
     everywhere, all scored by a 1-D radial solution on 2000 shells.  Every
     run stays positive and finite (without the rule the run limited
     everywhere loses positivity in a sliver cell near t = 2e-3, at any time
-    step); the learned blend is no further from the radial solution than the
-    run limited everywhere (parity unpinned: no closed form)."""
+    step); the learned blend is no further from the radial solution than
+    either FP64 run (parity unpinned: no closed form)."""
     from bench import geometric_dt
     case = configs.shocks_3d(n=40, problem="blast")
     t_end = case.dt * case.steps
@@ -126,3 +127,6 @@ def test_blast_learned_vs_classical():
     for label in ("fp64_limited", "fp64_classical", "fp32_learned"):
         assert res[label]["nonfinite"] == 0 and res[label]["min_rho"] > 0 and res[label]["min_p"] > 0, res
     assert res["fp32_learned"]["l1_rho"] <= res["fp64_limited"]["l1_rho"], res
+    # and no further than the classical sensor's run (measured 0.08948 vs
+    # 0.08952; the margin allows for rounding-level changes of the kernels)
+    assert res["fp32_learned"]["l1_rho"] <= 1.001 * res["fp64_classical"]["l1_rho"], res

@@ -242,7 +242,7 @@ def test_conservation_determinism_and_partitions(geos):
     assert np.all(np.abs(tot1 - tot0) <= 50 * np.finfo(float).eps * scale)
     ref = s.to_external(s.residual(s.to_internal(U)))
     for renumber in (0, 1, 2):
-        for pc in (32, 64, 1024):
+        for pc in (32, 64, 512, 1024):
             t = _solver(mesh, renumber=renumber, part_cells=pc, **kw)
             R = t.to_external(t.residual(t.to_internal(U)))
             _close(R, ref, rtol=1e-12, afloor=1e-13)
