@@ -65,8 +65,9 @@ def flux_kernel_bytes(nc, nf, nv, dim, el, scheme, blend=False):
     # second differentials arrive contracted with d, one value per face side
     per_cell = nv * el + (nv * dim * el if ord_ >= 1 or blend else 0) \
         + el + 4 + nv * el + (2.0 / 3.0) * nv * el + (4 if blend else 0)
-    # second differentials: the record index pair and d.H.d of both cells
-    per_face = 8 + 4 * el + dcs * el + 4 + (8 + 2 * nv * el if ord_ >= 2 else 0)
+    # second differentials: the two one-byte record positions and d.H.d of
+    # both cells
+    per_face = 8 + 4 * el + dcs * el + 4 + (2 + 2 * nv * el if ord_ >= 2 else 0)
     return nc * per_cell + nf * per_face, per_cell, per_face
 
 

@@ -100,7 +100,7 @@ void free_all(dolinc_ctx c) {
   free_mlp(c);
   DevMesh& m = c->m;
   dfree_t(m.part_ptr); dfree_t(m.ent_face); dfree_t(m.ent_pn); dfree_t(m.slot_ptr); dfree_t(m.slots);
-  dfree_t(m.ent_rec); dfree_t(m.ell_ptr);
+  dfree_t(m.ent_rec); dfree_t(m.ent_j); dfree_t(m.ell_ptr);
   dfree_t(m.gh_cell); dfree_t(m.gh_face); dfree_t(m.gh_patch); dfree_t(m.gh_ent); dfree_t(m.gh_n); dfree_t(m.gh_dist);
   dfree_t(m.bc_type); dfree_t(m.bc_val);
   dfree_t(m.face_ent); dfree_t(m.face_own); dfree_t(m.face_nei);
@@ -381,6 +381,12 @@ dolinc_status dolinc_create(const dolinc_mesh_desc* mesh, dolinc_stream stream, 
       fo[f] = P.new_of_old[X.d.owner[f]];
       fn[f] = P.new_of_old[X.d.neighbour[f]];
     }
+    // host sources of the asynchronous uploads below: they live until the
+    // stream is synchronised at the end of the set-up
+    std::vector<int32_t> gc, gp, ge, bt, ep;
+    std::vector<double> bv;
+    std::vector<int2> er;
+    std::vector<uchar2> ej;
     DevMesh& m = c->m;
     hipError_t e = hipSuccess;
 #define UP(dst, src, n)                                       \
@@ -398,7 +404,9 @@ dolinc_status dolinc_create(const dolinc_mesh_desc* mesh, dolinc_stream stream, 
     UP(m.fnodes, mesh->face_nodes, mesh->face_node_ptr[nf]);
     UP(m.shift, X.d.neigh_shift, nf * dim);
     if (c->n_ghost) {
-      std::vector<int32_t> gc(c->n_ghost), gp(c->n_ghost), ge(c->n_ghost);
+      gc.resize(c->n_ghost);
+      gp.resize(c->n_ghost);
+      ge.resize(c->n_ghost);
       for (int64_t k = 0; k < c->n_ghost; ++k) {
         gc[k] = P.new_of_old[mesh->owner[X.bface[k]]];
         gp[k] = mesh->face_patch[X.bface[k]];
@@ -414,8 +422,8 @@ dolinc_status dolinc_create(const dolinc_mesh_desc* mesh, dolinc_stream stream, 
       UP(m.gh_ent, ge.data(), ge.size());
       UP(m.gh_face, X.bface.data(), X.bface.size());
       UP(m.gh_patch, gp.data(), gp.size());
-      std::vector<int32_t> bt(c->n_patches, DOLINC_BC_ZERO_GRADIENT);
-      std::vector<double> bv((size_t)c->n_patches * 5, 0.0);
+      bt.assign(c->n_patches, DOLINC_BC_ZERO_GRADIENT);
+      bv.assign((size_t)c->n_patches * 5, 0.0);
       UP(m.bc_type, bt.data(), bt.size());
       UP(m.bc_val, bv.data(), bv.size());
       if (e == hipSuccess) e = hipMalloc((void**)&m.gh_n, (size_t)c->n_ghost * 3 * sizeof(double));
@@ -425,7 +433,7 @@ dolinc_status dolinc_create(const dolinc_mesh_desc* mesh, dolinc_stream stream, 
       // sliced-ELL offsets: ELL_BLOCK cells per block, as many records per
       // cell as the block's widest cell has faces
       const int64_t nb = (P.n_cells + ELL_BLOCK - 1) / ELL_BLOCK;
-      std::vector<int32_t> ep(nb + 1, 0);
+      ep.assign(nb + 1, 0);
       int64_t tot = 0;
       for (int64_t b = 0; b < nb; ++b) {
         int mf = 0;
@@ -439,7 +447,7 @@ dolinc_status dolinc_create(const dolinc_mesh_desc* mesh, dolinc_stream stream, 
       UP(m.ell_ptr, ep.data(), ep.size());
       // every entry names the record of its face in the owner's and in the
       // neighbour's list (a seam face's two entries name the same records)
-      std::vector<int2> er(c->n_entries, make_int2(-1, -1));
+      er.assign(c->n_entries, make_int2(-1, -1));
       for (int64_t cc = 0; cc < P.n_cells; ++cc) {
         const int64_t b = cc / ELL_BLOCK, ln = cc % ELL_BLOCK;
         const int64_t e0 = P.part_ent_ptr[cc / P.part_cells];
@@ -455,6 +463,22 @@ dolinc_status dolinc_create(const dolinc_mesh_desc* mesh, dolinc_stream stream, 
       for (int64_t k = 0; k < c->n_entries; ++k)
         if ((er[k].x < 0 || er[k].y < 0) && e == hipSuccess) e = hipErrorInvalidValue;  // reported below
       UP(m.ent_rec, er.data(), er.size());
+      // the flux kernel reads each entry's records as 2 one-byte positions
+      // (checked to give back the same records)
+      if (e == hipSuccess) {
+        ej.resize(c->n_entries);
+        bool fits = true;
+        auto pos = [&](int64_t cell, int32_t rec, unsigned char* j) {
+          const int64_t b = cell / ELL_BLOCK, ln = cell % ELL_BLOCK;
+          const int64_t q = (int64_t)rec - ep[b] - ln;
+          if (q < 0 || q % ELL_BLOCK != 0 || q / ELL_BLOCK > 255) return false;
+          *j = (unsigned char)(q / ELL_BLOCK);
+          return ep[b] + (q / ELL_BLOCK) * ELL_BLOCK + ln == rec;
+        };
+        for (int64_t k = 0; k < c->n_entries && fits; ++k)
+          fits = pos(pn[k].x, er[k].x, &ej[k].x) && pos(pn[k].y, er[k].y, &ej[k].y);
+        if (fits) UP(m.ent_j, ej.data(), ej.size());
+      }
     }
 #undef UP
     const size_t nc = (size_t)P.n_cells;

@@ -27,6 +27,7 @@ KArgs<T> base_args(dolinc_ctx_s* c) {
   a.G1 = (const T*)c->w.G1;
   a.Hf = (const T*)c->w.Hf;
   a.ent_rec = c->m.ent_rec;
+  a.ent_j = c->m.ent_j;
   a.theta = c->w.theta;
   a.gamma = (T)c->params.gamma;
   for (int k = 0; k < 3; ++k) {

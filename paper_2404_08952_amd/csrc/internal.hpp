@@ -45,6 +45,10 @@ struct DevMesh {
   int32_t* slot_ptr = nullptr;
   uint16_t* slots = nullptr;
   int2* ent_rec = nullptr;       // [entries] ELL record of the face in its owner / neighbour cell
+  // [entries] the same records as positions in the cells' record lists:
+  // record = ell_ptr[cell / ELL_BLOCK] + j * ELL_BLOCK + cell % ELL_BLOCK
+  // (null when a cell has more than 255 records)
+  uchar2* ent_j = nullptr;
   int32_t* ell_ptr = nullptr;    // [n_cells / ELL_BLOCK + 1] record offsets
   // auxiliary cells of non-coupled boundary faces (row n_interior + k)
   int32_t* gh_cell = nullptr;    // [n_ghost] internal boundary cell

@@ -46,6 +46,7 @@ struct KArgs {
   const T* G1;
   const T* Hf;          // [records][NV] second differentials contracted with the record's d
   const int2* ent_rec;  // [entries] record of the face in its owner / neighbour
+  const uchar2* ent_j;  // [entries] the same as positions in the two cells' record lists, or null
   const float* theta;
   const T* Un;
   T* out;
@@ -599,9 +600,21 @@ __device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T
     contract1<T, NV, D>(as_glb(a.G1 + N * NV * D), dc, gN);
   }
   if constexpr (ORD >= 2) {  // d.H.d of both cells, written per face record by the second-derivative kernel
-    const int2 rc = a.ent_rec[e];
-    GlbPtr<T> hp = as_glb(a.Hf + (int64_t)rc.x * NV);
-    GlbPtr<T> hn = as_glb(a.Hf + (int64_t)rc.y * NV);
+    // the records from their positions in the cells' lists (2 bytes per
+    // entry instead of 8; the block offsets are a small cached array)
+    static_assert(ELL_BLOCK == KTPB, "cell blocks of the record lists are workgroups of the cell kernels");
+    int64_t rP, rN;
+    if (a.ent_j) {
+      const uchar2 j = a.ent_j[e];
+      rP = (int64_t)a.ell_ptr[P / KTPB] + (int64_t)j.x * KTPB + P % KTPB;
+      rN = (int64_t)a.ell_ptr[N / KTPB] + (int64_t)j.y * KTPB + N % KTPB;
+    } else {
+      const int2 rc = a.ent_rec[e];
+      rP = rc.x;
+      rN = rc.y;
+    }
+    GlbPtr<T> hp = as_glb(a.Hf + rP * NV);
+    GlbPtr<T> hn = as_glb(a.Hf + rN * NV);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       hP[v] = hp[v];

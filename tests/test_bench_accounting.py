@@ -8,15 +8,16 @@ def test_flux_kernel_bytes_taylor_green_fp32():
     total, per_cell, per_face = bench.flux_kernel_bytes(nc, nf, 5, 3, 4, "USR5", blend=True)
     # per cell: U 20 + G1 60 + 1/V 4 + slot_ptr 4 + R/U out 20 + 2/3 of U^n 20 + theta 4
     assert abs(per_cell - (20 + 60 + 4 + 4 + 20 + 20 * 2 / 3 + 4)) < 1e-9
-    # per face: owner/neighbour 8 + S, omega 16 + d 12 + two slots 4 + record pair 8 + d.H.d of both cells 40
-    assert per_face == 8 + 16 + 12 + 4 + 8 + 40
-    assert abs(total - (9.013690368e9 + 4 * nf)) < 1.0
+    # per face: owner/neighbour 8 + S, omega 16 + d 12 + two slots 4 + record positions 2 + d.H.d of both
+    # cells 40
+    assert per_face == 8 + 16 + 12 + 4 + 2 + 40
+    assert abs(total - (9.013690368e9 - 2 * nf)) < 1.0
 
 
 def test_flux_kernel_bytes_fp64():
     _t, per_cell, per_face = bench.flux_kernel_bytes(1, 1, 5, 3, 8, "USR5", blend=True)
     # FP64: d (3 doubles); the coefficients are evaluated in the kernel
-    assert per_face == 8 + 32 + 3 * 8 + 4 + 8 + 80
+    assert per_face == 8 + 32 + 3 * 8 + 4 + 2 + 80
     assert abs(per_cell - (40 + 120 + 8 + 4 + 40 + 40 * 2 / 3 + 4)) < 1e-9
 
 
