@@ -852,7 +852,11 @@ def main():
             gbps = alg / (ms * 1e-3) / 1e9
             t = traffic.get(f"{prec} {name}")
             kern[name] = dict(avg_ms=ms, alg_bytes=alg, gbps=gbps, frac=gbps / HBM_PEAK_GBPS,
-                              traffic_bytes=t, traffic_over_alg=(t / alg if t else None))
+                              traffic_bytes=t, traffic_over_alg=(t / alg if t else None),
+                              # measured (counter) traffic over the live duration: the
+                              # achieved HBM rate of the kernel, as a fraction of peak
+                              traffic_gbps=(t / (ms * 1e-3) / 1e9 if t else None),
+                              traffic_frac=(t / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS if t else None))
         add("k_flux", 3, fb)
         if blend:
             add("k_grad_features", 2, grad_features_bytes(nc, nrec, nv, dim, el))
@@ -877,6 +881,7 @@ def main():
             log(f"[bench] {prec} {name}: {k['avg_ms']:.3f} ms, {k['alg_bytes'] / 1e9:.3f} GB algorithmic, "
                 f"{k['gbps']:.0f} GB/s = {k['frac']:.3f} of peak"
                 + (f", counter traffic {k['traffic_bytes'] / 1e9:.3f} GB = {k['traffic_over_alg']:.2f} x algorithmic"
+                   f" = {k['traffic_gbps']:.0f} GB/s = {k['traffic_frac']:.3f} of peak"
                    if k["traffic_bytes"] else ""))
         se = sm["stage_effective"]
         log(f"[bench] {prec} stage: {sm['ms_per_stage']:.3f} ms, compulsory {se['compulsory_bytes_per_cell']} B/cell "

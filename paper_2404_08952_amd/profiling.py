@@ -31,14 +31,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # sources that the stage kernels are compiled from
 FLUX_SOURCES = ("csrc/residual_impl.hpp", "csrc/dispatch_impl.hpp", "csrc/kernels_f32.hip",
                 "csrc/indicator_impl.hpp", "csrc/indicator.hip", "csrc/coefficients.hpp")
-FLUX_KERNEL = r"k_flux<float, 3, 3, 5, true, 2, 0>"
+FLUX_KERNEL = r"k_flux<float, 3, 3, 5, true, 2, 0(, \d+)?>"
 # the stage kernels of the headline workload (USR5 + HLLC + learned blend):
 # short name -> kernel-name pattern, FP32 (cell-reference form) and FP64
 STAGE_KERNELS = (
-    ("fp32 k_flux", re.escape("k_flux<float, 3, 3, 5, true, 2, 0>")),
+    ("fp32 k_flux", FLUX_KERNEL),
     ("fp32 k_grad_features", re.escape("k_grad_features<float, 3>")),
     ("fp32 k_hface", re.escape("k_hface_w5<float, 3, 5>")),
-    ("fp64 k_flux", re.escape("k_flux<double, 3, 3, 5, true, 0, 0>")),
+    ("fp64 k_flux", r"k_flux<double, 3, 3, 5, true, 0, 0(, \d+)?>"),
     ("fp64 k_grad_features", re.escape("k_grad_features<double, 3>")),
     ("fp64 k_hface", re.escape("k_hface<double, 3, 5>")),
     ("k_mlp_fwd", re.escape("k_mlp_fwd")),
@@ -85,7 +85,7 @@ def counter_values(pmc_dir, counter, kernel_regex, largest_grid=False):
     return [v for _g, v in sel]
 
 
-def traffic(fetch_dir, write_dir, kernel_regex=re.escape(FLUX_KERNEL), calib_regex=CALIB_KERNEL):
+def traffic(fetch_dir, write_dir, kernel_regex=FLUX_KERNEL, calib_regex=CALIB_KERNEL):
     """HBM bytes per launch of the kernel, calibrated on the streaming kernel."""
     f_k = counter_values(fetch_dir, "FETCH_SIZE", kernel_regex, largest_grid=True)
     w_k = counter_values(write_dir, "WRITE_SIZE", kernel_regex, largest_grid=True)
@@ -193,7 +193,7 @@ def main(argv):
         traffic_lines.append(f"traffic_bytes_per_launch[{short}] = {t['bytes']:.6e}")
         if ag:
             traffic_lines.append(f"algorithmic_bytes_per_launch[{short}] = {ag:.6e}")
-    t = traffic(fetch_dir, write_dir, kernel_regex=re.escape(FLUX_KERNEL))
+    t = traffic(fetch_dir, write_dir, kernel_regex=FLUX_KERNEL)
     lines.append(f"  (calibration factors: FETCH_SIZE x {t['fetch_factor']:.3f}, WRITE_SIZE x {t['write_factor']:.3f})")
     lines += traffic_lines
     lines.append(f"kernel_source_sha256 = {source_hash()}")
