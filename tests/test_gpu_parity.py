@@ -195,6 +195,25 @@ def test_fp32_stage_error(name, kw, form, geos):
     assert max(errs) <= 1e-5, errs
 
 
+@pytest.mark.parametrize("positivity", [False, True])
+def test_fp32_cell_form_on_512_cell_partitions(positivity, geos):
+    """Partitions of 512 cells run the flux kernel with 512 threads (the FP32
+    bench path), with and without the positivity rule's second pass: the
+    same stage tolerance against the oracle as on 256-cell partitions, and
+    the same residual as those to FP32 rounding of the sums."""
+    mesh, geo = MESHES["mixed3d"], geos["mixed3d"]
+    kw = dict(pde="euler", scheme="USR5", flux="hllc")
+    U = _euler_state(mesh.n_cells, np.random.default_rng(9)).astype(np.float32).astype(np.float64)
+    ref = SV.residual(mesh, geo, U, dict(oracle_params(kw), positivity=positivity))
+    R = {}
+    for pc in (256, 512):
+        s = _solver(mesh, precision="fp32", u_ref=FP32_REF, positivity=positivity, part_cells=pc, **kw)
+        R[pc] = s.to_external(s.residual(s.to_internal(U)))
+        assert max(_group_errors(R[pc], ref)) <= 1e-5, (pc, _group_errors(R[pc], ref))
+        s.close()
+    assert max(_group_errors(R[512], R[256])) <= 1e-6
+
+
 @pytest.mark.parametrize("form", ["constant", "cell"])
 @pytest.mark.parametrize("flux", ["rusanov", "hllc"])
 @pytest.mark.parametrize("scheme", ["USR3", "USR5", "CSR4", "WENO5"])
