@@ -204,10 +204,12 @@ dolinc_status dolinc_create(const dolinc_mesh_desc* mesh, dolinc_stream s, dolin
 dolinc_status dolinc_mesh_prepare(const dolinc_mesh_desc* mesh, int32_t* new_of_old,
                                   dolinc_mesh_stats* stats);
 
-/* new_of_old: host [n_cells]; internal index of each caller cell (the
- * auxiliary cell of the k-th boundary face, in caller face order, is row
- * n_cells + k). */
+/* new_of_old: host [n_cells], filled with the internal index of each caller
+ * cell (the auxiliary cell of the k-th boundary face, in caller face order,
+ * is row n_cells + k).  ESTATE for an invalid context, EINVAL for NULL. */
 dolinc_status dolinc_permutation(dolinc_ctx ctx, int32_t* new_of_old);
+/* Partition statistics of the context into host *stats.  ESTATE for an
+ * invalid context, EINVAL for NULL. */
 dolinc_status dolinc_stats(dolinc_ctx ctx, dolinc_mesh_stats* stats);
 
 /* Condition of boundary patch `patch` (dolinc_bc); values: host double
@@ -227,36 +229,61 @@ dolinc_status dolinc_set_boundary(dolinc_ctx ctx, int32_t patch, int32_t type, c
  * needed). */
 dolinc_status dolinc_precompute(dolinc_ctx ctx, const dolinc_params* params, dolinc_stream s);
 
-/* R = dU/dt = -V^-1 sum_f sigma F_f (device [n_cells][n_v] each, U != R). */
+/* The semi-discrete residual R = dU/dt = -V^-1 sum_f sigma F_f of the
+ * finite-volume form for cell averages (Sec. 2.2), with face states
+ * from the DOLINC reconstruction (Sec. 2.3-2.4, eq:USR3 / eq:CSR4 and the
+ * second-order templates), the optional blend and the Riemann flux of the
+ * params (Sec. 3).  U, R: device [n_rows][n_v], element type of the
+ * precision, internal order, owned by the caller; U != R.  The auxiliary
+ * rows of U are rewritten from the boundary conditions.  ESTATE before
+ * dolinc_precompute (or with the learned blend before dolinc_mlp_set),
+ * EINVAL for NULL or U == R, EHIP if a launch fails. */
 dolinc_status dolinc_residual(dolinc_ctx ctx, const void* U, void* R, dolinc_stream s);
 
-/* One SSP-RK3 step in place on U (device [n_cells][n_v]) with time step dt. */
+/* One step of the third-order TVD (SSP) Runge-Kutta method (Sec. 3,
+ * opening paragraph) in place on U (device [n_rows][n_v], caller-owned)
+ * with time step dt: three residual stages fused with their stage
+ * combinations, the intermediate states in the context's workspaces.
+ * ESTATE as for dolinc_residual, EINVAL for NULL U or dt not finite and
+ * > 0, EHIP if a launch fails. */
 dolinc_status dolinc_rk_step(dolinc_ctx ctx, void* U, double dt, dolinc_stream s);
 
-/* n_steps SSP-RK3 steps (same as calling dolinc_rk_step n_steps times). */
+/* n_steps SSP-RK3 steps (same as calling dolinc_rk_step n_steps times);
+ * EINVAL also for n_steps < 0. */
 dolinc_status dolinc_advance(dolinc_ctx ctx, void* U, double dt, int64_t n_steps, dolinc_stream s);
 
 /* Per-cell blend weights for DOLINC_BLEND_THETA: device float [n_cells]
- * (internal order), copied into the context on stream s. */
+ * (internal order, caller-owned), copied into the context on stream s.
+ * ESTATE unless the params' blend is THETA, EINVAL for NULL. */
 dolinc_status dolinc_set_theta(dolinc_ctx ctx, const float* theta, dolinc_stream s);
 
-/* Classical sensor weight theta per cell (device float [n_cells]) for state U. */
+/* Classical sensor weight theta per cell for state U: the smoothness ratio
+ * of the DOLINC upwind differences (Sec. 2.4, the undivided differences of
+ * ENO3) on density and energy, mapped to [0, 1].  U device [n_rows][n_v],
+ * theta device float [n_rows] (caller-owned).  ESTATE before precompute or
+ * when the scheme keeps no gradient (order 0 without blend), EINVAL for
+ * NULL. */
 dolinc_status dolinc_classical_theta(dolinc_ctx ctx, const void* U, float* theta, dolinc_stream s);
 
-/* Gauss-linear gradient (Sec. 2.3) of U: G1 device [n_cells][n_v][dim];
- * G2 (may be NULL) the symmetrised gradient of G1, [n_cells][n_v][dim*(dim+1)/2]
- * ordered xx,yy,(zz),xy,(xz,yz).  Element type as U. */
+/* Gauss-linear gradient (Sec. 2.3) of U: G1 device [n_rows][n_v][dim];
+ * G2 (may be NULL) the symmetrised gradient of G1, [n_rows][n_v][dim*(dim+1)/2]
+ * ordered xx,yy,(zz),xy,(xz,yz).  Element type as U; caller-owned.
+ * ESTATE before precompute, EINVAL for NULL U or G1. */
 dolinc_status dolinc_gradients(dolinc_ctx ctx, const void* U, void* G1, void* G2, dolinc_stream s);
 
-/* Reconstructed face states (after blend and positivity fallback) per face
- * in the caller's face order: UL, UR device [n_faces][n_v]; F (may be NULL)
- * the face-integrated numerical flux [n_faces][n_v]. */
+/* Reconstructed face states (Sec. 2.4, both sides of every face, after the
+ * blend and the positivity rules) per face in the caller's face order: UL,
+ * UR device [n_faces][n_v]; F (may be NULL) the face-integrated numerical
+ * flux [n_faces][n_v] (Sec. 3).  Caller-owned.  ESTATE as for
+ * dolinc_residual, EINVAL for NULL U, UL or UR. */
 dolinc_status dolinc_face_states(dolinc_ctx ctx, const void* U, void* UL, void* UR, void* F,
                                  dolinc_stream s);
 
-/* FP64 geometry after precompute: V, xc device double [n_cells], [n_cells][dim]
- * (internal order); S, xf [n_faces][dim], omega, g [n_faces] (caller order).
- * Any pointer may be NULL. */
+/* FP64 geometry after precompute (Sec. 2.2: volumes, centroids, face area
+ * vectors and centres, the distance weight omega and growth rate g of
+ * every face): V, xc device double [n_cells], [n_cells][dim] (internal
+ * order); S, xf [n_faces][dim], omega, g [n_faces] (caller order).  Any
+ * pointer may be NULL.  ESTATE before dolinc_precompute. */
 dolinc_status dolinc_geometry(dolinc_ctx ctx, double* V, double* xc, double* S, double* xf,
                               double* omega, double* g, dolinc_stream s);
 
