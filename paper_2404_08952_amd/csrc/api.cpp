@@ -608,7 +608,7 @@ dolinc_status dolinc_precompute(dolinc_ctx c, const dolinc_params* p, dolinc_str
     al(&c->w.sw, ne * 4 * el);
     al(&c->w.ell_sw, (size_t)c->n_ell * 4 * el);
     al(&c->w.ell_d, (size_t)c->n_ell * 3 * el);
-    al(&c->w.dc, ne * (size_t)dc_stride(p->scheme, p->precision) * el);
+    al(&c->w.dc, ne * (size_t)DC_VALUES * el);
     al(&c->w.rV, nc * el);
     if (ord >= 1 || bl) al(&c->w.G1, nc * nv * c->dim * el);
     if (ord >= 2) al(&c->w.Hf, (size_t)c->n_ell * nv * el);

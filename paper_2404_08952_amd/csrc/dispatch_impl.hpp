@@ -224,13 +224,12 @@ hipError_t run_theta(dolinc_ctx_s* c, const void* U, const void* G1, float* thet
   a.U = (const T*)U;
   a.G1 = (const T*)G1;
   const dim3 grid(8 * a.cell_per_xcd), blk(KTPB);
-  const int dcs = dc_stride(c->params.scheme, c->w.precision);
   if (c->dim == 2) {
-    hipLaunchKernelGGL((k_theta<T, 2, 1>), grid, blk, 0, s, a, dcs, theta);
+    hipLaunchKernelGGL((k_theta<T, 2, 1>), grid, blk, 0, s, a, theta);
   } else if (c->w.nv == 1) {
-    hipLaunchKernelGGL((k_theta<T, 3, 1>), grid, blk, 0, s, a, dcs, theta);
+    hipLaunchKernelGGL((k_theta<T, 3, 1>), grid, blk, 0, s, a, theta);
   } else {
-    hipLaunchKernelGGL((k_theta<T, 3, 5>), grid, blk, 0, s, a, dcs, theta);
+    hipLaunchKernelGGL((k_theta<T, 3, 5>), grid, blk, 0, s, a, theta);
   }
   return hipGetLastError();
 }

@@ -11,15 +11,14 @@ static_assert(MLP_IN == DOLINC_N_FEATURES && MLP_INP == DOLINC_FEATURE_STRIDE &&
               "network sizes of the kernels and of the C interface differ");
 
 hipError_t features_launch(dolinc_ctx_s* c, const void* U, float* X32, unsigned short* Xb, hipStream_t s) {
-  const int dcs = dc_stride(c->params.scheme, c->w.precision);
   if (c->w.precision == DOLINC_FP64) {
     KArgs<double> a = base_args<double>(c);
     a.U = (const double*)U;
-    hipLaunchKernelGGL((k_features<double, 3>), dim3(8 * a.cell_per_xcd), dim3(KTPB), 0, s, a, dcs, X32, Xb);
+    hipLaunchKernelGGL((k_features<double, 3>), dim3(8 * a.cell_per_xcd), dim3(KTPB), 0, s, a, X32, Xb);
   } else {
     KArgs<float> a = base_args<float>(c);
     a.U = (const float*)U;
-    hipLaunchKernelGGL((k_features<float, 3>), dim3(8 * a.cell_per_xcd), dim3(KTPB), 0, s, a, dcs, X32, Xb);
+    hipLaunchKernelGGL((k_features<float, 3>), dim3(8 * a.cell_per_xcd), dim3(KTPB), 0, s, a, X32, Xb);
   }
   return hipGetLastError();
 }
@@ -33,16 +32,15 @@ static MlpDev mlp_dev(dolinc_ctx_s* c) {
 }
 
 hipError_t grad_features_launch(dolinc_ctx_s* c, const void* U, void* G1, unsigned short* Xf, hipStream_t s) {
-  const int dcs = dc_stride(c->params.scheme, c->w.precision);
   if (c->w.precision == DOLINC_FP64) {
     KArgs<double> a = base_args<double>(c);
     a.U = (const double*)U;
-    hipLaunchKernelGGL((k_grad_features<double, 3>), dim3(8 * a.cell_per_xcd), dim3(KTPB), 0, s, a, dcs,
+    hipLaunchKernelGGL((k_grad_features<double, 3>), dim3(8 * a.cell_per_xcd), dim3(KTPB), 0, s, a,
                        (double*)G1, Xf);
   } else {
     KArgs<float> a = base_args<float>(c);
     a.U = (const float*)U;
-    hipLaunchKernelGGL((k_grad_features<float, 3>), dim3(8 * a.cell_per_xcd), dim3(KTPB), 0, s, a, dcs,
+    hipLaunchKernelGGL((k_grad_features<float, 3>), dim3(8 * a.cell_per_xcd), dim3(KTPB), 0, s, a,
                        (float*)G1, Xf);
   }
   return hipGetLastError();

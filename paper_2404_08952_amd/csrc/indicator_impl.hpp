@@ -32,7 +32,6 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 
 // FP32 -> bf16, round to nearest even (v_cvt_pk_bf16_f32 on gfx950)
 __device__ __forceinline__ unsigned short f2bf(float x) { return __builtin_bit_cast(unsigned short, (__bf16)x); }
-__device__ __forceinline__ float bf2f(unsigned short b) { return __uint_as_float(((unsigned)b) << 16); }
 
 __device__ __forceinline__ v4f mfma16(v4s a, v4s b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
@@ -159,7 +158,7 @@ __device__ __forceinline__ void feat_finish(const T* qc, const FeatAcc<T>& A, fl
 
 // Gc: the cell's gradient [NV][D] (from memory or registers)
 template <class T, int D>
-__device__ void cell_features_from(const KArgs<T>& a, int dcs, int64_t c, const T* Gc, float* feat,
+__device__ void cell_features_from(const KArgs<T>& a, int64_t c, const T* Gc, float* feat,
                                    const T* Ulds = nullptr, int64_t c0 = 0, int n = 0) {
   constexpr int NV = D + 2;
   const int64_t b = c / KTPB;
@@ -201,19 +200,19 @@ __device__ void cell_features_from(const KArgs<T>& a, int dcs, int64_t c, const 
 }
 
 template <class T, int D>
-__device__ __forceinline__ void cell_features(const KArgs<T>& a, int dcs, int64_t c, float* feat) {
-  cell_features_from<T, D>(a, dcs, c, a.G1 + c * (D + 2) * D, feat);
+__device__ __forceinline__ void cell_features(const KArgs<T>& a, int64_t c, float* feat) {
+  cell_features_from<T, D>(a, c, a.G1 + c * (D + 2) * D, feat);
 }
 
 template <class T, int D>
-__global__ __launch_bounds__(KTPB) void k_features(KArgs<T> a, int dcs, float* __restrict__ X32,
+__global__ __launch_bounds__(KTPB) void k_features(KArgs<T> a, float* __restrict__ X32,
                                                     unsigned short* __restrict__ Xb) {
   const int b = xcd_remap(blockIdx.x, a.cell_per_xcd, a.n_cell_blocks);
   if (b < 0) return;
   const int64_t c = (int64_t)b * KTPB + threadIdx.x;
   if (c >= a.nc) return;
   float f[MLP_IN];
-  cell_features<T, D>(a, dcs, c, f);
+  cell_features<T, D>(a, c, f);
   if (X32)
     for (int j = 0; j < MLP_IN; ++j) X32[c * MLP_IN + j] = f[j];
   if (Xb) {
@@ -594,7 +593,7 @@ __global__ void k_mlp_pack(const float* __restrict__ p, unsigned short* __restri
 // apart from them, so in FP32 a few features may round differently (FP64:
 // the same bf16 rows).
 template <class T, int D>
-__global__ __launch_bounds__(KTPB) void k_grad_features(KArgs<T> a, int dcs, T* __restrict__ G1out,
+__global__ __launch_bounds__(KTPB) void k_grad_features(KArgs<T> a, T* __restrict__ G1out,
                                                          unsigned short* __restrict__ Xf) {
   constexpr int NV = D + 2;
   static_assert(MLP_IN % 8 == 0, "feature rows are stored in 16-byte pieces");
@@ -672,7 +671,7 @@ __global__ __launch_bounds__(KTPB) void k_grad_features(KArgs<T> a, int dcs, T* 
       grad_sums<T, D, NV, 6>(a, a.U, c, acc, ul, c0, ncl);
       for (int k = 0; k < NV; ++k)
         for (int x = 0; x < D; ++x) g[k * D + x] = acc[k][x] * rv;
-      cell_features_from<T, D>(a, dcs, c, g, f, ul, c0, ncl);
+      cell_features_from<T, D>(a, c, g, f, ul, c0, ncl);
     }
     unsigned int w[MLP_IN / 2];
     for (int j = 0; j < MLP_IN / 2; ++j) w[j] = (unsigned)f2bf(f[2 * j]) | ((unsigned)f2bf(f[2 * j + 1]) << 16);

@@ -32,9 +32,8 @@ namespace dolinc {
 //   ell_d[r][3]  : sigma d_x, sigma d_y, sigma d_z (0 for padding).  A cell's
 //                  records j >= its face count (slot_ptr) are padding.
 constexpr int ELL_BLOCK = 256;
-inline bool nonlinear_scheme(int scheme) { return scheme == 6 || scheme == 7; }
-// values per face entry in dc (d)
-inline int dc_stride(int /*scheme*/, int /*precision*/) { return 3; }
+// values per face entry in dc: d
+constexpr int DC_VALUES = 3;
 inline int scheme_order(int scheme) { return scheme <= 2 ? 0 : scheme <= 4 ? 1 : 2; }
 
 struct DevMesh {

@@ -168,7 +168,7 @@ __global__ void k_face_scalars(int64_t nf, int dim, const int32_t* __restrict__ 
 }
 
 template <class T>
-__global__ void k_entry_fill(int64_t ne, int dcs, const int32_t* __restrict__ ent_face,
+__global__ void k_entry_fill(int64_t ne, const int32_t* __restrict__ ent_face,
                              const double* __restrict__ S, const double* __restrict__ omega,
                              const double* __restrict__ dvec, T* __restrict__ sw, T* __restrict__ dc) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -178,8 +178,7 @@ __global__ void k_entry_fill(int64_t ne, int dcs, const int32_t* __restrict__ en
   sw[4 * e + 1] = (T)S[3 * f + 1];
   sw[4 * e + 2] = (T)S[3 * f + 2];
   sw[4 * e + 3] = (T)omega[f];
-  T* o = dc + (int64_t)dcs * e;
-  for (int x = 0; x < dcs; ++x) o[x] = (T)0;
+  T* o = dc + (int64_t)DC_VALUES * e;
   o[0] = (T)dvec[3 * f + 0];
   o[1] = (T)dvec[3 * f + 1];
   o[2] = (T)dvec[3 * f + 2];
@@ -215,7 +214,7 @@ __global__ void k_ghost_geom(int64_t ng, int64_t n_int, const int32_t* __restric
 template <class T>
 __global__ void k_ell_fill(int64_t nc, int B, const int32_t* __restrict__ part_ptr,
                            const int32_t* __restrict__ slot_ptr, const uint16_t* __restrict__ slots,
-                           const int2* __restrict__ ent_pn, const int32_t* __restrict__ ell_ptr, int dcs,
+                           const int2* __restrict__ ent_pn, const int32_t* __restrict__ ell_ptr,
                            const T* __restrict__ sw, const T* __restrict__ dc, T* __restrict__ ell_sw,
                            T* __restrict__ ell_d) {
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -241,7 +240,7 @@ __global__ void k_ell_fill(int64_t nc, int B, const int32_t* __restrict__ part_p
       const T sg = nb ? T(-1) : T(1);
       for (int x = 0; x < 3; ++x) {
         q[x] = wgt * sw[4 * e + x];
-        dd[x] = sg * dc[(int64_t)dcs * e + x];
+        dd[x] = sg * dc[(int64_t)DC_VALUES * e + x];
       }
     } else {
       for (int x = 0; x < 4; ++x) q[x] = T(0);
@@ -282,21 +281,19 @@ hipError_t launch_geometry(dolinc_ctx_s* c, hipStream_t s) {
 
 hipError_t launch_entry_fill(dolinc_ctx_s* c, hipStream_t s) {
   DevMesh& m = c->m;
-  const int sch = c->params.scheme;
-  const int dcs = dc_stride(sch, c->w.precision);
   if (c->w.precision == DOLINC_FP64) {
-    hipLaunchKernelGGL(k_entry_fill<double>, dim3(nblk(c->n_entries)), dim3(TPB), 0, s, c->n_entries, dcs,
+    hipLaunchKernelGGL(k_entry_fill<double>, dim3(nblk(c->n_entries)), dim3(TPB), 0, s, c->n_entries,
                        m.ent_face, m.S, m.omega, m.dvec, (double*)c->w.sw, (double*)c->w.dc);
     hipLaunchKernelGGL(k_ell_fill<double>, dim3(nblk(c->n_cells)), dim3(TPB), 0, s, c->n_cells, c->part_cells,
-                       m.part_ptr, m.slot_ptr, m.slots, m.ent_pn, m.ell_ptr, dcs, (const double*)c->w.sw,
+                       m.part_ptr, m.slot_ptr, m.slots, m.ent_pn, m.ell_ptr, (const double*)c->w.sw,
                        (const double*)c->w.dc, (double*)c->w.ell_sw, (double*)c->w.ell_d);
     hipLaunchKernelGGL(k_recip<double>, dim3(nblk(c->n_cells)), dim3(TPB), 0, s, c->n_cells, m.V,
                        (double*)c->w.rV);
   } else {
-    hipLaunchKernelGGL(k_entry_fill<float>, dim3(nblk(c->n_entries)), dim3(TPB), 0, s, c->n_entries, dcs,
+    hipLaunchKernelGGL(k_entry_fill<float>, dim3(nblk(c->n_entries)), dim3(TPB), 0, s, c->n_entries,
                        m.ent_face, m.S, m.omega, m.dvec, (float*)c->w.sw, (float*)c->w.dc);
     hipLaunchKernelGGL(k_ell_fill<float>, dim3(nblk(c->n_cells)), dim3(TPB), 0, s, c->n_cells, c->part_cells,
-                       m.part_ptr, m.slot_ptr, m.slots, m.ent_pn, m.ell_ptr, dcs, (const float*)c->w.sw,
+                       m.part_ptr, m.slot_ptr, m.slots, m.ent_pn, m.ell_ptr, (const float*)c->w.sw,
                        (const float*)c->w.dc, (float*)c->w.ell_sw, (float*)c->w.ell_d);
     hipLaunchKernelGGL(k_recip<float>, dim3(nblk(c->n_cells)), dim3(TPB), 0, s, c->n_cells, m.V,
                        (float*)c->w.rV);

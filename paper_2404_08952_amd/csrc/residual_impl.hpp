@@ -546,7 +546,7 @@ __device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T
   static_assert(REF == 0 || PK >= 2, "reference-state forms are built for the Euler equations");
   static_assert(MODE == 0 || PK >= 2, "the positivity rule is built for the Euler equations");
   constexpr int ORD = SchemeInfo<SCH>::ORD;
-  constexpr int DCS = 3;  // d per face entry
+  constexpr int DCS = DC_VALUES;  // d per face entry
   const int2 pn = a.ent_pn[e];
   const int64_t P = pn.x, N = pn.y;
   const T* swp = a.sw + 4 * e;
@@ -1215,7 +1215,7 @@ __global__ __launch_bounds__(KTPB) __attribute__((amdgpu_waves_per_eu(5))) void 
 // Classical sensor: beta = |s - Delta| / (|s| + |Delta| + eps) on every face
 // in the frame where the cell is upwind; s = phi_0^(1) - Delta.
 template <class T, int D, int NV>
-__global__ __launch_bounds__(KTPB) void k_theta(KArgs<T> a, int dcs, float* __restrict__ theta) {
+__global__ __launch_bounds__(KTPB) void k_theta(KArgs<T> a, float* __restrict__ theta) {
   const int b = xcd_remap(blockIdx.x, a.cell_per_xcd, a.n_cell_blocks);
   if (b < 0) return;
   const int64_t c = (int64_t)b * KTPB + threadIdx.x;
