@@ -50,6 +50,12 @@ def make_case(workload):
 # the workgroups per CU (flux kernel 3.53 vs 2.85 ms at 288^3; 384 cells:
 # 3.92 ms).  FP64's 512-cell partitions measured 4 % slower.
 PART_CELLS = {"fp32": 512, "fp64": 256}
+# schemes timed without the blend on the headline mesh, and the paper's own
+# figures of the same kind (context: CPU times of an OpenFOAM implementation)
+SCHEME_COST_SCHEMES = ("CD2", "USR3", "CSR4", "USR5", "CSR6", "ENO3", "WENO5")
+SCHEME_COST_NOTE = ("time per step relative to CD2 on the same mesh, HLLC, no blend; the paper's CPU-time "
+                    "increases over CD2 (1-D linear advection, OpenFOAM on 2x Xeon Platinum 9242): USR3 +16 %, "
+                    "CSR4 +18 %, USR5 +29 %, CSR6 +29 %, WENO5 +44 %")
 
 
 def indicator_weights():
@@ -796,6 +802,7 @@ def main():
     res = {}
     # the non-oscillatory DOLINC schemes and CSR6 on the same mesh (FP32, no blend)
     nonlin = {}
+    scheme_costs = {}
     extras = args.workload == "tgv3d" and not args.headline_only
     for prec in ("fp32", "fp64"):
         t0 = time.time()
@@ -806,17 +813,26 @@ def main():
         res[prec] = time_path(solver, case, prec, ex, args.steps, args.warmup,
                               windows=0 if args.headline_only else 5)
         log(f"[bench] {prec}: {res[prec]['ms_per_step']:.3f} ms/step, kernels ms {res[prec]['kernel_ms']}")
-        if prec == "fp32" and extras:
-            for sch in ("WENO5", "ENO3", "CSR6"):
-                r = time_path(solver, case, "fp32", dict(fp32_extra, blend="none"), max(1, min(args.steps, 5)), 1,
+        if extras:
+            # every scheme on the same mesh without the blend: the cost of the
+            # DOLINC schemes relative to CD2, the form of the paper's own speed
+            # figures (its CPU-time increases over CD2)
+            el_ = 4 if prec == "fp32" else 8
+            for sch in SCHEME_COST_SCHEMES:
+                r = time_path(solver, case, prec, dict(ex, blend="none"), max(1, min(args.steps, 5)), 1,
                               params=dict(case.params, scheme=sch))
-                fb = flux_kernel_bytes(nc, nf, nv, dim, 4, sch)[0]
+                fb = flux_kernel_bytes(nc, nf, nv, dim, el_, sch)[0]
                 fl = r["kernel_ms"][3] / max(r["kernel_n"][3], 1)
-                nonlin[sch] = dict(ms_per_step=r["ms_per_step"],
-                                   value=nc * 3 / (r["ms_per_step"] * 1e-3),
-                                   flux_kernel_avg_ms=fl, flux_kernel_gbps=fb / (fl * 1e-3) / 1e9,
-                                   finite=r["finite"], min_rho=r["min_rho"], min_p=r["min_p"])
-                log(f"[bench] fp32 {sch}: {r['ms_per_step']:.3f} ms/step, kernels ms {r['kernel_ms']}")
+                row = dict(ms_per_step=r["ms_per_step"], value=nc * 3 / (r["ms_per_step"] * 1e-3),
+                           flux_kernel_avg_ms=fl, flux_kernel_gbps=fb / (fl * 1e-3) / 1e9,
+                           finite=r["finite"], min_rho=r["min_rho"], min_p=r["min_p"])
+                scheme_costs.setdefault(prec, {})[sch] = row
+                if prec == "fp32" and sch in ("WENO5", "ENO3", "CSR6"):
+                    nonlin[sch] = row
+                log(f"[bench] {prec} {sch} (no blend): {r['ms_per_step']:.3f} ms/step, kernels ms {r['kernel_ms']}")
+            base = scheme_costs[prec]["CD2"]["ms_per_step"]
+            for sch, row in scheme_costs[prec].items():
+                row["time_vs_cd2"] = row["ms_per_step"] / base
         solver.close()
         del solver
     tube = shock_tube_line(args) if extras else None
@@ -923,6 +939,7 @@ def main():
         "fp32_over_fp64": s32["value"] / s64["value"],
         "other_schemes_fp32": {k: dict(v, unit="cell-updates/s", scheme=k, flux="hllc", blend="none")
                                for k, v in nonlin.items()},
+        "scheme_costs": dict(scheme_costs, note=SCHEME_COST_NOTE) if scheme_costs else None,
         "bounded_fp32": tube,
         "indicator_network": mlp,
         "tgv_kinetic_energy": ke,
