@@ -523,7 +523,7 @@ def burgers_sweep_line(args):
     jitter; the same meshes unjittered; regular all-triangle and all-quad
     meshes to 256^2), u0 = 0.5 + 0.25 sin 2 pi (x + y) to t = 0.05 (before the shock),
     USR3 and CSR4 with the Godunov flux at CFL 0.5 on the cell geometry
-    (geometric_dt), FP64 and FP32: error
+    (geometric_dt), FP64 and FP32 (each face side about its own cell): error
     against the exact solution's cell averages at 64^2 .. 512^2 and the
     observed orders, and the throughput at 256^2."""
     import numpy as np
@@ -544,7 +544,9 @@ def burgers_sweep_line(args):
         case.dt, case.steps = dt, steps
         ex = fields.cell_averages(case.mesh, case.exact(case.steps * case.dt), n_pts=4)[:, 0]
         for _k, scheme, prec in [c for c in combos if c[0] == kind]:
-            s = Solver(case.mesh, **dict(case.params, scheme=scheme), precision=prec)
+            # FP32 with each face side about its own cell
+            s = Solver(case.mesh, **dict(case.params, scheme=scheme), precision=prec,
+                       **(dict(u_ref="cell") if prec == "fp32" else {}))
             U = s.to_internal(case.U0)
             torch.cuda.synchronize()
             e0 = torch.cuda.Event(enable_timing=True)

@@ -151,18 +151,18 @@ typedef struct {
   int32_t flux;                  /* dolinc_flux       */
   int32_t precision;             /* dolinc_precision  */
   int32_t blend;                 /* dolinc_blend      */
-  int32_t use_u_ref;             /* Euler: the state the face arithmetic is carried   */
-                                 /* about.  0: full states.  1: a constant reference  */
+  int32_t use_u_ref;             /* the state the face arithmetic is carried about.   */
+                                 /* 0: full states.  1 (Euler): a constant reference  */
                                  /* u_ref: reconstruct U - u_ref, flux F(U).S -       */
-                                 /* F(u_ref).S in difference form.  2: each face      */
-                                 /* side's own cell: increments over the cell value,  */
-                                 /* each cell summing F.S - F(U_c).S over its faces   */
-                                 /* (u_ref ignored; the FP32 form of choice: its      */
-                                 /* rounding enters only through F - F(U_c)).  In 1   */
-                                 /* and 2 the dropped F(.).S terms cancel over closed */
-                                 /* cells (FP64 geometry); same results as 0 to       */
-                                 /* rounding.  2 keeps two flux shares per face entry */
-                                 /* in LDS                                            */
+                                 /* F(u_ref).S in difference form.  2 (every law):    */
+                                 /* each face side's own cell: increments over the    */
+                                 /* cell value, each cell summing F.S - F(U_c).S over */
+                                 /* its faces (u_ref ignored; the FP32 form of        */
+                                 /* choice: its rounding enters only through          */
+                                 /* F - F(U_c)).  In 1 and 2 the dropped F(.).S terms */
+                                 /* cancel over closed cells (FP64 geometry); same    */
+                                 /* results as 0 to rounding.  2 keeps two flux       */
+                                 /* shares per face entry in LDS                      */
   double gamma;                  /* Euler ratio of specific heats                     */
   double adv_vel[3];             /* advection velocity                                */
   double burgers_dir[3];         /* Burgers flux u^2/2 * burgers_dir                   */

@@ -135,11 +135,11 @@ dolinc_status check_params(const dolinc_params* p, int dim) {
     if (p->pde != DOLINC_EULER) return fail(DOLINC_EUNSUPPORTED, "the positivity rule is built for the Euler equations");
     if (p->use_u_ref == 1) return fail(DOLINC_EUNSUPPORTED, "the positivity rule takes use_u_ref 0 or 2");
   }
-  if (p->use_u_ref) {
-    if (p->pde != DOLINC_EULER) return fail(DOLINC_EUNSUPPORTED, "reference-state forms are built for the Euler equations");
-    if (p->use_u_ref == 1)
-      for (int k = 0; k < 5; ++k)
-        if (!std::isfinite(p->u_ref[k])) return fail(DOLINC_EINVAL, "non-finite u_ref");
+  if (p->use_u_ref == 1) {
+    if (p->pde != DOLINC_EULER)
+      return fail(DOLINC_EUNSUPPORTED, "the constant reference state is built for the Euler equations");
+    for (int k = 0; k < 5; ++k)
+      if (!std::isfinite(p->u_ref[k])) return fail(DOLINC_EINVAL, "non-finite u_ref");
   }
   return DOLINC_OK;
 }
@@ -591,7 +591,7 @@ dolinc_status dolinc_precompute(dolinc_ctx c, const dolinc_params* p, dolinc_str
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || lim <= 0)
       lim = 64 * 1024;
-    const size_t per = (p->pde == DOLINC_EULER && p->use_u_ref == 2) ? 2 : 1;  // shares per entry
+    const size_t per = p->use_u_ref == 2 ? 2 : 1;  // shares per entry
     if ((size_t)c->max_entries * nv * el * per > (size_t)lim)
       return fail(DOLINC_EUNSUPPORTED, "partition face fluxes exceed the LDS of one workgroup (" +
                                            std::to_string(lim / 1024) + " KiB); use a smaller part_cells");

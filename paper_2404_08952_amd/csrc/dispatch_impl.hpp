@@ -128,7 +128,7 @@ hipError_t euler_by_ref(int ref, const KArgs<T>& a, int sch, size_t lds, hipStre
 // LDS of the flux kernel: one flux per face entry, two (the owner's and the
 // neighbour's share) in the cell-reference form
 inline size_t flux_lds_bytes(const dolinc_ctx_s* c, int nv, size_t el) {
-  const int per = (c->params.pde == DOLINC_EULER && c->params.use_u_ref == 2) ? 2 : 1;
+  const int per = c->params.use_u_ref == 2 ? 2 : 1;
   return (size_t)c->max_entries * nv * el * per;
 }
 
@@ -139,14 +139,20 @@ hipError_t run_flux(dolinc_ctx_s* c, const KArgs<T>& a, hipStream_t s, bool ex) 
   const size_t lds = flux_lds_bytes(c, nv, sizeof(T));
   const bool bl = c->params.blend != DOLINC_BLEND_NONE;
   const int sch = c->params.scheme;
+  const int ref = c->params.use_u_ref;
+  // scalar laws: full states or each face side about its own cell
+  const bool cell = ref == 2;
   if (c->dim == 2) {
-    if (pk == 0) return flux_by_scheme<T, 2, 0, false, 0>(sch, a, lds, s, ex);
-    if (pk == 1) return flux_by_scheme<T, 2, 1, false, 0>(sch, a, lds, s, ex);
+    if (pk == 0) return cell ? flux_by_scheme<T, 2, 0, false, 2>(sch, a, lds, s, ex)
+                             : flux_by_scheme<T, 2, 0, false, 0>(sch, a, lds, s, ex);
+    if (pk == 1) return cell ? flux_by_scheme<T, 2, 1, false, 2>(sch, a, lds, s, ex)
+                             : flux_by_scheme<T, 2, 1, false, 0>(sch, a, lds, s, ex);
     return hipErrorInvalidValue;
   }
-  if (pk == 0) return flux_by_scheme<T, 3, 0, false, 0>(sch, a, lds, s, ex);
-  if (pk == 1) return flux_by_scheme<T, 3, 1, false, 0>(sch, a, lds, s, ex);
-  const int ref = c->params.use_u_ref;
+  if (pk == 0) return cell ? flux_by_scheme<T, 3, 0, false, 2>(sch, a, lds, s, ex)
+                           : flux_by_scheme<T, 3, 0, false, 0>(sch, a, lds, s, ex);
+  if (pk == 1) return cell ? flux_by_scheme<T, 3, 1, false, 2>(sch, a, lds, s, ex)
+                           : flux_by_scheme<T, 3, 1, false, 0>(sch, a, lds, s, ex);
   if (pk == 2) return bl ? euler_by_ref<T, 2, true>(ref, a, sch, lds, s, ex) : euler_by_ref<T, 2, false>(ref, a, sch, lds, s, ex);
   return bl ? euler_by_ref<T, 3, true>(ref, a, sch, lds, s, ex) : euler_by_ref<T, 3, false>(ref, a, sch, lds, s, ex);
 }

@@ -543,7 +543,7 @@ __device__ __forceinline__ T nonlin_side(const NonlinCoef<T>& c, T a0, T a1, T D
 template <class T, int D, int PK, int SCH, bool BLEND, int REF = 0, int MODE = 0>
 __device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T* UR, T* F, T* F2 = nullptr) {
   constexpr int NV = NVars<PK, D>::value;
-  static_assert(REF == 0 || PK >= 2, "reference-state forms are built for the Euler equations");
+  static_assert(REF != 1 || PK >= 2, "the constant reference state is built for the Euler equations");
   static_assert(MODE == 0 || PK >= 2, "the positivity rule is built for the Euler equations");
   constexpr int ORD = SchemeInfo<SCH>::ORD;
   constexpr int DCS = DC_VALUES;  // d per face entry
@@ -685,21 +685,53 @@ __device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T
     T an = T(0);
 #pragma unroll
     for (int x = 0; x < D; ++x) an += a.adv[x] * S[x];
+    // REF 2: the states are increments over U_P, so this is the owner's
+    // share an (U_up - U_P); the neighbour's subtracts an (U_N - U_P)
     F[0] = an >= T(0) ? an * UL[0] : an * UR[0];
+    if constexpr (REF == 2) {
+      F2[0] = F[0] - an * uN[0];
+      UL[0] += base[0];
+      UR[0] += base[0];
+    }
   } else if constexpr (PK == 1) {
     T s = T(0);
 #pragma unroll
     for (int x = 0; x < D; ++x) s += a.bdir[x] * S[x];
-    const T uL = UL[0], uR = UR[0];
-    const T fL = T(0.5) * uL * uL * s, fR = T(0.5) * uR * uR * s;
-    const T lo = fmin(uL, uR), hi = fmax(uL, uR);
-    const bool has0 = lo <= T(0) && hi >= T(0);
-    T fmn = fmin(fL, fR), fmx = fmax(fL, fR);
-    if (has0) {
-      fmn = fmin(fmn, T(0));
-      fmx = fmax(fmx, T(0));
+    if constexpr (REF == 2) {
+      // Godunov's choice among f(u_L), f(u_R) and f(0) (when u = 0 lies
+      // between them), f(u) = u^2/2 s, taken among the same values less
+      // f(U_P), each formed from its increment: f(U_P + i) - f(U_P) =
+      // i (i + 2 U_P) s / 2.  The neighbour's share subtracts
+      // f(U_N) - f(U_P) in the same form.
+      const T b = base[0];
+      const T iL = UL[0], iR = UR[0];
+      const T uL = iL + b, uR = iR + b;
+      const T dL = T(0.5) * iL * (iL + T(2) * b) * s, dR = T(0.5) * iR * (iR + T(2) * b) * s;
+      const T lo = fmin(uL, uR), hi = fmax(uL, uR);
+      const bool has0 = lo <= T(0) && hi >= T(0);
+      T dmn = fmin(dL, dR), dmx = fmax(dL, dR);
+      if (has0) {
+        const T d0 = T(-0.5) * b * b * s;
+        dmn = fmin(dmn, d0);
+        dmx = fmax(dmx, d0);
+      }
+      F[0] = iL <= iR ? dmn : dmx;
+      const T iN = uN[0];
+      F2[0] = F[0] - T(0.5) * iN * (iN + T(2) * b) * s;
+      UL[0] = uL;
+      UR[0] = uR;
+    } else {
+      const T uL = UL[0], uR = UR[0];
+      const T fL = T(0.5) * uL * uL * s, fR = T(0.5) * uR * uR * s;
+      const T lo = fmin(uL, uR), hi = fmax(uL, uR);
+      const bool has0 = lo <= T(0) && hi >= T(0);
+      T fmn = fmin(fL, fR), fmx = fmax(fL, fR);
+      if (has0) {
+        fmn = fmin(fmn, T(0));
+        fmx = fmax(fmx, T(0));
+      }
+      F[0] = uL <= uR ? fmn : fmx;
     }
-    F[0] = uL <= uR ? fmn : fmx;
   } else if constexpr (REF == 0) {
     // positivity: a side with rho <= 0 or p <= 0 falls back to its cell value
     if constexpr (MODE != 2) {
@@ -941,11 +973,17 @@ __global__ __launch_bounds__(KTPB) void k_face_export(KArgs<T> a) {
     // the full face flux F.S: add back the reference state's physical flux
     // (rounded in the working precision; export only)
     const T* st = REF == 1 ? a.uref : a.U + (int64_t)a.ent_pn[a.face_ent[f]].x * NV;
-    T r, vv[D], E, p, Fr[NV];
-    euler_prim<T, D>(st, a.gamma, r, vv, E, p);
     const T* sw = a.sw + 4 * (int64_t)a.face_ent[f];
-    euler_phys<T, D>(st, r, vv, E, p, sw, Fr);
-    for (int v = 0; v < NV; ++v) F[v] += Fr[v];
+    if constexpr (PK >= 2) {
+      T r, vv[D], E, p, Fr[NV];
+      euler_prim<T, D>(st, a.gamma, r, vv, E, p);
+      euler_phys<T, D>(st, r, vv, E, p, sw, Fr);
+      for (int v = 0; v < NV; ++v) F[v] += Fr[v];
+    } else {
+      T vs = T(0);
+      for (int x = 0; x < D; ++x) vs += (PK == 0 ? a.adv[x] : a.bdir[x]) * sw[x];
+      F[0] += PK == 0 ? vs * st[0] : T(0.5) * st[0] * st[0] * vs;
+    }
   }
   for (int v = 0; v < NV; ++v) {
     a.eUL[f * NV + v] = UL[v];

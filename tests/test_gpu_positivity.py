@@ -180,3 +180,8 @@ def test_cell_positivity_refused_where_not_built():
     with pytest.raises(B.DolincError) as e:
         _solver(bm, pde="euler", scheme="USR3", flux="rusanov", positivity=True)
     assert e.value.status == B.EUNSUPPORTED
+    # the constant reference state is Euler-only (the cell form is not)
+    with pytest.raises(B.DolincError) as e:
+        _solver(MESHES["tri2d"], pde="advection", scheme="USR3", u_ref=(1, 0, 0, 0, 0))
+    assert e.value.status == B.EUNSUPPORTED
+    _solver(MESHES["tri2d"], pde="advection", scheme="USR3", u_ref="cell").close()
