@@ -519,9 +519,9 @@ __device__ __forceinline__ T nonlin_side(const NonlinCoef<T>& c, T a0, T a1, T D
 // face-integrated flux F.S (owner -> neighbour).  Cell rows are gathered
 // straight from HBM/L2: staging the partition's own rows in LDS cost more in
 // occupancy and barriers than it saved.
-// REF (Euler only) picks the state the face arithmetic is carried about:
+// REF picks the state the face arithmetic is carried about:
 //   0  none: full states;
-//   1  a constant reference state a.uref: perturbations U - U_ref, flux
+//   1  (Euler) a constant reference state a.uref: perturbations U - U_ref, flux
 //      F(U).S - F(U_ref).S (the dropped terms cancel over closed cells);
 //   2  each face side's own cell: the states are carried as increments over
 //      the owner's value U_P, the flux as G_P = F.S - F(U_P).S, and the
@@ -530,7 +530,8 @@ __device__ __forceinline__ T nonlin_side(const NonlinCoef<T>& c, T a0, T a1, T D
 //      F(U_c).sum(sigma S) vanishes with the FP64 geometry.  The rounded
 //      quantities are then O(h) increments instead of O(1) fluxes: in FP32
 //      the rounding of S and of the flux arithmetic enters only through
-//      F - F(U_c).
+//      F - F(U_c).  Every law: Euler through the perturbation fluxes,
+//      advection and Burgers in closed increment forms below.
 // The reconstruction, blend and nonlinear schemes are affine in the cell
 // values (coefficients summing to one, differences elsewhere), so they run
 // unchanged on the shifted values.  F receives the owner's share (REF 2:

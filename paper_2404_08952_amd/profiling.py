@@ -14,8 +14,9 @@ wrote, and prints (or writes) a short text summary:
   ``y = -x`` over 2 GiB of float32), so the factors absorb whatever the
   counters do not see; beside it the algorithmic bytes given on the command
   line (``bench.py`` prints them);
-* the SHA-256 of the kernel sources the numbers belong to.  ``bench.py``
-  reports the traffic only while the sources still hash to that value.
+* the SHA-256 of the kernel sources the numbers belong to (their code with
+  comments stripped).  ``bench.py`` reports the traffic only while the
+  sources still hash to that value.
 """
 from __future__ import annotations
 
@@ -47,11 +48,25 @@ CALIB_KERNEL = r"neg_kernel"
 CALIB_BYTES = 2 * 4 * (1 << 29)  # read + write of 2 GiB each
 
 
-def source_hash(files=FLUX_SOURCES) -> str:
+def _code_only(text: str) -> str:
+    """The source without comments and with whitespace collapsed: edits to
+    comments leave the compiled kernels, and so the hash, unchanged."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
+def source_hash(files=FLUX_SOURCES, read=None) -> str:
+    """SHA-256 over the code (comments stripped) of the kernel sources;
+    read(path) -> text may supply another version of each file."""
     h = hashlib.sha256()
     for f in files:
-        with open(os.path.join(HERE, f), "rb") as fh:
-            h.update(fh.read())
+        if read is None:
+            with open(os.path.join(HERE, f)) as fh:
+                text = fh.read()
+        else:
+            text = read(f)
+        h.update(_code_only(text).encode())
     return h.hexdigest()
 
 
