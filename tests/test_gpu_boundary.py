@@ -70,11 +70,15 @@ def _state(mesh, kw, rng):
 def test_residual_parity(name, kw, bcs, meshes):
     mesh, X = meshes[name]
     U = _state(mesh, kw, np.random.default_rng(21))
-    s = _solver(mesh, bcs, **kw)
-    R = s.to_external(s.residual(s.to_internal(U)))
     ref = OB.residual(X, U, oracle_params(kw), bcs)
-    for v in range(ref.shape[1]):
-        _close(R[:, v], ref[:, v])
+    # full states, and each face side about its own cell (the auxiliary
+    # cells are ordinary rows to it)
+    for extra in ({}, dict(u_ref=FP32_REF)):
+        s = _solver(mesh, bcs, **kw, **extra)
+        R = s.to_external(s.residual(s.to_internal(U)))
+        for v in range(ref.shape[1]):
+            _close(R[:, v], ref[:, v])
+        s.close()
 
 
 @pytest.mark.parametrize("name,kw,bcs", [CASES[0], CASES[2], CASES[5]], ids=[IDS[0], IDS[2], IDS[5]])
@@ -94,8 +98,7 @@ def test_rk_step_parity(name, kw, bcs, meshes):
 def test_fp32_stage_error(name, kw, bcs, meshes):
     mesh, X = meshes[name]
     U = _state(mesh, kw, np.random.default_rng(23)).astype(np.float32).astype(np.float64)
-    extra = dict(u_ref=FP32_REF) if kw["pde"] == "euler" else {}
-    s = _solver(mesh, bcs, precision="fp32", **kw, **extra)
+    s = _solver(mesh, bcs, precision="fp32", **kw, u_ref=FP32_REF)
     R32 = s.to_external(s.residual(s.to_internal(U)))
     ref = OB.residual(X, U, oracle_params(kw), bcs)
     errs = _group_errors(R32, ref)
