@@ -10,6 +10,7 @@ same mesh is reported beside it.  One JSON line goes to stdout.
 from __future__ import annotations
 
 import argparse
+import atexit
 import json
 import os
 import subprocess
@@ -712,7 +713,10 @@ def start_cpu_baseline(budget_s, workload, lattice):
                NUMEXPR_NUM_THREADS="1")
     cmd = [sys.executable, os.path.abspath(__file__), "--cpu-baseline-only", "--cpu-budget", str(budget_s),
            "--workload", workload, "--cpu-lattice", str(lattice)]
-    return subprocess.Popen(cmd, env=env, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
+    proc = subprocess.Popen(cmd, env=env, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
+    # if a GPU leg fails, the child does not outlive the benchmark
+    atexit.register(lambda: proc.poll() is None and proc.kill())
+    return proc
 
 
 def finish_cpu_baseline(proc, timeout_s=900):
