@@ -380,9 +380,11 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(MlpDev m, const unsigned short*
 __global__ __launch_bounds__(256) void k_mlp_grad(MlpDev m, const unsigned short* __restrict__ X,
                                                   const float* __restrict__ y, int64_t n, int rows_per_block,
                                                   float* __restrict__ part, float* __restrict__ loss_part) {
-  __shared__ unsigned short sd2[4][16 * MLP_H];   // delta2 [row][u2], bf16
-  __shared__ unsigned short sh1[4][16 * MLP_H];   // H1 [row][u1], bf16
-  __shared__ unsigned short sd1[4][16 * MLP_H];   // delta1 [row][u1], bf16
+  // per wave, unit-major (unit * 16 + row) so that an operand's four rows
+  // 4g..4g+3 of one unit are one 8-byte read
+  __shared__ __align__(16) unsigned short sd2[4][16 * MLP_H];   // delta2 [u2][row], bf16
+  __shared__ __align__(16) unsigned short sh1[4][16 * MLP_H];   // H1 [u1][row], bf16
+  __shared__ __align__(16) unsigned short sd1[4][16 * MLP_H];   // delta1 [u1][row], bf16
   __shared__ float red[MLP_NPARAM + 1];
   MlpRegs32 R;
   load_weights32(m, R);
@@ -432,8 +434,8 @@ __global__ __launch_bounds__(256) void k_mlp_grad(MlpDev m, const unsigned short
         db2[4 * t + i] += d2;
         const unsigned short bb = f2bf(d2);
         d2b[t][i] = (short)bb;
-        sd2[w][r * MLP_H + u] = bb;
-        sh1[w][r * MLP_H + u] = f2bf(H1[t][i]);
+        sd2[w][u * 16 + r] = bb;
+        sh1[w][u * 16 + r] = f2bf(H1[t][i]);
       }
     }
     // delta1 = (W2^T delta2) (1 - H1^2)
@@ -445,32 +447,31 @@ __global__ __launch_bounds__(256) void k_mlp_grad(MlpDev m, const unsigned short
         const float h1 = H1[t][i];
         const float d1 = acc[i] * (1.f - h1 * h1);
         db1[4 * t + i] += d1;
-        sd1[w][r * MLP_H + u] = f2bf(d1);
+        sd1[w][u * 16 + r] = f2bf(d1);
       }
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // dW2[u2][u1] += sum_rows delta2[row][u2] H1[row][u1]
-    for (int t = 0; t < 4; ++t) {
-      v4s A;
-      for (int i = 0; i < 4; ++i) A[i] = (short)sd2[w][(4 * g + i) * MLP_H + 16 * t + r];
-      for (int t2 = 0; t2 < 4; ++t2) {
-        v4s Bv;
-        for (int i = 0; i < 4; ++i) Bv[i] = (short)sh1[w][(4 * g + i) * MLP_H + 16 * t2 + r];
-        dW2[t][t2] = mfma16(A, Bv, dW2[t][t2]);
+    // B operands of the two weight-gradient products, which depend on the
+    // column tile only: loaded once per row tile
+    v4s Bh[4], Bx[2];
+    for (int t2 = 0; t2 < 4; ++t2)
+      Bh[t2] = *reinterpret_cast<const v4s*>(&sh1[w][(16 * t2 + r) * 16 + 4 * g]);
+    for (int t2 = 0; t2 < 2; ++t2)
+      for (int i = 0; i < 4; ++i) {
+        const int rr = 4 * g + i;
+        Bx[t2][i] = rr < nrow ? (short)X[(row0 + rr) * MLP_INP + 16 * t2 + r] : (short)0;
       }
+    for (int t = 0; t < 4; ++t) {
+      // dW2[u2][u1] += sum_rows delta2[row][u2] H1[row][u1]
+      v4s A;
+      A = *reinterpret_cast<const v4s*>(&sd2[w][(16 * t + r) * 16 + 4 * g]);
+      for (int t2 = 0; t2 < 4; ++t2) dW2[t][t2] = mfma16(A, Bh[t2], dW2[t][t2]);
       // dW1[u1][k] += sum_rows delta1[row][u1] X[row][k]
       v4s A1;
-      for (int i = 0; i < 4; ++i) A1[i] = (short)sd1[w][(4 * g + i) * MLP_H + 16 * t + r];
-      for (int t2 = 0; t2 < 2; ++t2) {
-        v4s Bv;
-        for (int i = 0; i < 4; ++i) {
-          const int rr = 4 * g + i;
-          Bv[i] = rr < nrow ? (short)X[(row0 + rr) * MLP_INP + 16 * t2 + r] : (short)0;
-        }
-        dW1[t][t2] = mfma16(A1, Bv, dW1[t][t2]);
-      }
+      A1 = *reinterpret_cast<const v4s*>(&sd1[w][(16 * t + r) * 16 + 4 * g]);
+      for (int t2 = 0; t2 < 2; ++t2) dW1[t][t2] = mfma16(A1, Bx[t2], dW1[t][t2]);
     }
     __builtin_amdgcn_wave_barrier();
   }
