@@ -393,12 +393,18 @@ __global__ __launch_bounds__(256) void k_mlp_grad(MlpDev m, const unsigned short
   const int w = threadIdx.x >> 6;
   const int r = l & 15, g = l >> 4;
   // W2^T in A layout for delta1 = W2^T delta2: A[m=u1][k=u2] = W2[u2][u1]
-  v4s w2t[4][4];
+  // (K = 32 instruction: slot 8g + i of K block b is u2 = 32b + 4g + i and
+  // slot 8g + 4 + i is u2 = 32b + 16 + 4g + i, the order in which each lane
+  // holds delta2 in its two accumulator tiles 2b, 2b + 1)
+  v8s w2t[4][2];
   for (int t = 0; t < 4; ++t)
-    for (int kk = 0; kk < 4; ++kk) {
-      v4s v;
-      for (int i = 0; i < 4; ++i) v[i] = (short)m.w2b[(16 * kk + 4 * g + i) * MLP_H + 16 * t + r];
-      w2t[t][kk] = v;
+    for (int b = 0; b < 2; ++b) {
+      v8s v;
+      for (int i = 0; i < 4; ++i) {
+        v[i] = (short)m.w2b[(32 * b + 4 * g + i) * MLP_H + 16 * t + r];
+        v[4 + i] = (short)m.w2b[(32 * b + 16 + 4 * g + i) * MLP_H + 16 * t + r];
+      }
+      w2t[t][b] = v;
     }
   v4f dW2[4][4], dW1[4][2];
   for (int a = 0; a < 4; ++a) {
@@ -438,10 +444,16 @@ __global__ __launch_bounds__(256) void k_mlp_grad(MlpDev m, const unsigned short
         sh1[w][u * 16 + r] = f2bf(H1[t][i]);
       }
     }
-    // delta1 = (W2^T delta2) (1 - H1^2)
+    // delta1 = (W2^T delta2) (1 - H1^2), two K = 32 blocks
+    v8s d2k[2];
+    for (int b = 0; b < 2; ++b)
+      for (int i = 0; i < 4; ++i) {
+        d2k[b][i] = d2b[2 * b][i];
+        d2k[b][4 + i] = d2b[2 * b + 1][i];
+      }
     for (int t = 0; t < 4; ++t) {
       v4f acc = v4f{0, 0, 0, 0};
-      for (int kk = 0; kk < 4; ++kk) acc = mfma16(w2t[t][kk], d2b[kk], acc);
+      for (int b = 0; b < 2; ++b) acc = mfma32(w2t[t][b], d2k[b], acc);
       for (int i = 0; i < 4; ++i) {
         const int u = 16 * t + 4 * g + i;
         const float h1 = H1[t][i];
