@@ -45,11 +45,11 @@ def make_case(workload):
     raise SystemExit(f"unknown workload {workload}")
 
 
-# Cells per partition of the flux kernel: 256 in both precisions.  The FP32
-# path keeps two flux shares per face entry in LDS (each side about its own
-# cell): on 512-cell partitions that is about 76 KB per workgroup and halves
-# the workgroups per CU (flux kernel 3.53 vs 2.85 ms at 288^3; 384 cells:
-# 3.92 ms).  FP64's 512-cell partitions measured 4 % slower.
+# Cells per partition of the flux kernel.  FP32 keeps two flux shares per
+# face entry in LDS (each side about its own cell) and runs 512-cell
+# partitions with 512-thread workgroups, two per CU (flux kernel at 288^3,
+# same box: 2.82 ms, against 2.87 ms on 256-cell and 3.27 ms on 1024-cell
+# partitions).  FP64's 512-cell partitions measured 4 % slower than 256.
 PART_CELLS = {"fp32": 512, "fp64": 256}
 # schemes timed without the blend on the headline mesh, and the paper's own
 # figures of the same kind (context: CPU times of an OpenFOAM implementation)
@@ -927,8 +927,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "cells": nc, "faces": nf, "stages_per_step": 3,
                    "precision": ("FP32 bulk, each face side carried about its own cell (flux shares "
-                                 "F.S - F(U_c).S); geometry and growth rates precomputed in FP64, the DOLINC "
-                                 "coefficients evaluated from them in FP64 in the flux kernel"),
+                                 "F.S - F(U_c).S); geometry and face weights precomputed in FP64 and stored in FP32, "
+                                 "the DOLINC coefficients evaluated from the weights in FP32 in the flux kernel"),
                    "partition_cells": PART_CELLS["fp32"]},
         "roofline": {"bound": "hbm", "achieved": fk["gbps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": fk["gbps"] / HBM_PEAK_GBPS, "traffic": traffic.get("fp32 k_flux"),

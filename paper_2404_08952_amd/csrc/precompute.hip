@@ -9,9 +9,9 @@
 //           gives exact volume and centroid of the fan-bounded polyhedron.
 // Face scalars (Sec. 2.2): d = x_N - x_P, omega = |x_N - x_f| /
 // (|x_P - x_f| + |x_N - x_f|), growth rate g = omega / (1 - omega).
-// Per face entry: S and omega, d, and either the coefficients of the DOLINC
-// representation (FP64 working type) or g, from which the FP32 flux kernel
-// evaluates them in FP64 (coefficients.hpp).
+// Per face entry: S and omega, and d; the flux kernels evaluate the
+// coefficients of the DOLINC representation from omega in the working
+// precision (coefficients.hpp).
 #include <hip/hip_runtime.h>
 
 #include "internal.hpp"

@@ -639,15 +639,9 @@ __device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T
       UR[v] = nonlin_side<T, SCH>(cf, uN[v], uP[v], T(-2) * gN[v], T(-2) * gP[v], T(4) * hN[v]);
   } else {
     // coefficients of both sides from the growth rate g = omega / (1 - omega)
-    // of the P -> N frame, in FP64 (the operations that define them; in FP64
-    // the same bits as a stored copy would hold), rounded once to T
-    T c[8];
-    {
-      double cd[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-      face_coefficients(SCH, (double)om / (1.0 - (double)om), cd);
-#pragma unroll
-      for (int k = 0; k < 8; ++k) c[k] = (T)cd[k];
-    }
+    // of the P -> N frame, in the working precision (one reciprocal per side)
+    T c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    face_coefficients_r<T>(SCH, om, c);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       if constexpr (SCH <= 2) {
