@@ -88,8 +88,10 @@ typedef enum { DOLINC_FLUX_UPWIND = 0, DOLINC_FLUX_RUSANOV = 1, DOLINC_FLUX_HLLC
 
 /* FP64: all arithmetic in double.  FP32_MIXED: geometry computed in double
  * and stored rounded to float; the inversion / reconstruction coefficients
- * evaluated in float from each face's stored weight omega in the flux kernel
- * (relative error below 1e-6); gradient, reconstruction, flux and update in
+ * evaluated from each face's stored weight omega in the flux kernel, in
+ * float where omega lies in [0.15, 0.85] (relative error below 1e-6), in
+ * double on more strongly graded faces; gradient, reconstruction, flux and
+ * update in
  * float with compensated (Neumaier) face-to-cell sums.  ENO3 / WENO5 form
  * their growth rates from omega in double. */
 typedef enum { DOLINC_FP64 = 0, DOLINC_FP32_MIXED = 1 } dolinc_precision;

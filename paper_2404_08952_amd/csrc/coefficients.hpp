@@ -11,8 +11,9 @@
 // The flux kernels evaluate them per face from g = omega / (1 - omega)
 // (omega and d are all a face entry stores), which trades 8 stored values
 // per entry for a few dozen operations in the working precision (in FP32
-// the relative error stays below 1e-6 for omega in [0.15, 0.85]; an FP64
-// evaluation there cost 24 % of the FP32 flux kernel's vector instructions).
+// the relative error stays below 1e-6 for omega in [0.15, 0.85], where the
+// FP32 kernels use it; an FP64 evaluation there cost 24 % of the FP32 flux
+// kernel's vector instructions).
 #pragma once
 #include <hip/hip_runtime.h>
 

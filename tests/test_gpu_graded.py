@@ -57,3 +57,25 @@ def test_gpu_error_trends_and_fp32(cases):
             assert e[-1] > 10 * e[0], (comp, sch, e)
         for r in GS.GROWTHS:
             assert err[(r, "CSR4")] < 0.7 * err[(r, "USR3")] and err[(r, "USR5")] < err[(r, "CSR4")], (comp, r)
+
+
+@pytest.mark.parametrize("scheme", ["USR3", "CSR4", "USR5", "CSR6"])
+def test_fp32_coefficients_on_extreme_grading(scheme):
+    """Faces between cells 2e4 times apart in width (omega ~ 5e-5 and
+    1 - 5e-5): the FP32 path evaluates the closed forms of these faces in
+    FP64, because in FP32 the degree-10 terms of USR5 and CSR6 (g^10 with
+    g = 2e4) overflow.  A constant field has zero differentials, so every
+    face state must be the constant itself (an infinite coefficient would
+    give 0 x inf = NaN), in both precisions."""
+    from synth import configs
+    m = configs.line_1d(16, widths=[1.0, 2.0e4] * 8)
+    U = np.full(m.n_cells, 0.75)
+    for prec in ("fp32", "fp64"):
+        from paper_2404_08952_amd import Solver
+        s = Solver(m, pde="advection", scheme=scheme, precision=prec, adv_vel=(1.0, 0.0, 0.0))
+        UL, UR, F = s.face_states(s.to_internal(U[:, None]))
+        UL, UR, F = (x.cpu().numpy().astype(np.float64) for x in (UL, UR, F))
+        s.close()
+        assert np.isfinite(F).all(), (prec, scheme)
+        np.testing.assert_array_equal(UL[:, 0], 0.75)
+        np.testing.assert_array_equal(UR[:, 0], 0.75)
