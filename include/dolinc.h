@@ -91,9 +91,8 @@ typedef enum { DOLINC_FLUX_UPWIND = 0, DOLINC_FLUX_RUSANOV = 1, DOLINC_FLUX_HLLC
  * evaluated from each face's stored weight omega in the flux kernel, in
  * float where omega lies in [0.15, 0.85] (relative error below 1e-6), in
  * double on more strongly graded faces; gradient, reconstruction, flux and
- * update in
- * float with compensated (Neumaier) face-to-cell sums.  ENO3 / WENO5 form
- * their growth rates from omega in double. */
+ * update in float with compensated (Neumaier) face-to-cell sums.  ENO3 /
+ * WENO5 form their growth rates from omega in double. */
 typedef enum { DOLINC_FP64 = 0, DOLINC_FP32_MIXED = 1 } dolinc_precision;
 
 /* Blend of the high-order face state with a Van Leer limited second-order
