@@ -182,8 +182,8 @@ __global__ void k_entry_fill(int64_t ne, const int32_t* __restrict__ ent_face,
   o[0] = (T)dvec[3 * f + 0];
   o[1] = (T)dvec[3 * f + 1];
   o[2] = (T)dvec[3 * f + 2];
-  // the kernels evaluate the coefficients in FP64 from the growth rate
-  // omega / (1 - omega) of the entry's omega
+  // the flux kernels evaluate the coefficients from the growth rate
+  // omega / (1 - omega) of the entry's omega (coefficients.hpp)
 }
 
 // Auxiliary cells of boundary faces: the mirror image of the boundary cell
