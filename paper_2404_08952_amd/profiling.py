@@ -2,7 +2,9 @@
 
 ``python -m paper_2404_08952_amd.profiling <stats_dir> <fetch_dir> <write_dir> <out.md> ["<kernel>=<bytes>" ...]``
 (``... --mfma <stats_dir> <pmc_dir> <rows>`` instead summarises the indicator
-network kernels' matrix-core use from an ``SQ_INSTS_VALU_MFMA_MOPS_BF16`` run)
+network kernels' matrix-core use from an ``SQ_INSTS_VALU_MFMA_MOPS_BF16`` run;
+``... --busy <sq_dir> <ta_dir>`` the stage kernels' vector-issue
+and texture-address shares from two counter runs, see ``busy_summary``)
 reads the CSV files that ``rocprofv3 --kernel-trace --stats`` and two
 ``rocprofv3 --pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE`` runs of ``bench.py``
 wrote, and prints (or writes) a short text summary:
@@ -163,7 +165,63 @@ def mfma_summary(stats_dir, pmc_dir, rows):
     return lines
 
 
+# per-SIMD issue cost of one wave64 instruction on a 16-lane SIMD, in cycles
+VALU_ISSUE_CYCLES = 4
+N_XCC = 8
+N_SIMD = 1024  # 256 CUs x 4 SIMDs
+
+
+def dispatch_us(pmc_dir, counter, kernel_regex):
+    """Durations (us) of the matching full-size dispatches of a counter run,
+    from their start and end timestamps (ns)."""
+    rows = _csv(pmc_dir, "*counter_collection.csv")
+    rx = re.compile(kernel_regex)
+    sel = [(int(r["Grid_Size"]), (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3) for r in rows
+           if r["Counter_Name"] == counter and rx.search(r["Kernel_Name"])]
+    if not sel:
+        return []
+    g = max(x[0] for x in sel)
+    return [us for gg, us in sel if gg == g]
+
+
+def busy_summary(sq_dir, ta_dir):
+    """Where the stage kernels spend their cycles, from two counter runs
+    (one dispatch at a time, so the network does not share the chip):
+    SQ_INSTS_VALU / SQ_INSTS_VALU_TRANS_F32 / SQ_WAVES with GRBM_GUI_ACTIVE,
+    and TA_BUSY_avr / TA_ADDR_STALLED_BY_TC_CYCLES_sum with GRBM_GUI_ACTIVE.
+    Per kernel (median over its full-size dispatches): the dispatch's
+    duration and GPU cycles (GRBM_GUI_ACTIVE summed over the 8 XCDs, so / 8),
+    VALU and transcendental instructions per wave, the VALU issue share
+    (instructions x 4 cycles over the SIMDs' cycles: a lower bound on the
+    vector units' busy time, since transcendentals take longer), and the
+    texture-address unit's busy share (TA_BUSY_avr over the cycles)."""
+    lines = [f"{'kernel':22s} {'us':>8s} {'GPU cycles':>11s} {'MHz':>6s} {'VALU/wave':>10s} {'trans/wave':>10s}"
+             f" {'VALU issue':>10s} {'TA busy':>8s} {'TA addr stalled by TC':>22s}"]
+    for short, rx in STAGE_KERNELS:
+        gui = counter_values(sq_dir, "GRBM_GUI_ACTIVE", rx, largest_grid=True)
+        if not gui:
+            continue
+        us = statistics.median(dispatch_us(sq_dir, "GRBM_GUI_ACTIVE", rx))
+        cyc = statistics.median(gui) / N_XCC
+        valu = statistics.median(counter_values(sq_dir, "SQ_INSTS_VALU", rx, largest_grid=True))
+        trans = statistics.median(counter_values(sq_dir, "SQ_INSTS_VALU_TRANS_F32", rx, largest_grid=True))
+        waves = statistics.median(counter_values(sq_dir, "SQ_WAVES", rx, largest_grid=True))
+        gui_ta = statistics.median(counter_values(ta_dir, "GRBM_GUI_ACTIVE", rx, largest_grid=True)) / N_XCC
+        ta = statistics.median(counter_values(ta_dir, "TA_BUSY_avr", rx, largest_grid=True))
+        stall = statistics.median(counter_values(ta_dir, "TA_ADDR_STALLED_BY_TC_CYCLES_sum", rx, largest_grid=True))
+        issue = valu * VALU_ISSUE_CYCLES / (N_SIMD * cyc)
+        lines.append(f"{short:22s} {us:8.1f} {cyc:11.4e} {cyc / us:6.0f} {valu / waves:10.1f} {trans / waves:10.1f}"
+                     f" {issue:10.3f} {ta / gui_ta:8.3f} {stall:22.4e}")
+    return lines
+
+
 def main(argv):
+    if len(argv) >= 2 and argv[1] == "--busy":
+        if len(argv) < 4:
+            print("usage: python -m paper_2404_08952_amd.profiling --busy <sq_pmc_dir> <ta_pmc_dir>")
+            return 2
+        print("\n".join(busy_summary(argv[2], argv[3])))
+        return 0
     if len(argv) >= 2 and argv[1] == "--mfma":
         if len(argv) < 5:
             print(__doc__)
