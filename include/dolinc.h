@@ -88,9 +88,8 @@ typedef enum { DOLINC_FLUX_UPWIND = 0, DOLINC_FLUX_RUSANOV = 1, DOLINC_FLUX_HLLC
 
 /* FP64: all arithmetic in double.  FP32_MIXED: geometry computed in double
  * and stored rounded to float; the inversion / reconstruction coefficients
- * evaluated from each face's stored weight omega in the flux kernel, in
- * float where omega lies in [0.15, 0.85] (relative error below 1e-6), in
- * double on more strongly graded faces; gradient, reconstruction, flux and
+ * evaluated in double from each face's stored weight omega in the flux
+ * kernel and rounded once to float; gradient, reconstruction, flux and
  * update in float with compensated (Neumaier) face-to-cell sums.  ENO3 /
  * WENO5 form their growth rates from omega in double. */
 typedef enum { DOLINC_FP64 = 0, DOLINC_FP32_MIXED = 1 } dolinc_precision;
@@ -225,8 +224,7 @@ dolinc_status dolinc_set_boundary(dolinc_ctx ctx, int32_t patch, int32_t type, c
 /* FP64 precompute on the device (Sec. 2.2 growth rate g and weight omega,
  * centre distance d, face area vectors, volumes; the flux kernel evaluates
  * the Sec. 2.3-2.4 inversion and reconstruction coefficients, folded into
- * the DOLINC representation eq:USR3 / eq:CSR4, from omega in the working
- * precision), then
+ * the DOLINC representation eq:USR3 / eq:CSR4, from omega in double), then
  * allocates the gradient and Runge-Kutta workspaces.  Synchronises before
  * returning.  May be called again to change params (re-allocates as
  * needed). */

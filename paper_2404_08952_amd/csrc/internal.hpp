@@ -14,11 +14,10 @@ namespace dolinc {
 // Per-face record layout (one record per partition entry).
 //   sw[e][4]  : S_x, S_y, S_z (0 in 2-D), omega (owner weight)
 //   dc[e][3]  : d_x, d_y, d_z.  The flux kernel evaluates the coefficients
-//               of the DOLINC representation in the working precision from
-//               the growth rate g = omega / (1 - omega) of the entry's omega
-//               (face_coefficients_r, coefficients.hpp): arithmetic is
-//               cheaper than 8 more values per entry in a memory-bound
-//               kernel.
+//               of the DOLINC representation in FP64 from the growth rate
+//               g = omega / (1 - omega) of the entry's omega
+//               (face_coefficients, coefficients.hpp): arithmetic is cheaper
+//               than 8 more values per entry in a memory-bound kernel.
 // Per-cell face records in sliced ELL order: cells are taken in blocks of
 // ELL_BLOCK; block b holds m_b = (max faces of a cell in b) records per
 // cell, record j of cell lane l at ell_ptr[b] + j * ELL_BLOCK + l, so that

@@ -639,24 +639,13 @@ __device__ __forceinline__ void eval_face(const KArgs<T>& a, int64_t e, T* UL, T
       UR[v] = nonlin_side<T, SCH>(cf, uN[v], uP[v], T(-2) * gN[v], T(-2) * gP[v], T(4) * hN[v]);
   } else {
     // coefficients of both sides from the growth rate g = omega / (1 - omega)
-    // of the P -> N frame (one reciprocal per side), in the working
-    // precision; in FP32 only where omega lies in [0.15, 0.85] (relative error
-    // below 1e-6), in FP64 on more strongly graded faces, where the FP32
-    // closed forms lose digits (USR5: 1e-5 at omega = 0.01) and overflow
-    // (g^10 beyond the FP32 range below omega ~ 1e-4)
-    T c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if constexpr (sizeof(T) == 4) {
-      if (om >= T(0.15) && om <= T(0.85)) {
-        face_coefficients_r<float>(SCH, om, c);
-      } else {
-        double cd[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        face_coefficients_r<double>(SCH, (double)om, cd);
+    // of the P -> N frame, in FP64 (one reciprocal per side), rounded once
+    // to the working type
+    double cd[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    face_coefficients(SCH, (double)om, cd);
+    T c[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) c[k] = (T)cd[k];
-      }
-    } else {
-      face_coefficients_r<T>(SCH, om, c);
-    }
+    for (int k = 0; k < 8; ++k) c[k] = (T)cd[k];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       if constexpr (SCH <= 2) {

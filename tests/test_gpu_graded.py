@@ -62,11 +62,11 @@ def test_gpu_error_trends_and_fp32(cases):
 @pytest.mark.parametrize("scheme", ["USR3", "CSR4", "USR5", "CSR6"])
 def test_fp32_coefficients_on_extreme_grading(scheme):
     """Faces between cells 2e4 times apart in width (omega ~ 5e-5 and
-    1 - 5e-5): the FP32 path evaluates the closed forms of these faces in
-    FP64, because in FP32 the degree-10 terms of USR5 and CSR6 (g^10 with
-    g = 2e4) overflow.  A constant field has zero differentials, so every
-    face state must be the constant itself (an infinite coefficient would
-    give 0 x inf = NaN), in both precisions."""
+    1 - 5e-5): both precisions evaluate the closed forms in FP64, where the
+    degree-10 terms of USR5 and CSR6 (g^10 with g = 2e4) stay finite (in
+    FP32 they would overflow).  A constant field has zero differentials, so
+    every face state must be the constant itself (an infinite coefficient
+    would give 0 x inf = NaN)."""
     from synth import configs
     m = configs.line_1d(16, widths=[1.0, 2.0e4] * 8)
     U = np.full(m.n_cells, 0.75)
