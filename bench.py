@@ -928,7 +928,7 @@ def main():
         "config": {"workload": desc, "cells": nc, "faces": nf, "stages_per_step": 3,
                    "precision": ("FP32 bulk, each face side carried about its own cell (flux shares "
                                  "F.S - F(U_c).S); geometry and face weights precomputed in FP64 and stored in FP32, "
-                                 "the DOLINC coefficients evaluated from the weights in FP32 in the flux kernel"),
+                                 "the DOLINC coefficients evaluated from the weights in FP64 in the flux kernel"),
                    "partition_cells": PART_CELLS["fp32"]},
         "roofline": {"bound": "hbm", "achieved": fk["gbps"], "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": fk["gbps"] / HBM_PEAK_GBPS, "traffic": traffic.get("fp32 k_flux"),
