@@ -179,7 +179,7 @@ def test_rk_step_parity(name, kw, geos):
                                      RES_CASES[14]],
                          ids=["adv-USR3", "burgers-USR3", "burgers-CSR4", "euler-CSR4", "euler-USR5", "euler-CSR6"])
 def test_fp32_stage_error(name, kw, form, geos):
-    """FP32 bulk (FP64 geometry, coefficients in FP32): per-variable relative L2 of
+    """FP32 bulk (FP64 geometry and coefficients): per-variable relative L2 of
     R32 against the FP64 oracle on the same FP32-rounded input <= 1e-5, with
     each face side about its own cell (every law) and, for Euler, about a
     constant reference state."""
