@@ -221,6 +221,7 @@ def main(argv):
             print("usage: python -m paper_2404_08952_amd.profiling --busy <sq_pmc_dir> <ta_pmc_dir>")
             return 2
         print("\n".join(busy_summary(argv[2], argv[3])))
+        print(f"kernel_source_sha256 = {source_hash()}")
         return 0
     if len(argv) >= 2 and argv[1] == "--mfma":
         if len(argv) < 5:

@@ -31,3 +31,21 @@ def test_gradient_kernel_bytes_taylor_green_fp32():
     # per cell: G1 60 + 1/V 4 + face count 4; per record: records 28 + d.H.d 20
     assert bench.hface_bytes(nc, nrec, 5, 3, 4) == nc * (60 + 4 + 4) + nrec * (28 + 20)
     assert bench.COMPULSORY_BYTES["fp32"] == 360 and bench.COMPULSORY_BYTES["fp64"] == 504
+
+
+def test_committed_counter_summaries_belong_to_the_current_kernels():
+    """The rocprofv3 summaries under profiles/ that the benchmark and the
+    design notes quote were taken on kernels whose code (comments stripped)
+    hashes to the current sources: the traffic summary (read back into the
+    bench line's roofline) and the vector-issue / address-unit summary."""
+    import os
+    import re
+    from paper_2404_08952_amd import profiling
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    cur = profiling.source_hash()
+    got = profiling.read_summary(os.path.join(root, "profiles", "stage_kernels_tgv288_usr5_hllc_learned.txt"))
+    assert got is not None and got[1] == cur
+    assert len(bench.measured_traffic("tgv3d")) == 7
+    with open(os.path.join(root, "profiles", "stage_kernels_tgv288_busy.txt")) as fh:
+        m = re.search(r"kernel_source_sha256\s*=\s*(\S+)", fh.read())
+    assert m is not None and m.group(1) == cur
