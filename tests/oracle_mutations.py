@@ -17,7 +17,7 @@ import tempfile
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 # what the CPU suite needs
-COPY = ["oracle", "synth", "tests", "paper_2404_08952_amd", "include", "pytest.ini", "bench.py",
+COPY = ["oracle", "synth", "tests", "paper_2404_08952_amd", "include", "profiles", "pytest.ini", "bench.py",
         "__graft_entry__.py"]
 
 MUTATIONS = [
