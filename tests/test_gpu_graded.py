@@ -79,3 +79,18 @@ def test_fp32_coefficients_on_extreme_grading(scheme):
         assert np.isfinite(F).all(), (prec, scheme)
         np.testing.assert_array_equal(UL[:, 0], 0.75)
         np.testing.assert_array_equal(UR[:, 0], 0.75)
+
+
+@pytest.mark.parametrize("scheme", ["USR3", "CSR4", "USR5", "CSR6"])
+@pytest.mark.parametrize("growth", [2.5, 4.0])
+def test_face_states_equal_oracle_strong_growth(growth, scheme):
+    """Rows growing 2.5x and 4x (omega from 0.29 and 0.2 to 0.71 and 0.8):
+    the GPU's FP64 face states still equal the oracle's, which evaluates
+    eq:coeff numerically.  The coefficients grow like g^5 here, so the
+    rounding of both sides is amplified; the bound scales with them."""
+    m, X, U, _ex = GS.case(growth)
+    for comp in (0, 1):
+        gL, gR = _gpu_faces(m, U[:, comp], scheme)
+        oL, oR = GS.oracle_face_states(X, U[:, comp], scheme)
+        _close(gL, oL, rtol=1e-9, afloor=1e-12)
+        _close(gR, oR, rtol=1e-9, afloor=1e-12)
